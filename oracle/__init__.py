@@ -1,0 +1,31 @@
+"""CPU FP64 oracle for the fermion determinant -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously-correct numpy/scipy implementations of what the GPU
+path computes.  Only the tests, the smoke check and the benchmark's CPU
+baseline may import this package; the library never does.  It shares no code
+with the HIP path.
+"""
+from .fdet_oracle import (  # noqa: F401
+    slice_exponential,
+    slice_matrices,
+    block_fermion_matrix,
+    bruteforce_logdet_greens,
+    bruteforce_force,
+    dense_logdet_greens,
+    stabilised_logdet_greens,
+    sporadic_logdet_greens,
+    dsplit_logdet_greens,
+    stabilised_force,
+    stabilised_force_rows,
+    udv_identity,
+    udv_product,
+    udv_close,
+    wrap_phase,
+    logdet_close,
+)
+from .closed_form import (  # noqa: F401
+    honeycomb_dispersion,
+    uniform_field_logdet,
+    uniform_field_greens,
+    uniform_field_force,
+)

@@ -1,0 +1,105 @@
+"""Closed forms for the honeycomb lattice with space-uniform fields.
+
+TEST INFRASTRUCTURE ONLY.
+
+If phi_{t,x} = c_t for every site, diag(exp(i phi_t)) = exp(i c_t) commutes
+with everything and the product of Sec. 2 collapses to
+    B_{N_t} ... B_1 = exp(i theta) exp(beta kappa K),   theta = sum_t c_t,
+since N_t * delta = beta.  The honeycomb hopping matrix is diagonal in
+momentum space: with unit cells (i, j), k = 2 pi (n1, n2) / L and
+f(k) = 1 + exp(-i k1) + exp(-i k2), the 2 x 2 Bloch matrix is
+h(k) = [[0, f], [f*, 0]] with eigenvalues +-|f(k)|.  Everything below is
+written from these facts with no dense linear algebra:
+
+  log det M = sum_k [ i theta + log(2 cos theta + 2 cosh(beta kappa |f|)) ],
+  G(k)      = sum_+- Pi_+-(k) / (1 + exp(i theta) exp(+-beta kappa |f|)),
+              Pi_+- = (1 +- h/|f|) / 2  (G(k) = 1/(1+exp(i theta)) if f = 0),
+  F_{t,x}   = i/2 - (1/N) sum_k sin theta / (cos theta + cosh(beta kappa |f|)).
+"""
+from __future__ import annotations
+
+import cmath
+import math
+
+import numpy as np
+
+
+def _momenta(L):
+    for n1 in range(L):
+        for n2 in range(L):
+            yield 2.0 * math.pi * n1 / L, 2.0 * math.pi * n2 / L
+
+
+def honeycomb_dispersion(L: int) -> np.ndarray:
+    """f(k) for every momentum k (complex, L*L values, n1-major)."""
+    return np.array([1.0 + cmath.exp(-1j * k1) + cmath.exp(-1j * k2)
+                     for k1, k2 in _momenta(L)])
+
+
+def _wrap(z: complex) -> complex:
+    im = math.remainder(z.imag, 2.0 * math.pi)
+    if im <= -math.pi:
+        im += 2.0 * math.pi
+    return complex(z.real, im)
+
+
+def uniform_field_logdet(L: int, bk: float, theta: float) -> complex:
+    """log det M for phi_{t,x} = c_t, theta = sum_t c_t, bk = beta * kappa.
+
+    Each +-|f| pair contributes (1 + e^{i th} e^{a})(1 + e^{i th} e^{-a})
+    = e^{i th} (2 cos th + 2 cosh a), a = bk |f|.  For large a the log is
+    evaluated as a + log(1 + 2 cos th e^{-a} + e^{-2a}) to avoid overflow.
+    """
+    total = 0.0 + 0.0j
+    for f in honeycomb_dispersion(L):
+        a = bk * abs(f)
+        inner = 2.0 * math.cos(theta) * math.exp(-a) + math.exp(-2.0 * a)
+        total += 1j * theta + a + math.log1p(inner)
+    return _wrap(total)
+
+
+def uniform_field_greens(L: int, bk: float, theta: float) -> np.ndarray:
+    """Real-space G for a uniform field, by Fourier synthesis of G(k).
+
+    Site index 2 (i L + j) + sigma; G_{(r,s),(r',s')} =
+    (1/L^2) sum_k exp(i k.(r - r')) G(k)_{s s'}.
+    """
+    N = 2 * L * L
+    G = np.zeros((N, N), dtype=np.complex128)
+    eith = cmath.exp(1j * theta)
+    idx = np.arange(L)
+    for (k1, k2), f in zip(_momenta(L), honeycomb_dispersion(L)):
+        af = abs(f)
+        if af < 1e-14:
+            Gk = np.eye(2, dtype=np.complex128) / (1.0 + eith)
+        else:
+            h = np.array([[0.0, f], [np.conj(f), 0.0]], dtype=np.complex128)
+            Gk = np.zeros((2, 2), dtype=np.complex128)
+            for sgn in (1.0, -1.0):
+                proj = 0.5 * (np.eye(2) + sgn * h / af)
+                x = sgn * bk * af
+                # 1 / (1 + e^{i th} e^{x}), written to avoid overflow for x >> 0
+                if x > 0:
+                    w = cmath.exp(-x) / (cmath.exp(-x) + eith)
+                else:
+                    w = 1.0 / (1.0 + eith * cmath.exp(x))
+                Gk += w * proj
+        # phase e^{i k.(r - r')} over unit cells
+        ph_i = np.exp(1j * k1 * idx)
+        ph_j = np.exp(1j * k2 * idx)
+        cell = np.outer(ph_i, ph_j).reshape(-1)          # e^{i k.r}, r = i*L + j
+        phase = np.outer(cell, np.conj(cell)) / (L * L)  # (r, r')
+        for s in range(2):
+            for sp in range(2):
+                G[s::2, sp::2] += Gk[s, sp] * phase
+    return G
+
+
+def uniform_field_force(L: int, bk: float, theta: float) -> complex:
+    """F_{t,x} for a uniform field (the same for every t and x)."""
+    N = 2 * L * L
+    acc = 0.0
+    for f in honeycomb_dispersion(L):
+        a = bk * abs(f)
+        acc += math.sin(theta) / (math.cos(theta) + math.cosh(a))
+    return complex(-acc / N, 0.5)

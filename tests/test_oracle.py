@@ -1,0 +1,286 @@
+"""Pins for the CPU oracle: brute force, closed forms, N_t = 1, invariants.
+
+Each test checks the oracle against something other than itself: the block
+fermion matrix (paper Sec. 2), the momentum-space closed form of the uniform
+field, the textbook single-slice determinant, finite differences, and exact
+symmetries of the honeycomb model.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workload import honeycomb_hopping, sample_phi, uniform_phi
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def wrapped_diff(a, b):
+    d = complex(a) - complex(b)
+    return complex(d.real, math.remainder(d.imag, 2 * math.pi))
+
+
+def rel_err(a, b):
+    return abs(wrapped_diff(a, b)) / max(abs(b), 1e-300)
+
+
+def case(L, Nt, beta, U=3.0, seed=11):
+    K = honeycomb_hopping(L)
+    N = K.shape[0]
+    dk = beta / Nt
+    return K, dk, sample_phi(seed, Nt, N, dk, U)
+
+
+# --- inputs -----------------------------------------------------------------
+
+def test_honeycomb_spectrum_is_plus_minus_abs_f():
+    for L in (2, 3, 4, 6):
+        lam = np.sort(np.linalg.eigvalsh(honeycomb_hopping(L)))
+        f = np.abs(O.honeycomb_dispersion(L))
+        ref = np.sort(np.concatenate([f, -f]))
+        assert np.abs(lam - ref).max() < 1e-13
+
+
+def test_honeycomb_structure():
+    K = honeycomb_hopping(3)
+    assert np.array_equal(K, K.T)
+    assert np.all(K.sum(0) == 3)          # coordination number 3
+    assert np.trace(K) == 0
+    S = np.diag([(-1.0) ** a for a in range(K.shape[0])])
+    assert np.array_equal(S @ K @ S, -K)  # bipartite
+
+
+def test_phi_sampler_variance():
+    phi = sample_phi(5, 256, 128, 0.125, 3.0)
+    assert phi.shape == (256, 128)
+    assert abs(phi.var() - 0.375) < 0.01
+    assert np.array_equal(phi, sample_phi(5, 256, 128, 0.125, 3.0))
+
+
+# --- the single slice -----------------------------------------------------
+
+def test_slice_exponential_inverse_and_series():
+    K = honeycomb_hopping(3)
+    dk = 0.125
+    E = O.slice_exponential(K, dk)
+    Ei = O.slice_exponential(K, -dk)
+    assert np.abs(E @ Ei - np.eye(18)).max() < 1e-14
+    # power series written out (|dk K| <= 0.375)
+    A = dk * K
+    S = np.eye(18)
+    term = np.eye(18)
+    for k in range(1, 30):
+        term = term @ A / k
+        S = S + term
+    assert np.abs(E - S).max() < 1e-14
+
+
+# --- brute force block matrix vs dense definition ----------------------------
+
+@pytest.mark.parametrize("L,Nt,beta", [(2, 1, 0.5), (2, 4, 1.0), (3, 8, 1.0)])
+def test_block_matrix_equals_dense_definition(L, Nt, beta):
+    K, dk, phi = case(L, Nt, beta)
+    l1, G1 = O.bruteforce_logdet_greens(K, dk, phi)
+    l0, G0 = O.dense_logdet_greens(K, dk, phi)
+    assert rel_err(l1, l0) < 1e-13
+    assert np.abs(G1 - G0).max() < 1e-13
+
+
+def test_single_slice_textbook():
+    """N_t = 1: M = 1 + E diag(e^{i phi}) is one dense matrix."""
+    for L in (2, 3, 5):
+        K, dk, phi = case(L, 1, 0.4, seed=3)
+        N = K.shape[0]
+        w, V = np.linalg.eigh(K)
+        E = (V * np.exp(dk * w)) @ V.T
+        A = np.eye(N) + E * np.exp(1j * phi[0])[None, :]
+        sign, la = np.linalg.slogdet(A)
+        ref = complex(la, np.angle(sign))
+        l2, G2 = O.stabilised_logdet_greens(K, dk, phi)
+        assert rel_err(l2, ref) < 1e-13
+        # rounding bound of an inverse: a few eps * cond(A) * |A^-1|
+        Ainv = np.linalg.inv(A)
+        tol = 50 * np.finfo(float).eps * np.linalg.cond(A) * np.abs(Ainv).max()
+        assert np.abs(G2 - Ainv).max() < tol
+
+
+# --- stabilised method vs brute force -------------------------------------------
+
+@pytest.mark.parametrize("L,Nt,beta", [(2, 16, 2.0), (2, 64, 16.0), (3, 16, 2.0), (3, 32, 8.0)])
+def test_stabilised_matches_bruteforce(L, Nt, beta):
+    K, dk, phi = case(L, Nt, beta)
+    l1, G1 = O.bruteforce_logdet_greens(K, dk, phi)
+    l2, G2 = O.stabilised_logdet_greens(K, dk, phi)
+    assert rel_err(l2, l1) < 1e-13
+    assert np.abs(G2 - G1).max() < 1e-12
+    for s in (1, 3, 4):
+        l3, G3 = O.sporadic_logdet_greens(K, dk, phi, s)
+        assert rel_err(l3, l1) < 1e-13
+        assert np.abs(G3 - G1).max() < 1e-12
+
+
+@pytest.mark.slow
+def test_stabilised_matches_bruteforce_low_temperature():
+    """beta = 32 on the block matrix, which stays well conditioned."""
+    K, dk, phi = case(2, 256, 32.0)
+    l1, G1 = O.bruteforce_logdet_greens(K, dk, phi)
+    l2, G2 = O.sporadic_logdet_greens(K, dk, phi, 8)
+    assert rel_err(l2, l1) < 1e-13
+    assert np.abs(G2 - G1).max() < 1e-12
+
+
+def test_time_order_is_later_slices_left():
+    """The oracle's G belongs to 1 + B_{N_t}...B_1, not to the reversed order
+    (the two share a determinant but not the inverse)."""
+    K, dk, phi = case(2, 8, 2.0)
+    _, G1 = O.bruteforce_logdet_greens(K, dk, phi)
+    _, Grev = O.bruteforce_logdet_greens(K, dk, phi[::-1].copy())
+    _, G2 = O.stabilised_logdet_greens(K, dk, phi)
+    assert np.abs(G2 - G1).max() < 1e-13
+    assert np.abs(G2 - Grev).max() > 1e-3
+
+
+# --- closed forms ---------------------------------------------------------------
+
+def test_closed_form_matches_dense_at_high_temperature():
+    for L in (2, 3, 4):
+        K = honeycomb_hopping(L)
+        N = K.shape[0]
+        Nt, beta = 8, 1.0
+        c = np.random.default_rng(L).normal(0, 0.4, Nt)
+        phi = uniform_phi(c, N)
+        l0, G0 = O.dense_logdet_greens(K, beta / Nt, phi)
+        lc = O.uniform_field_logdet(L, beta, c.sum())
+        Gc = O.uniform_field_greens(L, beta, c.sum())
+        assert rel_err(lc, l0) < 1e-13
+        assert np.abs(Gc - G0).max() < 1e-13
+
+
+@pytest.mark.parametrize("L,beta,Nt,s", [(3, 32.0, 256, 8), (3, 64.0, 512, 16), (6, 32.0, 256, 8)])
+def test_stabilised_matches_closed_form_low_temperature(L, beta, Nt, s):
+    K = honeycomb_hopping(L)
+    N = K.shape[0]
+    c = np.random.default_rng(2).normal(0, 0.6, Nt)
+    phi = uniform_phi(c, N)
+    th = c.sum()
+    lc = O.uniform_field_logdet(L, beta, th)
+    Gc = O.uniform_field_greens(L, beta, th)
+    l2, G2 = O.sporadic_logdet_greens(K, beta / Nt, phi, s)
+    assert rel_err(l2, lc) < 1e-13
+    assert np.abs(G2 - Gc).max() < 1e-11
+
+
+def test_free_field_phi_zero():
+    """phi = 0: log det = sum_k [a_k + 2 log(1 + e^{-a_k})] on each +-|f| pair."""
+    L, beta, Nt = 3, 32.0, 256
+    K = honeycomb_hopping(L)
+    phi = np.zeros((Nt, K.shape[0]))
+    a = beta * np.abs(O.honeycomb_dispersion(L))
+    ref = float(np.sum(a + 2.0 * np.log1p(np.exp(-a))))
+    l2, G2 = O.sporadic_logdet_greens(K, beta / Nt, phi, 8)
+    assert abs(l2.real - ref) / ref < 1e-13 and abs(l2.imag) < 1e-12
+    assert np.abs(G2 - G2.conj().T).max() < 1e-12       # Hermitian at phi = 0
+
+
+# --- invariants -------------------------------------------------------------------
+
+@pytest.mark.parametrize("L,Nt,beta", [(3, 32, 4.0), (4, 64, 8.0)])
+def test_phase_invariant_and_half_filling(L, Nt, beta):
+    """Bipartite K with tr K = 0: Im log det = sum(phi)/2 (mod pi), Re G_xx = 1/2."""
+    K, dk, phi = case(L, Nt, beta, seed=17)
+    l2, G2 = O.stabilised_logdet_greens(K, dk, phi)
+    d = math.remainder(l2.imag - 0.5 * phi.sum(), math.pi)
+    assert abs(d) < 1e-11
+    assert np.abs(np.diag(G2).real - 0.5).max() < 1e-12 * max(1.0, np.abs(G2).max())
+
+
+def test_cyclic_shift():
+    """Moving B_1 to the far left keeps log det and maps G -> B_1 G B_1^-1."""
+    K, dk, phi = case(3, 16, 4.0)
+    l1, G1 = O.stabilised_logdet_greens(K, dk, phi)
+    l2, G2 = O.stabilised_logdet_greens(K, dk, np.roll(phi, -1, axis=0))
+    B1 = O.slice_matrices(K, dk, phi[:1])[0]
+    assert rel_err(l2, l1) < 1e-13
+    assert np.abs(G2 - B1 @ G1 @ np.linalg.inv(B1)).max() < 1e-12
+
+
+def test_dsplit_cross_check():
+    K, dk, phi = case(4, 128, 16.0)
+    l1, G1 = O.sporadic_logdet_greens(K, dk, phi, 8)
+    l2, G2 = O.dsplit_logdet_greens(K, dk, phi, 8)
+    assert rel_err(l2, l1) < 1e-13
+    assert np.abs(G2 - G1).max() < 1e-12
+
+
+def test_s_independence():
+    K, dk, phi = case(3, 64, 8.0)
+    l1, G1 = O.sporadic_logdet_greens(K, dk, phi, 1)
+    for s in (2, 4, 8, 16):
+        l2, G2 = O.sporadic_logdet_greens(K, dk, phi, s)
+        assert rel_err(l2, l1) < 1e-13
+        assert np.abs(G2 - G1).max() < 1e-12
+
+
+# --- force -----------------------------------------------------------------------
+
+@pytest.mark.parametrize("L,Nt,beta", [(2, 8, 1.0), (2, 32, 8.0), (3, 16, 2.0)])
+def test_force_matches_bruteforce_jacobi(L, Nt, beta):
+    K, dk, phi = case(L, Nt, beta)
+    F1 = O.bruteforce_force(K, dk, phi)
+    F2 = O.stabilised_force(K, dk, phi)
+    assert np.abs(F2 - F1).max() < 1e-12
+    assert np.abs(F2.imag - 0.5).max() < 1e-12
+
+
+def test_force_first_row_is_greens_diagonal():
+    K, dk, phi = case(3, 16, 4.0)
+    _, G = O.stabilised_logdet_greens(K, dk, phi)
+    F = O.stabilised_force_rows(K, dk, phi, [1])
+    assert np.abs(F[0] - 1j * (1.0 - np.diag(G))).max() < 1e-12
+
+
+def test_force_finite_differences():
+    K, dk, phi = case(3, 16, 4.0)
+    F = O.stabilised_force(K, dk, phi)
+    h = 1e-6
+    rng = np.random.default_rng(0)
+    for _ in range(6):
+        t, x = int(rng.integers(16)), int(rng.integers(18))
+        pp = phi.copy(); pp[t, x] += h
+        pm = phi.copy(); pm[t, x] -= h
+        lp = O.stabilised_logdet_greens(K, dk, pp)[0]
+        lm = O.stabilised_logdet_greens(K, dk, pm)[0]
+        fd = wrapped_diff(lp, lm) / (2 * h)
+        assert abs(fd.real - F[t, x].real) < 1e-6
+        assert abs(fd.imag - F[t, x].imag) < 1e-6
+
+
+def test_force_uniform_closed_form():
+    L, beta, Nt = 3, 8.0, 64
+    K = honeycomb_hopping(L)
+    c = np.random.default_rng(4).normal(0, 0.5, Nt)
+    phi = uniform_phi(c, K.shape[0])
+    rows = [1, 17, 64]
+    F = O.stabilised_force_rows(K, beta / Nt, phi, rows)
+    ref = O.uniform_field_force(L, beta, c.sum())
+    assert np.abs(F - ref).max() < 1e-12
+
+
+# --- planted mistakes: each must be caught by a pin above --------------------------
+
+def test_pins_catch_planted_mistakes(monkeypatch):
+    """A sign error in the close and a dropped pivot parity must both fail."""
+    K, dk, phi = case(2, 8, 2.0)
+    l1, G1 = O.bruteforce_logdet_greens(K, dk, phi)
+    import oracle.fdet_oracle as fo
+    monkeypatch.setattr(fo, "_perm_parity", lambda piv: 0)
+    bad = [fo.stabilised_logdet_greens(K, dk, p)[0]
+           for p in (phi, phi + 0.3, phi * 1.7)]
+    good = [O.bruteforce_logdet_greens(K, dk, p)[0] for p in (phi, phi + 0.3, phi * 1.7)]
+    assert any(abs(wrapped_diff(b, g)) > 1.0 for b, g in zip(bad, good))
+    monkeypatch.undo()
+    orig = fo.udv_identity
+    monkeypatch.setattr(fo, "udv_identity", lambda N: (orig(N)[0], -orig(N)[1], orig(N)[2]))
+    l3, G3 = fo.stabilised_logdet_greens(K, dk, phi)
+    assert np.abs(G3 - G1).max() > 1e-3
