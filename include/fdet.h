@@ -1,0 +1,148 @@
+/*
+ * fdet.h -- C ABI of libfdet, a gfx950 (MI355X) implementation of the dense
+ * stabilised fermion determinant.
+ *
+ * Problem (paper Sec. 2, "The sausage"): V = N lattice sites, N_t time
+ * slices, slice matrices B_t = exp(dk K) diag(exp(i phi_t)), t = 1..N_t, and
+ *     M = 1 + B_{N_t} ... B_1          (later slices to the left).
+ * det M equals the determinant of the full (N N_t)^2 block fermion matrix
+ * (Sec. 2), M^{-1} is the equal-time Green's function, and the HMC action
+ * carries -log det M (eq. hamiltonian_alg), so its force is built from
+ * d log det M / d phi_{t,x} (Sec. 3.1, Sec. 4 response formula).
+ *
+ * Method (Sec. 7, with the sporadic stabilisation of Sec. 9): the product is
+ * kept as X D Y^{-1} (eq. def_matrix_as_product), re-decomposed by a pivoted
+ * Householder QR every s slices (eqs. prod_2_mat_stab .. res_2_mat_stab) and
+ * closed by one more QR (Sec. 7 steps 4-6).
+ *
+ * Conventions for every entry point
+ *   - Matrix and field arrays are DEVICE pointers; descriptors and option
+ *     structs are host memory.  Real matrices are N*N doubles; complex
+ *     matrices are N*N interleaved {re, im} doubles; all row-major.
+ *   - phi is N_t*N doubles, row t-1 holding phi_t (B_1, row 0, acts first).
+ *   - logdet is 2 doubles {Re, Im}, Im wrapped into (-pi, pi].
+ *   - The caller owns every buffer, including the workspace, whose size comes
+ *     from fd_workspace_bytes for the same problems, options and `what`.  The
+ *     library never frees caller memory and allocates no device memory in
+ *     these calls.
+ *   - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream).  The return code reports argument and launch errors found
+ *     before or while enqueueing.  Numerical outcomes are written to the
+ *     device `status` word(s) (one int32 per problem): FD_OK,
+ *     FD_WARN_ILLCOND (results returned, M nearly singular),
+ *     FD_ERR_SINGULAR (a pivot of the close was zero or non-finite),
+ *     FD_ERR_NONFINITE (non-finite input or intermediate).
+ *   - Thread-safe; calls on different streams must use different workspaces.
+ */
+#ifndef FDET_H
+#define FDET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FD_MAX_N 512          /* largest supported number of sites            */
+
+/* return and status codes */
+enum {
+  FD_OK = 0,
+  FD_WARN_ILLCOND = 1,
+  FD_ERR_INVALID_ARG = -1,
+  FD_ERR_WORKSPACE = -2,
+  FD_ERR_SINGULAR = -3,
+  FD_ERR_NONFINITE = -4,
+  FD_ERR_HIP = -5,
+  FD_ERR_UNSUPPORTED = -6
+};
+
+/* what a workspace is sized for */
+enum { FD_WHAT_LOGDET = 0, FD_WHAT_GREENS = 1, FD_WHAT_FORCE = 2, FD_WHAT_UDV = 3 };
+
+/* option flags */
+#define FD_REUSE_E 0x1   /* exp(+-dk K) already in this workspace from an earlier
+                            call on the same problems: skip recomputing it     */
+
+typedef struct {
+  int32_t N;            /* sites V, 1 <= N <= FD_MAX_N                        */
+  int32_t Nt;           /* time slices, >= 1                                   */
+  double dk;            /* delta * kappa: the exponent of a slice is dk*K      */
+  const double *K;      /* device, N*N real symmetric hopping matrix           */
+  const double *phi;    /* device, Nt*N auxiliary field                        */
+} fd_problem;
+
+typedef struct {
+  int32_t s;            /* QR every s slices (Sec. 9 sporadic stabilisation);
+                           0 = 8.  Keep s*dk*spectral_radius(K) <= 6.          */
+  int32_t checkpoint;   /* force: UDV checkpoint interval c (0 = 16).  G~ is
+                           carried across c slices, which amplifies rounding
+                           like cond(B)^c: keep c*dk*spectral_radius(K) <= 6. */
+  int32_t segments;     /* det/G: independent time segments per problem that
+                           are combined by stabilised products (0 = auto)      */
+  int32_t flags;        /* FD_REUSE_E                                          */
+} fd_options;
+
+/* Bytes of workspace needed for `nprob` problems and the given entry point
+ * (`what` = FD_WHAT_*).  Returns 0 on invalid arguments (see fd_last_error).
+ * The workspace must be 256-byte aligned.                                    */
+size_t fd_workspace_bytes(const fd_problem *p, int32_t nprob, const fd_options *o,
+                          int32_t what);
+
+/* E = exp(dk K) (Sec. 6 steps 1-2; Sec. 8 notes that a truncated polynomial
+ * serves equally).  E is N*N row-major real; ws as for FD_WHAT_LOGDET.       */
+int fd_slice_exponential(const fd_problem *p, double *E, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* log det M (Sec. 7 steps 1-5).  logdet: device, 2 doubles.                  */
+int fd_logdet(const fd_problem *p, const fd_options *o, double *logdet, void *ws,
+              size_t ws_bytes, int32_t *status, void *stream);
+
+/* log det M and G = M^{-1} (Sec. 7 steps 1-6).  logdet may be NULL.
+ * G: device, N*N complex (interleaved), row-major.                           */
+int fd_greens(const fd_problem *p, const fd_options *o, double *logdet, double *G,
+              void *ws, size_t ws_bytes, int32_t *status, void *stream);
+
+/* Force F_{t,x} = d log det M / d phi_{t,x} = i (1 - G~_t)_{xx} with
+ * G~_t = (1 + B_{t-1}...B_1 B_{N_t}...B_t)^{-1} (Sec. 4 response formula;
+ * phi_{t,x} enters only the right-most factor of B_t, so the derivative is
+ * exact).  The G~_t come from UDV checkpoints every c slices of the prefix and
+ * suffix products (Sec. 5, stabilised dense pre- and suffix) and are carried
+ * between checkpoints by G~_{t+1} = B_t G~_t B_t^{-1}.
+ * force: device, Nt*N doubles, Re F (row t-1 = slice t).
+ * force_im: NULL or Nt*N doubles, Im F.  logdet: NULL or 2 doubles.          */
+int fd_force(const fd_problem *p, const fd_options *o, double *logdet, double *force,
+             double *force_im, void *ws, size_t ws_bytes, int32_t *status, void *stream);
+
+/* The stabilised factorisation B_{N_t}...B_1 = X diag(D) T (eq.
+ * def_matrix_as_product with T = Y^{-1}): X unitary, D >= 0 sorted by the
+ * pivoting, |det T| = 1.  X, T: N*N complex row-major; D: N doubles.         */
+int fd_udv(const fd_problem *p, const fd_options *o, double *X, double *D, double *T,
+           void *ws, size_t ws_bytes, int32_t *status, void *stream);
+
+/* Batched forms: `p` is a host array of nprob descriptors (sizes may differ).
+ * logdet: 2*nprob doubles.  G: one device buffer, problem i at offset
+ * 2*sum_{j<i} N_j^2 doubles.  force / force_im: problem i at offset
+ * sum_{j<i} Nt_j*N_j doubles.  status: nprob int32.  All problems run in the
+ * same kernel launches.                                                      */
+int fd_logdet_batched(const fd_problem *p, int32_t nprob, const fd_options *o,
+                      double *logdet, void *ws, size_t ws_bytes, int32_t *status,
+                      void *stream);
+int fd_greens_batched(const fd_problem *p, int32_t nprob, const fd_options *o,
+                      double *logdet, double *G, void *ws, size_t ws_bytes,
+                      int32_t *status, void *stream);
+int fd_force_batched(const fd_problem *p, int32_t nprob, const fd_options *o,
+                     double *logdet, double *force, double *force_im, void *ws,
+                     size_t ws_bytes, int32_t *status, void *stream);
+
+/* Text for a return/status code; the last error message of this thread.      */
+const char *fd_strerror(int code);
+const char *fd_last_error(void);
+/* Library version string.                                                    */
+const char *fd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDET_H */

@@ -1,0 +1,332 @@
+"""Python binding of libfdet: the stabilised fermion determinant on gfx950.
+
+Argument marshalling only.  Every step of the computation runs in the HIP
+kernels of libfdet.so; PyTorch supplies device memory and the stream.  There
+is no CPU fallback: without the built library or a GPU the calls raise.
+
+    import paper_2604_02130_amd as fd
+    ld, G = fd.greens(K, phi, dk, s=8)        # K, phi: float64 CUDA tensors
+    F = fd.force(K, phi, dk, s=8, checkpoint=16).real
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdet.so")
+
+FD_OK = 0
+FD_WARN_ILLCOND = 1
+FD_ERR_INVALID_ARG = -1
+FD_ERR_WORKSPACE = -2
+FD_ERR_SINGULAR = -3
+FD_ERR_NONFINITE = -4
+FD_ERR_HIP = -5
+FD_ERR_UNSUPPORTED = -6
+
+FD_WHAT_LOGDET, FD_WHAT_GREENS, FD_WHAT_FORCE, FD_WHAT_UDV = 0, 1, 2, 3
+FD_REUSE_E = 0x1
+MAX_N = 512
+
+# exported names (each declared in include/fdet.h)
+SYMBOLS = (
+    "fd_workspace_bytes", "fd_slice_exponential", "fd_logdet", "fd_greens", "fd_force",
+    "fd_udv", "fd_logdet_batched", "fd_greens_batched", "fd_force_batched",
+    "fd_strerror", "fd_last_error", "fd_version",
+)
+
+
+class FdProblem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("Nt", ctypes.c_int32), ("dk", ctypes.c_double),
+                ("K", ctypes.c_void_p), ("phi", ctypes.c_void_p)]
+
+
+class FdOptions(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int32), ("checkpoint", ctypes.c_int32),
+                ("segments", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class FdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libfdet error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libfdet.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FdError(FD_ERR_UNSUPPORTED,
+                      f"{path} is not built; run `python -m paper_2604_02130_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER(FdProblem)
+    O = ctypes.POINTER(FdOptions)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    lib.fd_workspace_bytes.argtypes = [P, i32, O, i32]
+    lib.fd_workspace_bytes.restype = sz
+    lib.fd_slice_exponential.argtypes = [P, vp, vp, sz, vp]
+    lib.fd_logdet.argtypes = [P, O, vp, vp, sz, vp, vp]
+    lib.fd_greens.argtypes = [P, O, vp, vp, vp, sz, vp, vp]
+    lib.fd_force.argtypes = [P, O, vp, vp, vp, vp, sz, vp, vp]
+    lib.fd_udv.argtypes = [P, O, vp, vp, vp, vp, sz, vp, vp]
+    lib.fd_logdet_batched.argtypes = [P, i32, O, vp, vp, sz, vp, vp]
+    lib.fd_greens_batched.argtypes = [P, i32, O, vp, vp, vp, sz, vp, vp]
+    lib.fd_force_batched.argtypes = [P, i32, O, vp, vp, vp, vp, sz, vp, vp]
+    for name in ("fd_slice_exponential", "fd_logdet", "fd_greens", "fd_force", "fd_udv",
+                 "fd_logdet_batched", "fd_greens_batched", "fd_force_batched"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib.fd_strerror.argtypes = [ctypes.c_int]
+    lib.fd_strerror.restype = ctypes.c_char_p
+    lib.fd_last_error.argtypes = []
+    lib.fd_last_error.restype = ctypes.c_char_p
+    lib.fd_version.argtypes = []
+    lib.fd_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def version() -> str:
+    return load_library().fd_version().decode()
+
+
+def strerror(code: int) -> str:
+    return load_library().fd_strerror(int(code)).decode()
+
+
+def _check(rc: int):
+    if rc != FD_OK:
+        lib = load_library()
+        raise FdError(rc, f"{lib.fd_strerror(rc).decode()}: {lib.fd_last_error().decode()}")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise FdError(FD_ERR_UNSUPPORTED, "libfdet needs a ROCm GPU; none is visible")
+    return torch
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else 0
+
+
+def _prob(K, phi, dk) -> FdProblem:
+    torch = _torch()
+    for name, t in (("K", K), ("phi", phi)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise FdError(FD_ERR_INVALID_ARG, f"{name} must be a CUDA tensor")
+        if t.dtype != torch.float64 or not t.is_contiguous():
+            raise FdError(FD_ERR_INVALID_ARG, f"{name} must be contiguous float64")
+    if K.dim() != 2 or K.shape[0] != K.shape[1]:
+        raise FdError(FD_ERR_INVALID_ARG, "K must be square")
+    if phi.dim() != 2 or phi.shape[1] != K.shape[0]:
+        raise FdError(FD_ERR_INVALID_ARG, "phi must have shape (Nt, N)")
+    return FdProblem(int(K.shape[0]), int(phi.shape[0]), float(dk), K.data_ptr(), phi.data_ptr())
+
+
+def _opts(s=0, checkpoint=0, segments=0, flags=0) -> FdOptions:
+    return FdOptions(int(s), int(checkpoint), int(segments), int(flags))
+
+
+class Workspace:
+    """A growable device byte buffer reused across calls on one device."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device):
+        torch = _torch()
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        off = (-base) % 256
+        return base + off, self.buf.numel() - off
+
+
+_default_ws = Workspace()
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _status_check(status, check: bool):
+    if not check:
+        return
+    vals = status.cpu().tolist()
+    for i, v in enumerate(vals):
+        if v < 0:
+            raise FdError(v, f"problem {i}: {strerror(v)}")
+
+
+def workspace_bytes(probs: Sequence[FdProblem], what: int, **opts) -> int:
+    lib = load_library()
+    arr = (FdProblem * len(probs))(*probs)
+    o = _opts(**opts)
+    n = lib.fd_workspace_bytes(arr, len(probs), ctypes.byref(o), what)
+    if n == 0:
+        raise FdError(FD_ERR_INVALID_ARG, lib.fd_last_error().decode())
+    return int(n)
+
+
+def slice_exponential(K, dk, ws: Workspace | None = None):
+    """E = exp(dk K) computed on the GPU (N x N float64)."""
+    torch = _torch()
+    lib = load_library()
+    phi = torch.zeros((1, K.shape[0]), dtype=torch.float64, device=K.device)
+    p = _prob(K, phi, dk)
+    E = torch.empty_like(K)
+    need = workspace_bytes([p], FD_WHAT_LOGDET)
+    wsp, wsn = (ws or _default_ws).get(need, K.device)
+    _check(lib.fd_slice_exponential(ctypes.byref(p), E.data_ptr(), wsp, wsn, _stream()))
+    return E
+
+
+def logdet(K, phi, dk, s=0, segments=0, flags=0, check=True, ws: Workspace | None = None):
+    """log det(1 + B_{N_t}...B_1) as a complex128 scalar tensor on the device."""
+    torch = _torch()
+    lib = load_library()
+    p = _prob(K, phi, dk)
+    o = _opts(s=s, segments=segments, flags=flags)
+    out = torch.empty(2, dtype=torch.float64, device=K.device)
+    status = torch.empty(1, dtype=torch.int32, device=K.device)
+    need = workspace_bytes([p], FD_WHAT_LOGDET, s=s, segments=segments)
+    wsp, wsn = (ws or _default_ws).get(need, K.device)
+    _check(lib.fd_logdet(ctypes.byref(p), ctypes.byref(o), out.data_ptr(), wsp, wsn,
+                         status.data_ptr(), _stream()))
+    _status_check(status, check)
+    return torch.view_as_complex(out)
+
+
+def greens(K, phi, dk, s=0, segments=0, flags=0, check=True, ws: Workspace | None = None,
+           out=None, status=None):
+    """(log det M, G = M^{-1}); G is an N x N complex128 tensor."""
+    torch = _torch()
+    lib = load_library()
+    p = _prob(K, phi, dk)
+    N = p.N
+    o = _opts(s=s, segments=segments, flags=flags)
+    ld = torch.empty(2, dtype=torch.float64, device=K.device) if out is None else out[0]
+    G = torch.empty((N, N, 2), dtype=torch.float64, device=K.device) if out is None else out[1]
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=K.device)
+    need = workspace_bytes([p], FD_WHAT_GREENS, s=s, segments=segments)
+    wsp, wsn = (ws or _default_ws).get(need, K.device)
+    _check(lib.fd_greens(ctypes.byref(p), ctypes.byref(o), ld.data_ptr(), G.data_ptr(), wsp, wsn,
+                         status.data_ptr(), _stream()))
+    _status_check(status, check)
+    return torch.view_as_complex(ld), torch.view_as_complex(G)
+
+
+def force(K, phi, dk, s=0, checkpoint=0, flags=0, check=True, ws: Workspace | None = None,
+          with_logdet=False):
+    """Complex force F[t-1, x] = d log det M / d phi_{t,x} as an (N_t, N) tensor."""
+    torch = _torch()
+    lib = load_library()
+    p = _prob(K, phi, dk)
+    o = _opts(s=s, checkpoint=checkpoint, flags=flags)
+    Fr = torch.empty((p.Nt, p.N), dtype=torch.float64, device=K.device)
+    Fi = torch.empty((p.Nt, p.N), dtype=torch.float64, device=K.device)
+    ld = torch.empty(2, dtype=torch.float64, device=K.device)
+    status = torch.empty(1, dtype=torch.int32, device=K.device)
+    need = workspace_bytes([p], FD_WHAT_FORCE, s=s, checkpoint=checkpoint)
+    wsp, wsn = (ws or _default_ws).get(need, K.device)
+    _check(lib.fd_force(ctypes.byref(p), ctypes.byref(o), ld.data_ptr(), Fr.data_ptr(),
+                        Fi.data_ptr(), wsp, wsn, status.data_ptr(), _stream()))
+    _status_check(status, check)
+    F = torch.complex(Fr, Fi)
+    return (F, torch.view_as_complex(ld)) if with_logdet else F
+
+
+def udv(K, phi, dk, s=0, segments=0, check=True, ws: Workspace | None = None):
+    """(X, D, T) with B_{N_t}...B_1 = X diag(D) T."""
+    torch = _torch()
+    lib = load_library()
+    p = _prob(K, phi, dk)
+    N = p.N
+    o = _opts(s=s, segments=segments)
+    X = torch.empty((N, N, 2), dtype=torch.float64, device=K.device)
+    T = torch.empty((N, N, 2), dtype=torch.float64, device=K.device)
+    D = torch.empty(N, dtype=torch.float64, device=K.device)
+    status = torch.empty(1, dtype=torch.int32, device=K.device)
+    need = workspace_bytes([p], FD_WHAT_UDV, s=s, segments=segments)
+    wsp, wsn = (ws or _default_ws).get(need, K.device)
+    _check(lib.fd_udv(ctypes.byref(p), ctypes.byref(o), X.data_ptr(), D.data_ptr(), T.data_ptr(),
+                      wsp, wsn, status.data_ptr(), _stream()))
+    _status_check(status, check)
+    return torch.view_as_complex(X), D, torch.view_as_complex(T)
+
+
+def _batch(problems):
+    return [_prob(K, phi, dk) for (K, phi, dk) in problems]
+
+
+def greens_batched(problems, s=0, segments=0, flags=0, check=True, ws: Workspace | None = None,
+                   want_g=True):
+    """Batched log det (and G) of a list of (K, phi, dk); all problems share the
+    kernel launches.  Returns (logdet complex (nprob,), [G_i])."""
+    torch = _torch()
+    lib = load_library()
+    probs = _batch(problems)
+    n = len(probs)
+    dev = problems[0][0].device
+    arr = (FdProblem * n)(*probs)
+    o = _opts(s=s, segments=segments, flags=flags)
+    ld = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    if want_g:
+        total = sum(2 * p.N * p.N for p in probs)
+        G = torch.empty(total, dtype=torch.float64, device=dev)
+        need = workspace_bytes(probs, FD_WHAT_GREENS, s=s, segments=segments)
+        wsp, wsn = (ws or _default_ws).get(need, dev)
+        _check(lib.fd_greens_batched(arr, n, ctypes.byref(o), ld.data_ptr(), G.data_ptr(), wsp,
+                                     wsn, status.data_ptr(), _stream()))
+    else:
+        need = workspace_bytes(probs, FD_WHAT_LOGDET, s=s, segments=segments)
+        wsp, wsn = (ws or _default_ws).get(need, dev)
+        _check(lib.fd_logdet_batched(arr, n, ctypes.byref(o), ld.data_ptr(), wsp, wsn,
+                                     status.data_ptr(), _stream()))
+    _status_check(status, check)
+    Gs = []
+    if want_g:
+        off = 0
+        for p in probs:
+            m = 2 * p.N * p.N
+            Gs.append(torch.view_as_complex(G[off:off + m].view(p.N, p.N, 2)))
+            off += m
+    return torch.view_as_complex(ld), Gs
+
+
+def force_batched(problems, s=0, checkpoint=0, flags=0, check=True, ws: Workspace | None = None):
+    """Batched complex force of a list of (K, phi, dk) -> ([F_i], logdet (nprob,))."""
+    torch = _torch()
+    lib = load_library()
+    probs = _batch(problems)
+    n = len(probs)
+    dev = problems[0][0].device
+    arr = (FdProblem * n)(*probs)
+    o = _opts(s=s, checkpoint=checkpoint, flags=flags)
+    total = sum(p.N * p.Nt for p in probs)
+    Fr = torch.empty(total, dtype=torch.float64, device=dev)
+    Fi = torch.empty(total, dtype=torch.float64, device=dev)
+    ld = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    need = workspace_bytes(probs, FD_WHAT_FORCE, s=s, checkpoint=checkpoint)
+    wsp, wsn = (ws or _default_ws).get(need, dev)
+    _check(lib.fd_force_batched(arr, n, ctypes.byref(o), ld.data_ptr(), Fr.data_ptr(),
+                                Fi.data_ptr(), wsp, wsn, status.data_ptr(), _stream()))
+    _status_check(status, check)
+    Fs, off = [], 0
+    for p in probs:
+        m = p.N * p.Nt
+        Fs.append(torch.complex(Fr[off:off + m], Fi[off:off + m]).view(p.Nt, p.N))
+        off += m
+    return Fs, torch.view_as_complex(ld)

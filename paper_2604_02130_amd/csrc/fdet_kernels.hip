@@ -1,0 +1,643 @@
+// gfx950 kernels for the stabilised fermion determinant.
+//
+// One workgroup executes one work item (see fdet_plan.h):
+//   IK_EXPM     E = exp(+-dk K) by a scaled Taylor polynomial and squaring
+//               (Sec. 8 notes a truncated polynomial may stand for the
+//               exponential; Sec. 6 diagonalises instead).
+//   IK_CHAIN    product of a range of slices B_t = E diag(e^{i phi_t}) as
+//               X diag(D) T (eq. def_matrix_as_product), re-decomposed by a
+//               pivoted QR every s slices (Sec. 7 steps 2-3, Sec. 9).
+//   IK_COMBINE  stabilised product of two UDV triples
+//               (eqs. prod_2_mat_stab .. res_2_mat_stab).
+//   IK_CLOSE    log det(1 + X D T) and (1 + X D T)^{-1} (Sec. 7 steps 4-6).
+//   IK_FORCE    G~ at a checkpoint from prefix and suffix UDVs (Sec. 5,
+//               stabilised pre- and suffix), then G~_{t+1} = B_t G~_t B_t^{-1}
+//               across the checkpoint interval; F_{t,x} = i (1 - G~_t)_{xx}.
+//   IK_EXPORT   copy a UDV triple out in the caller's layout.
+#include "fdet_device.hpp"
+#include "fdet_plan.h"
+
+namespace fdet {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ void status_merge(int32_t* st, int32_t code) {
+  if (code == 0 || st == nullptr) return;
+  int32_t old = *((volatile int32_t*)st);
+  while (true) {
+    int32_t worse = (old < 0 || code < 0) ? (old < code ? old : code) : (old > code ? old : code);
+    if (worse == old) return;
+    int32_t prev = atomicCAS(st, old, worse);
+    if (prev == old) return;
+    old = prev;
+  }
+}
+
+template <int MAXN>
+__device__ void load_phases(const Prob& P, int t, Smem<MAXN>& S) {
+  for (int x = threadIdx.x; x < P.N; x += WG) {
+    double sv, cv;
+    sincos(P.phi[(size_t)t * P.N + x], &sv, &cv);
+    S.phr[x] = cv;
+    S.phi_[x] = sv;
+  }
+}
+
+__device__ void set_identity(CMat A, int N) {
+  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
+    const int i = idx % N, j = idx / N;
+    A.r(i, j) = (i == j) ? 1.0 : 0.0;
+    A.m(i, j) = 0.0;
+  }
+}
+
+__device__ void copy_cmat(CMat dst, CMat src, int N) {
+  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
+    const int i = idx % N, j = idx / N;
+    dst.r(i, j) = src.r(i, j);
+    dst.m(i, j) = src.m(i, j);
+  }
+}
+
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane_id() == 0) red[wave_id()] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < NWAVE; ++w) t += red[w];
+  __syncthreads();
+  return t;
+}
+
+__device__ double block_max(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane_id() == 0) red[wave_id()] = v;
+  __syncthreads();
+  double t = red[0];
+#pragma unroll
+  for (int w = 1; w < NWAVE; ++w) t = fmax(t, red[w]);
+  __syncthreads();
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// slice products
+// ---------------------------------------------------------------------------
+
+// out = E diag(e^{i phi_t}) in     (forward slice B_t)
+template <int MAXN>
+__device__ void slice_forward(const Prob& P, CMat in, CMat out, Smem<MAXN>& S) {
+  const int N = P.N, Np = P.Np;
+  const double* E = P.E;
+  gemm_rc(
+      Np, [&](int i, int k) { return (i < N && k < N) ? E[(size_t)k * Np + i] : 0.0; },
+      [&](int k, int j, double& br, double& bi) {
+        if (k < N && j < N) {
+          const double xr = in.r(k, j), xi = in.m(k, j), c = S.phr[k], s = S.phi_[k];
+          br = c * xr - s * xi;
+          bi = s * xr + c * xi;
+        } else {
+          br = 0.0; bi = 0.0;
+        }
+      },
+      [&](int i, int j, double cr, double ci) {
+        if (i < N && j < N) { out.r(i, j) = cr; out.m(i, j) = ci; }
+      });
+}
+
+// out = diag(e^{-i phi_t}) E in    (B_t^H for real symmetric E)
+template <int MAXN>
+__device__ void slice_adjoint(const Prob& P, CMat in, CMat out, Smem<MAXN>& S) {
+  const int N = P.N, Np = P.Np;
+  const double* E = P.E;
+  gemm_rc(
+      Np, [&](int i, int k) { return (i < N && k < N) ? E[(size_t)k * Np + i] : 0.0; },
+      [&](int k, int j, double& br, double& bi) {
+        if (k < N && j < N) { br = in.r(k, j); bi = in.m(k, j); }
+        else { br = 0.0; bi = 0.0; }
+      },
+      [&](int i, int j, double cr, double ci) {
+        if (i < N && j < N) {
+          const double c = S.phr[i], s = S.phi_[i];
+          out.r(i, j) = c * cr + s * ci;
+          out.m(i, j) = c * ci - s * cr;
+        }
+      });
+}
+
+// After wg_qrp on W with keys: D_new (S.v2) = |R_ii| keys_i and the row scale
+// S.v3 = 1 / D_new used to build T' = D_new^{-1} R diag(keys) (unit-modulus
+// diagonal).  Returns nothing; flags a zero or non-finite scale in S.flag.
+template <int MAXN>
+__device__ void udv_scales(CMat W, int N, Smem<MAXN>& S) {
+  for (int i = threadIdx.x; i < N; i += WG) {
+    const double a = hypot(W.r(i, i), W.m(i, i));
+    const double d = a * S.csp[i];
+    S.v2[i] = d;
+    S.v3[i] = (d > 0.0 && isfinite(d)) ? 1.0 / d : 0.0;
+    if (!(d > 0.0) || !isfinite(d)) S.flag = 1;
+  }
+}
+
+// To = T' Pi^T T2op with T'(i,k) = R(i,k) keys_k / D_new_i for k >= i.
+template <int MAXN, class LT2>
+__device__ void udv_new_t(CMat W, int N, int Np, LT2 t2, CMat To, Smem<MAXN>& S) {
+  gemm_cc(
+      Np,
+      [&](int i, int k, double& ar, double& ai) {
+        if (i < N && k < N && k >= i) {
+          const double sc = S.csp[k] * S.v3[i];
+          ar = W.r(i, k) * sc;
+          ai = W.m(i, k) * sc;
+        } else {
+          ar = 0.0; ai = 0.0;
+        }
+      },
+      [&](int k, int j, double& br, double& bi) {
+        if (k < N && j < N) t2(S.piv[k], j, br, bi);
+        else { br = 0.0; bi = 0.0; }
+      },
+      [&](int i, int j, double cr, double ci) {
+        if (i < N && j < N) { To.r(i, j) = cr; To.m(i, j) = ci; }
+      });
+}
+
+// ---------------------------------------------------------------------------
+// IK_CHAIN
+// ---------------------------------------------------------------------------
+template <int MAXN>
+__device__ void do_chain(const Prob& P, const Item& it, Smem<MAXN>& S);
+
+template <int MAXN>
+__device__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
+                         bool user_out, Smem<MAXN>& S);
+
+template <int MAXN>
+__device__ void chain_chunk(const Prob& P, const Item& it, CMat X, CMat& Tc, CMat& Tt, double* D,
+                            CMat W, CMat Y2, int tfirst, int ns, bool adj, Smem<MAXN>& S) {
+  const int N = P.N, Np = P.Np;
+  CMat src = X;
+  CMat dst = (ns & 1) ? W : Y2;
+  for (int q = 0; q < ns; ++q) {
+    const int t = adj ? tfirst - q : tfirst + q;
+    load_phases(P, t, S);
+    __syncthreads();
+    if (adj) slice_adjoint(P, src, dst, S);
+    else slice_forward(P, src, dst, S);
+    __syncthreads();
+    src = dst;
+    dst = (dst.re == W.re) ? Y2 : W;
+  }
+  wg_qrp<MAXN>(W, N, D, S);
+  udv_scales(W, N, S);
+  __syncthreads();
+  wg_form_q<MAXN>(W, N, X, S);
+  udv_new_t<MAXN>(W, N, Np,
+                  [&](int r, int j, double& br, double& bi) { br = Tc.r(r, j); bi = Tc.m(r, j); },
+                  Tt, S);
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += WG) D[i] = S.v2[i];
+  CMat tmp = Tc; Tc = Tt; Tt = tmp;
+  __syncthreads();
+}
+
+__device__ void save_ckpt(double* dst, CMat X, CMat T, const double* D, int N, int Np) {
+  CMat Xc = cmat_at(dst, Np), Tc = cmat_at(dst + cmat_doubles(Np), Np);
+  double* Dc = dst + 2 * cmat_doubles(Np);
+  copy_cmat(Xc, X, N);
+  copy_cmat(Tc, T, N);
+  for (int i = threadIdx.x; i < N; i += WG) Dc[i] = D[i];
+}
+
+template <int MAXN>
+__device__ void do_chain(const Prob& P, const Item& it, Smem<MAXN>& S) {
+  const int N = P.N, Np = P.Np;
+  const size_t cd = cmat_doubles(Np);
+  CMat X = cmat_at(it.a.X, Np), T = cmat_at(it.a.T, Np);
+  double* D = it.a.D;
+  CMat W = cmat_at(it.scr, Np), Y2 = cmat_at(it.scr + cd, Np), Tn = cmat_at(it.scr + 2 * cd, Np);
+  const bool adj = (it.flags & IF_ADJOINT) != 0;
+  const bool ckpt = (it.flags & IF_CKPT) != 0;
+  if (threadIdx.x == 0) S.flag = 0;
+  if (it.flags & IF_IDENTITY) {
+    set_identity(X, N);
+    set_identity(T, N);
+    for (int i = threadIdx.x; i < N; i += WG) D[i] = 1.0;
+  }
+  __syncthreads();
+  CMat Tc = T, Tt = Tn;
+  const int rows = it.t1 - it.t0;
+  const int c = ckpt ? it.c : (rows > 0 ? rows : 1);
+  const int nck = (rows + c - 1) / c;
+  const int s = it.s;
+  for (int q = 0; q < nck; ++q) {
+    const int kseg = adj ? (nck - 1 - q) : q;
+    const int r0 = it.t0 + kseg * c;
+    const int r1 = min(r0 + c, it.t1);
+    if (ckpt && !adj) save_ckpt(it.ck + (size_t)kseg * it.ckstride, X, Tc, D, N, Np);
+    if (ckpt && !adj) __syncthreads();
+    if (!adj) {
+      for (int t = r0; t < r1; t += s) chain_chunk(P, it, X, Tc, Tt, D, W, Y2, t, min(s, r1 - t), false, S);
+    } else {
+      for (int t = r1 - 1; t >= r0; t -= s) chain_chunk(P, it, X, Tc, Tt, D, W, Y2, t, min(s, t - r0 + 1), true, S);
+    }
+    if (ckpt && adj) { save_ckpt(it.ck + (size_t)kseg * it.ckstride, X, Tc, D, N, Np); __syncthreads(); }
+  }
+  if (Tc.re != T.re) {
+    copy_cmat(T, Tc, N);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && S.flag) status_merge(P.status, -4);
+  if (it.flags & IF_CLOSE_AFTER) {
+    Udv U = it.a;
+    do_close<MAXN>(P, U, W, Y2, Tn, false, true, S);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// IK_COMBINE and the shared stabilised product
+// result = A1 A2 with A1 = (X1, D1, T1) and A2 = (X2, D2, T2); when B_ADJ the
+// second operand is given by the UDV (Xs, Ds, Ts) of its adjoint, i.e.
+// X2 = Ts^H, D2 = Ds, T2 = Xs^H.
+// ---------------------------------------------------------------------------
+template <int MAXN, bool B_ADJ>
+__device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMat Xo, CMat To,
+                             double* Do, Smem<MAXN>& S) {
+  const int N = P.N, Np = P.Np;
+  CMat X1 = cmat_at(A1.X, Np), T1 = cmat_at(A1.T, Np);
+  CMat X2 = cmat_at(A2.X, Np), T2 = cmat_at(A2.T, Np);
+  const double* D1 = A1.D;
+  for (int i = threadIdx.x; i < N; i += WG) S.v1[i] = D1[i];
+  __syncthreads();
+  // bracket D1 (T1 X2): its column scale D2 is left to the pivoted QR keys
+  gemm_cc(
+      Np,
+      [&](int i, int k, double& ar, double& ai) {
+        if (i < N && k < N) { ar = T1.r(i, k); ai = T1.m(i, k); }
+        else { ar = 0.0; ai = 0.0; }
+      },
+      [&](int k, int j, double& br, double& bi) {
+        if (k < N && j < N) {
+          if (B_ADJ) { br = T2.r(j, k); bi = -T2.m(j, k); }   // (Ts^H)(k,j)
+          else { br = X2.r(k, j); bi = X2.m(k, j); }
+        } else {
+          br = 0.0; bi = 0.0;
+        }
+      },
+      [&](int i, int j, double cr, double ci) {
+        if (i < N && j < N) { W.r(i, j) = S.v1[i] * cr; W.m(i, j) = S.v1[i] * ci; }
+      });
+  __syncthreads();
+  wg_qrp<MAXN>(W, N, A2.D, S);
+  udv_scales(W, N, S);
+  __syncthreads();
+  wg_form_q<MAXN>(W, N, Qb, S);
+  // X = X1 Q
+  gemm_cc(
+      Np,
+      [&](int i, int k, double& ar, double& ai) {
+        if (i < N && k < N) { ar = X1.r(i, k); ai = X1.m(i, k); }
+        else { ar = 0.0; ai = 0.0; }
+      },
+      [&](int k, int j, double& br, double& bi) {
+        if (k < N && j < N) { br = Qb.r(k, j); bi = Qb.m(k, j); }
+        else { br = 0.0; bi = 0.0; }
+      },
+      [&](int i, int j, double cr, double ci) {
+        if (i < N && j < N) { Xo.r(i, j) = cr; Xo.m(i, j) = ci; }
+      });
+  // T = T' Pi^T T2
+  udv_new_t<MAXN>(W, N, Np,
+                  [&](int r, int j, double& br, double& bi) {
+                    if (B_ADJ) { br = X2.r(j, r); bi = -X2.m(j, r); }   // (Xs^H)(r,j)
+                    else { br = T2.r(r, j); bi = T2.m(r, j); }
+                  },
+                  To, S);
+  __syncthreads();
+  for (int i = threadIdx.x; i < N; i += WG) Do[i] = S.v2[i];
+  __syncthreads();
+}
+
+template <int MAXN>
+__device__ void do_combine(const Prob& P, const Item& it, Smem<MAXN>& S) {
+  const int N = P.N, Np = P.Np;
+  const size_t cd = cmat_doubles(Np);
+  CMat W = cmat_at(it.scr, Np), Qb = cmat_at(it.scr + cd, Np);
+  CMat Xo = cmat_at(it.scr + 2 * cd, Np), To = cmat_at(it.scr + 3 * cd, Np);
+  double* Do = it.scr + 4 * cd;
+  if (threadIdx.x == 0) S.flag = 0;
+  // later segment (b) on the left, earlier (a) on the right; result into a
+  combine_core<MAXN, false>(P, it.b, it.a, W, Qb, Xo, To, Do, S);
+  copy_cmat(cmat_at(it.a.X, Np), Xo, N);
+  copy_cmat(cmat_at(it.a.T, Np), To, N);
+  for (int i = threadIdx.x; i < N; i += WG) it.a.D[i] = Do[i];
+  if (threadIdx.x == 0 && S.flag) status_merge(P.status, -4);
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// IK_CLOSE: log det(1 + X D T) and G = (1 + X D T)^{-1}.
+// With D_b = max(D, 1) and D_s = min(D, 1):
+//   1 + X D T = X (1 + D T X) X^H = X D_b A X^H,  A = D_b^{-1} + D_s T X,
+// A has O(1) rows, and its pivoted QR A Pi = Q R gives
+//   log det = sum log R_ii + sum log D_b + i pi (nref + parity(Pi)),
+//   G = X Pi R^{-1} Q^H D_b^{-1} X^H.
+// This is Sec. 7 steps 4-6 with the rows of 1 + D T X divided by D_b first.
+// ---------------------------------------------------------------------------
+template <int MAXN>
+__device__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
+                         bool user_out, Smem<MAXN>& S) {
+  const int N = P.N, Np = P.Np;
+  CMat X = cmat_at(U.X, Np), T = cmat_at(U.T, Np);
+  bool bad = false;
+  for (int i = threadIdx.x; i < N; i += WG) {
+    const double d = U.D[i];
+    if (!isfinite(d)) bad = true;
+    S.v1[i] = d > 1.0 ? d : 1.0;
+    S.v2[i] = d < 1.0 ? d : 1.0;
+  }
+  __syncthreads();
+  gemm_cc(
+      Np,
+      [&](int i, int k, double& ar, double& ai) {
+        if (i < N && k < N) { ar = T.r(i, k); ai = T.m(i, k); }
+        else { ar = 0.0; ai = 0.0; }
+      },
+      [&](int k, int j, double& br, double& bi) {
+        if (k < N && j < N) { br = X.r(k, j); bi = X.m(k, j); }
+        else { br = 0.0; bi = 0.0; }
+      },
+      [&](int i, int j, double cr, double ci) {
+        if (i < N && j < N) {
+          W.r(i, j) = S.v2[i] * cr + (i == j ? 1.0 / S.v1[i] : 0.0);
+          W.m(i, j) = S.v2[i] * ci;
+        }
+      });
+  __syncthreads();
+  wg_qrp<MAXN>(W, N, nullptr, S);
+  // log det
+  double lr = 0.0, li = 0.0, amin = INFINITY, amax = 0.0;
+  for (int i = threadIdx.x; i < N; i += WG) {
+    const double rr = W.r(i, i), ri = W.m(i, i);
+    const double a = hypot(rr, ri);
+    lr += log(a) + log(S.v1[i]);
+    li += atan2(ri, rr);
+    amin = fmin(amin, a);
+    amax = fmax(amax, a);
+    if (!isfinite(a)) bad = true;
+  }
+  lr = block_sum(lr, S.red);
+  li = block_sum(li, S.red);
+  amax = block_max(amax, S.red);
+  amin = -block_max(-amin, S.red);
+  const double nbad = block_sum(bad ? 1.0 : 0.0, S.red);
+  if (threadIdx.x == 0) {
+    // parity of the pivot permutation by cycle counting
+    int par = 0;
+    for (int i = 0; i < N; ++i) S.pinv[i] = 0;
+    for (int i = 0; i < N; ++i) {
+      if (S.pinv[i]) continue;
+      int j = i, len = 0;
+      while (!S.pinv[j]) { S.pinv[j] = 1; j = S.piv[j]; ++len; }
+      par ^= (len - 1) & 1;
+    }
+    double im = li + kPi * (double)((S.nref + par) & 1);
+    im = remainder(im, 2.0 * kPi);
+    if (im <= -kPi) im += 2.0 * kPi;
+    if (user_out && P.logdet) { P.logdet[0] = lr; P.logdet[1] = im; }
+    int32_t code = 0;
+    if (nbad > 0.0) code = -4;
+    else if (!(amin > 0.0)) code = -3;
+    else if (amin < 1e3 * N * 2.220446049250313e-16 * fmax(1.0, amax)) code = 1;
+    status_merge(P.status, code);
+  }
+  __syncthreads();
+  if (!want_g) return;
+  // Yb = D_b^{-1} X^H
+  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
+    const int i = idx % N, j = idx / N;
+    const double sc = 1.0 / S.v1[i];
+    Yb.r(i, j) = X.r(j, i) * sc;
+    Yb.m(i, j) = -X.m(j, i) * sc;
+  }
+  for (int r = threadIdx.x; r < N; r += WG) S.pinv[S.piv[r]] = r;
+  __syncthreads();
+  wg_apply_qh<MAXN>(W, N, Yb, S);
+  __syncthreads();
+  wg_backsolve<MAXN>(W, N, Yb);
+  __syncthreads();
+  // G = X Pi Z: row a of (Pi Z) is row pinv[a] of Z
+  double* Gu = P.G;
+  gemm_cc(
+      Np,
+      [&](int i, int k, double& ar, double& ai) {
+        if (i < N && k < N) { ar = X.r(i, k); ai = X.m(i, k); }
+        else { ar = 0.0; ai = 0.0; }
+      },
+      [&](int k, int j, double& br, double& bi) {
+        if (k < N && j < N) { const int r = S.pinv[k]; br = Yb.r(r, j); bi = Yb.m(r, j); }
+        else { br = 0.0; bi = 0.0; }
+      },
+      [&](int i, int j, double cr, double ci) {
+        if (i < N && j < N) {
+          if (user_out) {
+            Gu[2 * ((size_t)i * N + j)] = cr;
+            Gu[2 * ((size_t)i * N + j) + 1] = ci;
+          } else {
+            Gint.r(i, j) = cr;
+            Gint.m(i, j) = ci;
+          }
+        }
+      });
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// IK_FORCE
+// ---------------------------------------------------------------------------
+template <int MAXN>
+__device__ void do_force(const Prob& P, const Item& it, Smem<MAXN>& S) {
+  const int N = P.N, Np = P.Np;
+  const size_t cd = cmat_doubles(Np);
+  CMat W = cmat_at(it.scr, Np), Qb = cmat_at(it.scr + cd, Np);
+  CMat Xc = cmat_at(it.scr + 2 * cd, Np), Tc = cmat_at(it.scr + 3 * cd, Np);
+  double* Dc = it.scr + 4 * cd;
+  if (threadIdx.x == 0) S.flag = 0;
+  // G~ at the first slice of the interval: (1 + P_k S_k)^{-1}
+  combine_core<MAXN, true>(P, it.a, it.b, W, Qb, Xc, Tc, Dc, S);
+  Udv U;
+  U.X = Xc.re; U.T = Tc.re; U.D = Dc;
+  do_close<MAXN>(P, U, W, Qb, W, true, false, S);
+  CMat G = W, Y = Qb;
+  const double* E = P.E;
+  const double* Ei = P.Einv;
+  for (int t = it.t0; t < it.t1; ++t) {
+    for (int x = threadIdx.x; x < N; x += WG) {
+      P.force[(size_t)t * N + x] = G.m(x, x);
+      if (P.force_im) P.force_im[(size_t)t * N + x] = 1.0 - G.r(x, x);
+    }
+    if (t + 1 >= it.t1) break;
+    load_phases(P, t, S);
+    __syncthreads();
+    // Y = E diag(e^{i phi}) G diag(e^{-i phi})
+    gemm_rc(
+        Np, [&](int i, int k) { return (i < N && k < N) ? E[(size_t)k * Np + i] : 0.0; },
+        [&](int k, int j, double& br, double& bi) {
+          if (k < N && j < N) {
+            const double gr = G.r(k, j), gi = G.m(k, j);
+            // e^{i(phi_k - phi_j)}
+            const double c = S.phr[k] * S.phr[j] + S.phi_[k] * S.phi_[j];
+            const double s = S.phi_[k] * S.phr[j] - S.phr[k] * S.phi_[j];
+            br = c * gr - s * gi;
+            bi = s * gr + c * gi;
+          } else {
+            br = 0.0; bi = 0.0;
+          }
+        },
+        [&](int i, int j, double cr, double ci) {
+          if (i < N && j < N) { Y.r(i, j) = cr; Y.m(i, j) = ci; }
+        });
+    __syncthreads();
+    // G = Y E^{-1}
+    gemm_cr(
+        Np,
+        [&](int i, int k, double& ar, double& ai) {
+          if (i < N && k < N) { ar = Y.r(i, k); ai = Y.m(i, k); }
+          else { ar = 0.0; ai = 0.0; }
+        },
+        [&](int k, int j) { return (k < N && j < N) ? Ei[(size_t)j * Np + k] : 0.0; },
+        [&](int i, int j, double cr, double ci) {
+          if (i < N && j < N) { G.r(i, j) = cr; G.m(i, j) = ci; }
+        });
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && S.flag) status_merge(P.status, -4);
+}
+
+// ---------------------------------------------------------------------------
+// IK_EXPM: exp(sign dk K) = (Taylor_16(A / 2^q))^(2^q), A = sign dk K,
+// q chosen so that |A / 2^q|_1 <= 1/2 (truncation below 1e-19).
+// ---------------------------------------------------------------------------
+template <int MAXN>
+__device__ void do_expm(const Prob& P, const Item& it, Smem<MAXN>& S) {
+  const int N = P.N, Np = P.Np;
+  const double* K = P.K;
+  double* B0 = it.scr;
+  double* B1 = it.scr + (size_t)Np * Np;
+  double* out = (it.sign > 0) ? P.E : P.Einv;
+  // 1-norm of dk K
+  double cm = 0.0;
+  for (int j = threadIdx.x; j < N; j += WG) {
+    double acc = 0.0;
+    for (int i = 0; i < N; ++i) acc += fabs(K[(size_t)i * N + j]);
+    cm = fmax(cm, acc);
+  }
+  const double nrm = fabs(P.dk) * block_max(cm, S.red);
+  int q = 0;
+  double scaled = nrm;
+  while (scaled > 0.5 && q < 1000) { scaled *= 0.5; ++q; }
+  const double a = (double)it.sign * P.dk * ldexp(1.0, -q);
+  // Horner: Y <- 1 + (a/k) K Y, k = 16..1, starting from Y = 1
+  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
+    const int i = idx % N, j = idx / N;
+    B0[(size_t)j * Np + i] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double* cur = B0;
+  double* nxt = B1;
+  for (int k = 16; k >= 1; --k) {
+    const double f = a / (double)k;
+    gemm_rr(
+        Np, [&](int i, int kk) { return (i < N && kk < N) ? K[(size_t)i * N + kk] : 0.0; },
+        [&](int kk, int j) { return (kk < N && j < N) ? cur[(size_t)j * Np + kk] : 0.0; },
+        [&](int i, int j, double c) {
+          if (i < N && j < N) nxt[(size_t)j * Np + i] = f * c + (i == j ? 1.0 : 0.0);
+        });
+    __syncthreads();
+    double* t = cur; cur = nxt; nxt = t;
+  }
+  for (int r = 0; r < q; ++r) {
+    gemm_rr(
+        Np, [&](int i, int kk) { return (i < N && kk < N) ? cur[(size_t)kk * Np + i] : 0.0; },
+        [&](int kk, int j) { return (kk < N && j < N) ? cur[(size_t)j * Np + kk] : 0.0; },
+        [&](int i, int j, double c) {
+          if (i < N && j < N) nxt[(size_t)j * Np + i] = c;
+        });
+    __syncthreads();
+    double* t = cur; cur = nxt; nxt = t;
+  }
+  bool bad = false;
+  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
+    const int i = idx % N, j = idx / N;
+    const double v = cur[(size_t)j * Np + i];
+    if (!isfinite(v)) bad = true;
+    out[(size_t)j * Np + i] = v;
+    if (it.sign > 0 && P.outE) P.outE[(size_t)i * N + j] = v;
+  }
+  if (bad) status_merge(P.status, -4);
+}
+
+// ---------------------------------------------------------------------------
+// IK_EXPORT: X, D, T of slot a in the caller's layout.
+// ---------------------------------------------------------------------------
+template <int MAXN>
+__device__ void do_export(const Prob& P, const Item& it, Smem<MAXN>&) {
+  const int N = P.N, Np = P.Np;
+  CMat X = cmat_at(it.a.X, Np), T = cmat_at(it.a.T, Np);
+  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
+    const int i = idx / N, j = idx % N;
+    if (P.outX) { P.outX[2 * (size_t)idx] = X.r(i, j); P.outX[2 * (size_t)idx + 1] = X.m(i, j); }
+    if (P.outT) { P.outT[2 * (size_t)idx] = T.r(i, j); P.outT[2 * (size_t)idx + 1] = T.m(i, j); }
+  }
+  for (int i = threadIdx.x; i < N; i += WG)
+    if (P.outD) P.outD[i] = it.a.D[i];
+}
+
+template <int MAXN>
+__global__ __launch_bounds__(WG) void k_items(const Prob* __restrict__ probs,
+                                              const Item* __restrict__ items) {
+  __shared__ Smem<MAXN> S;
+  const Item it = items[blockIdx.x];
+  const Prob P = probs[it.prob];
+  switch (it.kind) {
+    case IK_EXPM: do_expm<MAXN>(P, it, S); break;
+    case IK_CHAIN: do_chain<MAXN>(P, it, S); break;
+    case IK_COMBINE: do_combine<MAXN>(P, it, S); break;
+    case IK_CLOSE: {
+      const size_t cd = cmat_doubles(P.Np);
+      CMat W = cmat_at(it.scr, P.Np), Yb = cmat_at(it.scr + cd, P.Np);
+      do_close<MAXN>(P, it.a, W, Yb, W, (it.flags & IF_WANT_G) != 0, true, S);
+      break;
+    }
+    case IK_FORCE: do_force<MAXN>(P, it, S); break;
+    case IK_EXPORT: do_export<MAXN>(P, it, S); break;
+    default: break;
+  }
+}
+
+__global__ void k_init_status(const Prob* __restrict__ probs, int nprob) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nprob && probs[i].status) *probs[i].status = 0;
+}
+
+}  // namespace fdet
+
+// Launchers used by the host planner.
+extern "C" hipError_t fdet_launch_items(int maxn, const fdet::Prob* probs, const fdet::Item* items,
+                                        int nitems, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  if (maxn <= 128)
+    hipLaunchKernelGGL(fdet::k_items<128>, dim3(nitems), dim3(fdet::WG), 0, st, probs, items);
+  else
+    hipLaunchKernelGGL(fdet::k_items<512>, dim3(nitems), dim3(fdet::WG), 0, st, probs, items);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t fdet_launch_init_status(const fdet::Prob* probs, int nprob, hipStream_t st) {
+  hipLaunchKernelGGL(fdet::k_init_status, dim3((nprob + 255) / 256), dim3(256), 0, st, probs, nprob);
+  return hipGetLastError();
+}

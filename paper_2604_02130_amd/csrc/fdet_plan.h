@@ -1,0 +1,62 @@
+// Work descriptors shared by the host planner and the kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace fdet {
+
+// One problem (one field configuration).
+struct Prob {
+  int N, Np, Nt, pad0;
+  double dk;
+  const double* K;      // user, N*N real symmetric
+  const double* phi;    // user, Nt*N
+  double* E;            // workspace, Np*Np column-major: exp(dk K)
+  double* Einv;         // workspace, Np*Np: exp(-dk K)
+  int32_t* status;      // user, 1 int32
+  double* logdet;       // user, 2 doubles (may be null)
+  double* G;            // user, N*N interleaved complex row-major (may be null)
+  double* force;        // user, Nt*N (may be null)
+  double* force_im;     // user, Nt*N (may be null)
+  double* outE;         // user, N*N real row-major (may be null)
+  double* outX;         // user UDV export (may be null)
+  double* outD;
+  double* outT;
+};
+
+enum ItemKind : int32_t {
+  IK_EXPM = 0,      // E (sign +1) or Einv (sign -1) of one problem
+  IK_CHAIN = 1,     // stabilised product of a range of slices
+  IK_COMBINE = 2,   // UDV(a) <- UDV(b) x UDV(a): stabilised product of two
+  IK_CLOSE = 3,     // log det (+ G) from a UDV
+  IK_FORCE = 4,     // G~ at a checkpoint, then wrap over the checkpoint interval
+  IK_EXPORT = 5,    // copy a UDV out in user layout
+};
+
+enum ItemFlags : int32_t {
+  IF_ADJOINT = 1,      // chain: accumulate the adjoint of the suffix product
+  IF_IDENTITY = 2,     // chain: start from the identity
+  IF_CKPT = 4,         // chain: write UDV checkpoints
+  IF_WANT_G = 8,       // close: also form G
+  IF_CLOSE_AFTER = 16, // chain: close (log det only) at the end
+};
+
+// A UDV triple X diag(D) T in workspace layout.
+struct Udv {
+  double* X;   // cmat
+  double* T;   // cmat
+  double* D;   // Np doubles
+};
+
+struct Item {
+  int32_t kind, prob, flags, sign;
+  int32_t t0, t1;       // slice rows [t0, t1)
+  int32_t s, c;         // stabilisation and checkpoint intervals
+  Udv a;                // state / first operand / result
+  Udv b;                // second operand (combine, force suffix)
+  double* ck;           // checkpoint array base (IF_CKPT)
+  int64_t ckstride;     // doubles per checkpoint
+  double* scr;          // scratch: 4 cmats + 2*Np doubles
+};
+
+}  // namespace fdet

@@ -1,0 +1,310 @@
+"""GPU parity: libfdet against the CPU oracle on the same seeded inputs.
+
+Bar (taken from the problem statement): relative error of log det M (with the
+imaginary part compared modulo 2 pi) <= 1e-10, max-abs error of G <= 1e-10,
+max-abs error of the force against the oracle gradient <= 1e-10, and against
+central finite differences (h = 1e-6) <= 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workload import WORKLOADS, Workload, honeycomb_hopping, sample_phi, uniform_phi
+
+pytestmark = pytest.mark.gpu
+
+TOL_LD = 1e-10
+TOL_G = 1e-10
+TOL_F = 1e-10
+
+
+def wrapped(a, b):
+    d = complex(a) - complex(b)
+    return complex(d.real, math.remainder(d.imag, 2 * math.pi))
+
+
+def dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+
+
+def check_ld(ld, ref, tol=TOL_LD):
+    err = abs(wrapped(ld, ref)) / max(abs(ref), 1e-300)
+    assert err <= tol, (complex(ld), complex(ref), err)
+
+
+def check_G(G, ref, tol=TOL_G):
+    err = np.abs(np.asarray(G) - ref).max()
+    assert err <= tol, err
+
+
+def gpu_greens(fd, K, phi, dk, **kw):
+    ld, G = fd.greens(to_dev(K), to_dev(phi), dk, **kw)
+    return complex(ld.item()), G.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# a1: slice exponential
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("L,dk", [(2, 0.125), (3, 0.125), (6, 0.125), (8, 0.4), (3, 2.0)])
+def test_slice_exponential(fd, L, dk):
+    K = honeycomb_hopping(L)
+    E = fd.slice_exponential(to_dev(K), dk).cpu().numpy()
+    ref = O.slice_exponential(K, dk)
+    assert np.abs(E - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+
+
+def test_slice_exponential_random_symmetric(fd):
+    rng = np.random.default_rng(3)
+    for N in (1, 5, 17, 40, 129):
+        A = rng.normal(size=(N, N))
+        K = (A + A.T) / 2
+        E = fd.slice_exponential(to_dev(K), 0.3).cpu().numpy()
+        ref = O.slice_exponential(K, 0.3)
+        assert np.abs(E - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), N
+
+
+# ---------------------------------------------------------------------------
+# a2-a5: log det and G
+# ---------------------------------------------------------------------------
+
+CASES = [
+    # L, Nt, beta, U, s, segments
+    (2, 8, 1.0, 2.0, 1, 1),
+    (2, 13, 2.0, 2.0, 4, 1),      # ragged last chunk
+    (3, 16, 2.0, 2.0, 4, 1),      # the plain-det workload shape
+    (3, 16, 2.0, 2.0, 4, 4),      # four segments combined
+    (3, 37, 4.0, 3.0, 5, 3),      # ragged segments and chunks
+    (5, 32, 4.0, 3.0, 8, 2),      # N = 50: ragged MFMA tiles
+    (4, 64, 8.0, 3.0, 8, 1),
+]
+
+
+@pytest.mark.parametrize("L,Nt,beta,U,s,seg", CASES)
+def test_greens_vs_oracle(fd, L, Nt, beta, U, s, seg):
+    K = honeycomb_hopping(L)
+    dk = beta / Nt
+    phi = sample_phi(100 + L + Nt, Nt, K.shape[0], dk, U)
+    ld, G = gpu_greens(fd, K, phi, dk, s=s, segments=seg)
+    lo, Go = O.stabilised_logdet_greens(K, dk, phi)
+    check_ld(ld, lo)
+    check_G(G, Go)
+
+
+def test_greens_vs_bruteforce(fd):
+    K = honeycomb_hopping(2)
+    Nt, beta = 24, 6.0
+    dk = beta / Nt
+    phi = sample_phi(8, Nt, 8, dk, 3.0)
+    ld, G = gpu_greens(fd, K, phi, dk, s=4)
+    lb, Gb = O.bruteforce_logdet_greens(K, dk, phi)
+    check_ld(ld, lb)
+    check_G(G, Gb)
+
+
+def test_single_slice(fd):
+    for L in (2, 3, 5):
+        K = honeycomb_hopping(L)
+        N = K.shape[0]
+        phi = sample_phi(L, 1, N, 0.4, 3.0)
+        ld, G = gpu_greens(fd, K, phi, 0.4, s=1)
+        lo, Go = O.dense_logdet_greens(K, 0.4, phi)
+        check_ld(ld, lo)
+        check_G(G, Go, tol=1e-12 * max(1.0, np.abs(Go).max()))
+
+
+@pytest.mark.parametrize("L,beta,Nt,s", [(3, 32.0, 256, 8), (3, 64.0, 512, 16), (6, 32.0, 256, 8)])
+def test_closed_form_low_temperature(fd, L, beta, Nt, s):
+    K = honeycomb_hopping(L)
+    N = K.shape[0]
+    c = np.random.default_rng(2).normal(0, 0.6, Nt)
+    phi = uniform_phi(c, N)
+    ld, G = gpu_greens(fd, K, phi, beta / Nt, s=s)
+    check_ld(ld, O.uniform_field_logdet(L, beta, c.sum()))
+    check_G(G, O.uniform_field_greens(L, beta, c.sum()))
+
+
+def test_free_field(fd):
+    L, beta, Nt = 6, 32.0, 256
+    K = honeycomb_hopping(L)
+    phi = np.zeros((Nt, K.shape[0]))
+    ld, G = gpu_greens(fd, K, phi, beta / Nt, s=8)
+    a = beta * np.abs(O.honeycomb_dispersion(L))
+    ref = float(np.sum(a + 2.0 * np.log1p(np.exp(-a))))
+    check_ld(ld, complex(ref, 0.0))
+    check_G(G, O.uniform_field_greens(L, beta, 0.0))
+
+
+def test_plain_det_workload(fd):
+    w = WORKLOADS["plain_det_L3"]
+    K, phi = w.K(), w.phi()
+    ld, G = gpu_greens(fd, K, phi, w.dk, s=w.s)
+    lo, Go = O.stabilised_logdet_greens(K, w.dk, phi)
+    check_ld(ld, lo)
+    check_G(G, Go)
+    ld2 = complex(fd.logdet(to_dev(K), to_dev(phi), w.dk, s=w.s).item())
+    check_ld(ld2, lo)
+
+
+@pytest.mark.parametrize("seg", [1, 8])
+def test_low_temperature_workload(fd, seg):
+    """L = 6 (N = 72), N_t = 256, beta = 32, s = 8: the full-size single config."""
+    w = WORKLOADS["lowT_L6"]
+    K, phi = w.K(), w.phi()
+    ld, G = gpu_greens(fd, K, phi, w.dk, s=w.s, segments=seg)
+    lo, Go = O.sporadic_logdet_greens(K, w.dk, phi, 1)
+    check_ld(ld, lo)
+    check_G(G, Go)
+    # invariants of the bipartite, traceless honeycomb K
+    assert abs(math.remainder(ld.imag - 0.5 * phi.sum(), math.pi)) < 1e-9
+    assert np.abs(np.diag(G).real - 0.5).max() < 1e-10
+
+
+def test_udv_invariants(fd):
+    import torch
+    L, Nt, beta = 3, 32, 8.0
+    K = honeycomb_hopping(L)
+    dk = beta / Nt
+    phi = sample_phi(5, Nt, 18, dk, 3.0)
+    X, D, T = fd.udv(to_dev(K), to_dev(phi), dk, s=4)
+    X, D, T = X.cpu().numpy(), D.cpu().numpy(), T.cpu().numpy()
+    assert np.abs(X.conj().T @ X - np.eye(18)).max() < 1e-13
+    assert np.all(np.diff(D) <= 0)                       # sorted by the pivoting
+    assert abs(abs(np.linalg.det(T)) - 1.0) < 1e-10
+    B = O.slice_matrices(K, dk, phi)
+    P = np.eye(18, dtype=complex)
+    for b in B:
+        P = b @ P
+    assert np.abs(X @ np.diag(D) @ T - P).max() <= 1e-12 * np.abs(P).max()
+
+
+def test_determinism_and_segments(fd):
+    w = WORKLOADS["lowT_L6"]
+    K, phi = to_dev(w.K()), to_dev(w.phi())
+    a = fd.greens(K, phi, w.dk, s=8, segments=4)
+    b = fd.greens(K, phi, w.dk, s=8, segments=4)
+    assert np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
+    assert np.array_equal(a[0].cpu().numpy(), b[0].cpu().numpy())
+
+
+def test_status_singular(fd):
+    """K = 0 and phi = pi / N_t on every site: the product is -1, M = 0."""
+    import torch
+    N, Nt = 8, 4
+    K = np.zeros((N, N))
+    phi = np.full((Nt, N), math.pi / Nt)
+    ld, G = fd.greens(to_dev(K), to_dev(phi), 0.1, s=2, check=False)
+    status = torch.empty(1, dtype=torch.int32, device=dev())
+    fd.greens(to_dev(K), to_dev(phi), 0.1, s=2, check=False, status=status)
+    code = int(status.item())
+    assert code in (fd.FD_ERR_SINGULAR, fd.FD_WARN_ILLCOND, fd.FD_ERR_NONFINITE)
+    if code < 0:
+        with pytest.raises(fd.FdError):
+            fd.greens(to_dev(K), to_dev(phi), 0.1, s=2)
+
+
+# ---------------------------------------------------------------------------
+# a6: force
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("L,Nt,beta,s,c", [
+    # s and c keep s*dk*rho(K) <= 6 and c*dk*rho(K) <= 6 (rho = 3 for the honeycomb)
+    (2, 16, 2.0, 4, 16), (2, 40, 5.0, 3, 7), (3, 48, 6.0, 8, 16), (3, 64, 32.0, 4, 4),
+])
+def test_force_vs_oracle(fd, L, Nt, beta, s, c):
+    K = honeycomb_hopping(L)
+    dk = beta / Nt
+    phi = sample_phi(7 + L, Nt, K.shape[0], dk, 3.0)
+    F, ld = fd.force(to_dev(K), to_dev(phi), dk, s=s, checkpoint=c, with_logdet=True)
+    F = F.cpu().numpy()
+    Fo = O.stabilised_force(K, dk, phi)
+    assert np.abs(F - Fo).max() <= TOL_F, np.abs(F - Fo).max()
+    lo = O.stabilised_logdet_greens(K, dk, phi)[0]
+    check_ld(complex(ld.item()), lo)
+
+
+def test_force_vs_bruteforce(fd):
+    K = honeycomb_hopping(2)
+    Nt, beta = 32, 8.0
+    dk = beta / Nt
+    phi = sample_phi(4, Nt, 8, dk, 3.0)
+    F = fd.force(to_dev(K), to_dev(phi), dk, s=4, checkpoint=8).cpu().numpy()
+    Fb = O.bruteforce_force(K, dk, phi)
+    assert np.abs(F - Fb).max() <= TOL_F
+
+
+def test_force_uniform_closed_form(fd):
+    L, beta, Nt = 6, 32.0, 256
+    K = honeycomb_hopping(L)
+    c = np.random.default_rng(4).normal(0, 0.5, Nt)
+    phi = uniform_phi(c, K.shape[0])
+    F = fd.force(to_dev(K), to_dev(phi), beta / Nt, s=8, checkpoint=16).cpu().numpy()
+    ref = O.uniform_field_force(L, beta, c.sum())
+    assert np.abs(F - ref).max() <= TOL_F
+
+
+def test_force_workload_sampled_and_fd(fd):
+    """L = 8 (N = 128), N_t = 256, beta = 32, c = 16: sampled rows against the
+    oracle, a few entries against central finite differences of log det."""
+    w = WORKLOADS["force_L8"]
+    K, phi = w.K(), w.phi()
+    Kd, pd = to_dev(K), to_dev(phi)
+    F = fd.force(Kd, pd, w.dk, s=w.s, checkpoint=w.c).cpu().numpy()
+    assert np.abs(F.imag - 0.5).max() < 1e-9
+    rows = [1, 17, 128, 256]
+    Fo = O.stabilised_force_rows(K, w.dk, phi, rows)
+    assert np.abs(F[[r - 1 for r in rows]] - Fo).max() <= TOL_F
+    h = 1e-6
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        t, x = int(rng.integers(w.Nt)), int(rng.integers(w.N))
+        pp = phi.copy(); pp[t, x] += h
+        pm = phi.copy(); pm[t, x] -= h
+        lp = complex(fd.logdet(Kd, to_dev(pp), w.dk, s=w.s).item())
+        lm = complex(fd.logdet(Kd, to_dev(pm), w.dk, s=w.s).item())
+        fdv = wrapped(lp, lm) / (2 * h)
+        assert abs(fdv.real - F[t, x].real) <= 1e-6
+        assert abs(fdv.imag - F[t, x].imag) <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# a7: batched launches
+# ---------------------------------------------------------------------------
+
+def test_batched_mixed_sizes(fd):
+    specs = [(3, 32, 2), (5, 16, 1), (2, 45, 3), (6, 64, 2), (3, 8, 1)]
+    probs, refs = [], []
+    for i, (L, Nt, seg) in enumerate(specs):
+        K = honeycomb_hopping(L)
+        dk = 0.125
+        phi = sample_phi(900 + i, Nt, K.shape[0], dk, 3.0)
+        probs.append((to_dev(K), to_dev(phi), dk))
+        refs.append(O.stabilised_logdet_greens(K, dk, phi))
+    ld, Gs = fd.greens_batched(probs, s=4, segments=2)
+    ld = ld.cpu().numpy()
+    for i, (lo, Go) in enumerate(refs):
+        check_ld(ld[i], lo)
+        check_G(Gs[i].cpu().numpy(), Go)
+    ld2, _ = fd.greens_batched(probs, s=4, segments=2, want_g=False)
+    assert np.array_equal(ld2.cpu().numpy(), ld)
+
+
+def test_batched_force(fd):
+    probs, refs = [], []
+    for i, (L, Nt) in enumerate([(2, 24), (3, 16), (2, 9)]):
+        K = honeycomb_hopping(L)
+        dk = 0.25
+        phi = sample_phi(50 + i, Nt, K.shape[0], dk, 3.0)
+        probs.append((to_dev(K), to_dev(phi), dk))
+        refs.append(O.stabilised_force(K, dk, phi))
+    Fs, _ = fd.force_batched(probs, s=4, checkpoint=8)
+    for F, Fo in zip(Fs, refs):
+        assert np.abs(F.cpu().numpy() - Fo).max() <= TOL_F
