@@ -1,0 +1,314 @@
+#!/usr/bin/env python3
+"""Throughput of the stabilised fermion determinant on one MI355X.
+
+Headline: det+G evaluations per second of the low-temperature single
+configuration (honeycomb L = 6, N = 72 sites, N_t = 256, beta = 32, U = 3,
+QR every s = 8 slices).  One step = one complete evaluation: slice
+exponential, stabilised slice chain, time-segment combines, close, log det and
+G, all on inputs already resident in HBM.
+
+Printed as one JSON line, with
+  roofline      the dominant kernel's model FLOP/s (HIP events around every
+                kernel phase inside the timed region) against FP64 MFMA peak,
+  cpu_baseline  the CPU oracle timed on a bounded sample on the host cores,
+  force         HMC force evals/s (L = 8, N = 128, N_t = 256): checkpointed
+                adjoint (c = 16) against the plain per-slice inversion (c = 1),
+  batched       256 mixed-size configurations: one launch sequence against
+                one configuration per call.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_MFMA = 78.6e12      # MI355X dense FP64 matrix, FLOP/s
+PEAK_HBM = 8.0e12             # bytes/s
+
+
+# ---------------------------------------------------------------------------
+# model FLOP counts (complex multiply-add = 8 real FLOP; LAPACK counts)
+# ---------------------------------------------------------------------------
+
+def chain_flops(N, rows, s):
+    """Slice products 4N^3 each (real E times complex X) and, per chunk of s
+    slices, pivoted QR 16/3 N^3 + explicit Q 16/3 N^3 + T update 4 N^3."""
+    return N ** 3 * (4.0 * rows + (16 / 3 + 16 / 3 + 4.0) * math.ceil(rows / s))
+
+
+def combine_flops(N):
+    """Bracket 8N^3, QR 16/3, Q 16/3, X1 Q 8N^3, T update 4N^3."""
+    return N ** 3 * (8.0 + 16 / 3 + 16 / 3 + 8.0 + 4.0)
+
+
+def close_flops(N, want_g=True):
+    """T X 8N^3, QR 16/3 N^3 and, for G, Q^H 8N^3, R^-1 4N^3, X (.) 8N^3."""
+    return N ** 3 * (8.0 + 16 / 3 + ((8.0 + 4.0 + 8.0) if want_g else 0.0))
+
+
+def det_flops(N, Nt, s, nseg):
+    bounds = [Nt * k // nseg for k in range(nseg + 1)]
+    f = sum(chain_flops(N, bounds[k + 1] - bounds[k], s) for k in range(nseg))
+    return f + (nseg - 1) * combine_flops(N) + close_flops(N) + 32.0 * N ** 3
+
+
+def force_flops(N, Nt, s, c):
+    """Prefix and suffix chains with checkpoints, then per checkpoint interval
+    one combine + close + G, and two real-by-complex products (8N^3) per
+    carried slice."""
+    nck = math.ceil(Nt / c)
+    f = 2 * chain_flops(N, Nt, s) + 2 * 32.0 * N ** 3
+    f += nck * (combine_flops(N) + close_flops(N)) + (Nt - nck) * 8.0 * N ** 3
+    return f + close_flops(N, want_g=False)
+
+
+def src_digest():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2604_02130_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, only if
+    they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except OSError:
+        return None
+    if rec.get("src_digest") != src_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+# ---------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--segments", type=int, default=0, help="time segments (0 = tuned)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the force and batched legs")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device copy of this size first (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} (WORLD_SIZE={world}) "
+              "is not supported by this single-GPU build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2604_02130_amd as fd
+    from workload import WORKLOADS, batched_mix
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(2)
+    fd.load_library()
+    dev = torch.device("cuda:0")
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # ---------------- headline: det + G of the low-temperature configuration
+    w = WORKLOADS["lowT_L6"]
+    N, Nt, s = w.N, w.Nt, w.s
+    nseg = args.segments if args.segments > 0 else 16
+    Kd = torch.from_numpy(w.K()).to(dev)
+    pd = torch.from_numpy(w.phi()).to(dev)
+    ws = fd.Workspace()
+    ld = torch.empty(2, dtype=torch.float64, device=dev)
+    G = torch.empty((N, N, 2), dtype=torch.float64, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+
+    def step():
+        fd.greens(Kd, pd, w.dk, s=s, segments=nseg, check=False, ws=ws, out=(ld, G),
+                  status=status)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done; timing {args.steps} steps", file=sys.stderr, flush=True)
+    fd.profile_start()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = fd.profile_stop()
+    st = int(status.item())
+    if st < 0:
+        raise SystemExit(f"status {st}: {fd.strerror(st)}")
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    evals_per_s = args.steps / (t1 - t0)
+
+    # dominant phase of the step and its model FLOP per launch
+    per_phase = {}
+    for name, nitems, ms in phases:
+        tot, cnt, items = per_phase.get(name, (0.0, 0, nitems))
+        per_phase[name] = (tot + ms, cnt + 1, nitems)
+    bounds = [Nt * k // nseg for k in range(nseg + 1)]
+    phase_flops = {
+        "expm": 32.0 * N ** 3,
+        "chain": sum(chain_flops(N, bounds[k + 1] - bounds[k], s) for k in range(nseg)),
+        "close": close_flops(N),
+    }
+    dom = max(per_phase, key=lambda k: per_phase[k][0])
+    dom_ms = per_phase[dom][0] / per_phase[dom][1]
+    if dom == "combine":
+        launches = per_phase[dom][1] / args.steps
+        combines_per_step = nseg - 1
+        dom_flops = combine_flops(N) * combines_per_step / launches
+    else:
+        dom_flops = phase_flops.get(dom, float("nan"))
+    achieved = dom_flops / (dom_ms * 1e-3)
+    kernel_name = f"k_{dom}"
+    roofline = {
+        "bound": "mfma",
+        "kernel": kernel_name,
+        "achieved": achieved / 1e12,
+        "peak": PEAK_FP64_MFMA / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP64_MFMA,
+        "traffic": traffic_from_profiles(kernel_name, "lowT_L6"),
+        "avg_launch_ms": dom_ms,
+        "model_flop_per_launch": dom_flops,
+        "phases_ms_per_step": {k: v[0] / args.steps for k, v in per_phase.items()},
+    }
+    step_flops = det_flops(N, Nt, s, nseg)
+
+    result = {
+        "metric": "det+G evals/s & FP64 MFMA %peak; HMC force evals/s, batched/adjoint vs plain",
+        "value": evals_per_s,
+        "unit": "det+G evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "lowT_L6: honeycomb L=6 (N=72), Nt=256, beta=32, kappa=1, U=3, "
+                        "phi~N(0, delta*U) seed 2, s=8; log det M and G per step",
+            "segments": nseg,
+            "parallelism": "single GPU",
+        },
+        "fp64_mfma_pct_peak": 100.0 * step_flops / (ms_per_step * 1e-3) / PEAK_FP64_MFMA,
+        "model_flop_per_step": step_flops,
+        "roofline": roofline,
+    }
+
+    # ---------------- CPU oracle on the host cores (bounded sample)
+    if not args.no_cpu:
+        import oracle
+        try:
+            import threadpoolctl
+            cores = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or 1
+        except Exception:
+            cores = os.cpu_count()
+        K, phi = w.K(), w.phi()
+        oracle.sporadic_logdet_greens(K, w.dk, phi, s)      # warm-up
+        n, tc0 = 0, time.perf_counter()
+        while True:
+            oracle.sporadic_logdet_greens(K, w.dk, phi, s)
+            n += 1
+            if time.perf_counter() - tc0 > 10.0:
+                break
+        dt = time.perf_counter() - tc0
+        result["cpu_baseline"] = {
+            "value": n / dt, "unit": "det+G evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} full det+G evals of the same workload (numpy/scipy stabilised "
+                      f"oracle, QR every {s} slices), {dt:.1f} s",
+        }
+        print(f"[bench] cpu oracle: {n / dt:.3f} evals/s", file=sys.stderr, flush=True)
+
+    # ---------------- force leg: checkpointed adjoint vs plain per-slice inversion
+    if not args.no_extra:
+        wf = WORKLOADS["force_L8"]
+        Kf = torch.from_numpy(wf.K()).to(dev)
+        pf = torch.from_numpy(wf.phi()).to(dev)
+        wsf = fd.Workspace()
+        out = {}
+        for label, c, reps in (("adjoint_c16", wf.c, 5), ("plain_c1", 1, 2)):
+            fd.force(Kf, pf, wf.dk, s=wf.s, checkpoint=c, check=False, ws=wsf)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            for _ in range(reps):
+                fd.force(Kf, pf, wf.dk, s=wf.s, checkpoint=c, check=False, ws=wsf)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - a) / reps
+            out[label] = {"force_evals_per_s": 1.0 / dt, "ms": dt * 1e3,
+                          "model_tflop_s": force_flops(wf.N, wf.Nt, wf.s, c) / dt / 1e12}
+            print(f"[bench] force {label}: {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
+        out["workload"] = "force_L8: honeycomb L=8 (N=128), Nt=256, beta=32, U=3, s=8"
+        out["adjoint_vs_plain"] = out["adjoint_c16"]["force_evals_per_s"] / out["plain_c1"]["force_evals_per_s"]
+        result["force"] = out
+
+        # ---------------- batched leg: 256 mixed configurations
+        mix = batched_mix()
+        cache = {}
+        probs = []
+        for wb in mix:
+            if wb.L not in cache:
+                cache[wb.L] = torch.from_numpy(wb.K()).to(dev)
+            probs.append((cache[wb.L], torch.from_numpy(wb.phi()).to(dev), wb.dk))
+        wsb = fd.Workspace()
+        seg_b = 4
+        fd.greens_batched(probs, s=8, segments=seg_b, check=False, ws=wsb)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            fd.greens_batched(probs, s=8, segments=seg_b, check=False, ws=wsb)
+        torch.cuda.synchronize()
+        dtb = (time.perf_counter() - a) / reps
+        a = time.perf_counter()
+        for (Kb, pb, dkb) in probs:
+            fd.greens(Kb, pb, dkb, s=8, segments=1, check=False, ws=wsb)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - a
+        bflops = sum(det_flops(wb.N, wb.Nt, 8, seg_b) for wb in mix)
+        result["batched"] = {
+            "workload": "256 configs, L in {3,5,6,7,8}, Nt in {32..512}, delta=0.125, U=3, s=8",
+            "batched_evals_per_s": len(mix) / dtb,
+            "plain_evals_per_s": len(mix) / dtp,
+            "batched_vs_plain": dtp / dtb,
+            "batched_ms": dtb * 1e3,
+            "fp64_mfma_pct_peak": 100.0 * bflops / dtb / PEAK_FP64_MFMA,
+        }
+        print(f"[bench] batched {dtb * 1e3:.1f} ms vs plain {dtp * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

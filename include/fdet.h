@@ -142,6 +142,15 @@ const char *fd_last_error(void);
 /* Library version string.                                                    */
 const char *fd_version(void);
 
+/* Diagnostics: after fd_profile_start, every kernel phase launched by this
+ * thread is bracketed by HIP events recorded on the call's stream.
+ * fd_profile_stop waits for those events, writes up to `max` records (phase
+ * kind: 0 exponential, 1 chain, 2 combine, 3 close, 4 force, 5 export; work
+ * items in the launch; milliseconds) and returns the number of phases seen.
+ * Any output pointer may be NULL.                                            */
+int fd_profile_start(void);
+int fd_profile_stop(int32_t max, int32_t *kinds, int32_t *nitems, float *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,8 +34,10 @@ MAX_N = 512
 SYMBOLS = (
     "fd_workspace_bytes", "fd_slice_exponential", "fd_logdet", "fd_greens", "fd_force",
     "fd_udv", "fd_logdet_batched", "fd_greens_batched", "fd_force_batched",
-    "fd_strerror", "fd_last_error", "fd_version",
+    "fd_strerror", "fd_last_error", "fd_version", "fd_profile_start", "fd_profile_stop",
 )
+
+PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export"}
 
 
 class FdProblem(ctypes.Structure):
@@ -88,8 +90,28 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fd_last_error.restype = ctypes.c_char_p
     lib.fd_version.argtypes = []
     lib.fd_version.restype = ctypes.c_char_p
+    lib.fd_profile_start.argtypes = []
+    lib.fd_profile_start.restype = ctypes.c_int
+    lib.fd_profile_stop.argtypes = [i32, vp, vp, vp]
+    lib.fd_profile_stop.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def profile_start():
+    """Start timing every kernel phase of this thread's calls with HIP events."""
+    _check(load_library().fd_profile_start())
+
+
+def profile_stop(max_records: int = 65536):
+    """Stop timing; returns a list of (phase name, work items, milliseconds)."""
+    lib = load_library()
+    kinds = (ctypes.c_int32 * max_records)()
+    nitems = (ctypes.c_int32 * max_records)()
+    ms = (ctypes.c_float * max_records)()
+    n = lib.fd_profile_stop(max_records, kinds, nitems, ms)
+    n = min(n, max_records)
+    return [(PHASE_NAMES.get(kinds[i], str(kinds[i])), nitems[i], float(ms[i])) for i in range(n)]
 
 
 def version() -> str:

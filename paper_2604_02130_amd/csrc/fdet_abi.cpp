@@ -12,8 +12,8 @@
 #include "../../include/fdet.h"
 #include "fdet_plan.h"
 
-extern "C" hipError_t fdet_launch_items(int maxn, const fdet::Prob* probs, const fdet::Item* items,
-                                        int nitems, hipStream_t st);
+extern "C" hipError_t fdet_launch_items(int maxn, int kind, const fdet::Prob* probs,
+                                        const fdet::Item* items, int nitems, hipStream_t st);
 extern "C" hipError_t fdet_launch_init_status(const fdet::Prob* probs, int nprob, hipStream_t st);
 
 namespace {
@@ -23,6 +23,15 @@ using fdet::Prob;
 using fdet::Udv;
 
 thread_local std::string g_last_error;
+
+// Phase timing with HIP events (diagnostics; off unless fd_profile_start).
+struct PhaseRec {
+  int kind;
+  int nitems;
+  hipEvent_t a, b;
+};
+thread_local bool g_prof_on = false;
+thread_local std::vector<PhaseRec> g_prof;
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
@@ -274,8 +283,19 @@ int execute(Plan& pl, char* ws, hipStream_t st) {
   e = fdet_launch_init_status(dprobs, (int)pl.probs.size(), st);
   if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
   for (size_t k = 0; k < pl.phases.size(); ++k) {
-    e = fdet_launch_items(pl.maxN, dprobs, ditems + first[k], (int)pl.phases[k].size(), st);
+    const int kind = pl.phases[k].front().kind;
+    PhaseRec rec{kind, (int)pl.phases[k].size(), nullptr, nullptr};
+    if (g_prof_on) {
+      if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess)
+        return fail(FD_ERR_HIP, "event creation failed");
+      hipEventRecord(rec.a, st);
+    }
+    e = fdet_launch_items(pl.maxN, kind, dprobs, ditems + first[k], (int)pl.phases[k].size(), st);
     if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+    if (g_prof_on) {
+      hipEventRecord(rec.b, st);
+      g_prof.push_back(rec);
+    }
   }
   return FD_OK;
 }
@@ -446,5 +466,34 @@ const char* fd_strerror(int code) {
 const char* fd_last_error(void) { return g_last_error.c_str(); }
 
 const char* fd_version(void) { return "fdet 0.1.0 (gfx950)"; }
+
+int fd_profile_start(void) {
+  for (auto& r : g_prof) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  g_prof_on = true;
+  return FD_OK;
+}
+
+int fd_profile_stop(int32_t max, int32_t* kinds, int32_t* nitems, float* ms) {
+  g_prof_on = false;
+  int n = 0;
+  for (auto& r : g_prof) {
+    if (n < max) {
+      float t = -1.0f;
+      if (hipEventSynchronize(r.b) == hipSuccess) hipEventElapsedTime(&t, r.a, r.b);
+      if (kinds) kinds[n] = r.kind;
+      if (nitems) nitems[n] = r.nitems;
+      if (ms) ms[n] = t;
+    }
+    ++n;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  return n;
+}
 
 }  // extern "C"

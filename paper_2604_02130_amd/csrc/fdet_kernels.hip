@@ -597,27 +597,25 @@ __device__ void do_export(const Prob& P, const Item& it, Smem<MAXN>&) {
     if (P.outD) P.outD[i] = it.a.D[i];
 }
 
-template <int MAXN>
-__global__ __launch_bounds__(WG) void k_items(const Prob* __restrict__ probs,
-                                              const Item* __restrict__ items) {
-  __shared__ Smem<MAXN> S;
-  const Item it = items[blockIdx.x];
-  const Prob P = probs[it.prob];
-  switch (it.kind) {
-    case IK_EXPM: do_expm<MAXN>(P, it, S); break;
-    case IK_CHAIN: do_chain<MAXN>(P, it, S); break;
-    case IK_COMBINE: do_combine<MAXN>(P, it, S); break;
-    case IK_CLOSE: {
-      const size_t cd = cmat_doubles(P.Np);
-      CMat W = cmat_at(it.scr, P.Np), Yb = cmat_at(it.scr + cd, P.Np);
-      do_close<MAXN>(P, it.a, W, Yb, W, (it.flags & IF_WANT_G) != 0, true, S);
-      break;
-    }
-    case IK_FORCE: do_force<MAXN>(P, it, S); break;
-    case IK_EXPORT: do_export<MAXN>(P, it, S); break;
-    default: break;
+// One kernel per work-item kind, so that profiles and timings name the phase.
+#define FDET_KERNEL(NAME, BODY)                                                        \
+  template <int MAXN>                                                                  \
+  __global__ __launch_bounds__(WG) void NAME(const Prob* __restrict__ probs,           \
+                                             const Item* __restrict__ items) {         \
+    __shared__ Smem<MAXN> S;                                                           \
+    const Item it = items[blockIdx.x];                                                 \
+    const Prob P = probs[it.prob];                                                     \
+    BODY;                                                                              \
   }
-}
+
+FDET_KERNEL(k_expm, do_expm<MAXN>(P, it, S))
+FDET_KERNEL(k_chain, do_chain<MAXN>(P, it, S))
+FDET_KERNEL(k_combine, do_combine<MAXN>(P, it, S))
+FDET_KERNEL(k_close, do_close<MAXN>(P, it.a, cmat_at(it.scr, P.Np),
+                                    cmat_at(it.scr + cmat_doubles(P.Np), P.Np),
+                                    cmat_at(it.scr, P.Np), (it.flags & IF_WANT_G) != 0, true, S))
+FDET_KERNEL(k_force, do_force<MAXN>(P, it, S))
+FDET_KERNEL(k_export, do_export<MAXN>(P, it, S))
 
 __global__ void k_init_status(const Prob* __restrict__ probs, int nprob) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -627,14 +625,28 @@ __global__ void k_init_status(const Prob* __restrict__ probs, int nprob) {
 }  // namespace fdet
 
 // Launchers used by the host planner.
-extern "C" hipError_t fdet_launch_items(int maxn, const fdet::Prob* probs, const fdet::Item* items,
-                                        int nitems, hipStream_t st) {
-  if (nitems <= 0) return hipSuccess;
-  if (maxn <= 128)
-    hipLaunchKernelGGL(fdet::k_items<128>, dim3(nitems), dim3(fdet::WG), 0, st, probs, items);
-  else
-    hipLaunchKernelGGL(fdet::k_items<512>, dim3(nitems), dim3(fdet::WG), 0, st, probs, items);
+template <int MAXN>
+static hipError_t launch_kind(int kind, const fdet::Prob* probs, const fdet::Item* items, int n,
+                              hipStream_t st) {
+  using namespace fdet;
+  const dim3 g(n), b(WG);
+  switch (kind) {
+    case IK_EXPM: hipLaunchKernelGGL(k_expm<MAXN>, g, b, 0, st, probs, items); break;
+    case IK_CHAIN: hipLaunchKernelGGL(k_chain<MAXN>, g, b, 0, st, probs, items); break;
+    case IK_COMBINE: hipLaunchKernelGGL(k_combine<MAXN>, g, b, 0, st, probs, items); break;
+    case IK_CLOSE: hipLaunchKernelGGL(k_close<MAXN>, g, b, 0, st, probs, items); break;
+    case IK_FORCE: hipLaunchKernelGGL(k_force<MAXN>, g, b, 0, st, probs, items); break;
+    case IK_EXPORT: hipLaunchKernelGGL(k_export<MAXN>, g, b, 0, st, probs, items); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+
+extern "C" hipError_t fdet_launch_items(int maxn, int kind, const fdet::Prob* probs,
+                                        const fdet::Item* items, int nitems, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  if (maxn <= 128) return launch_kind<128>(kind, probs, items, nitems, st);
+  return launch_kind<512>(kind, probs, items, nitems, st);
 }
 
 extern "C" hipError_t fdet_launch_init_status(const fdet::Prob* probs, int nprob, hipStream_t st) {
