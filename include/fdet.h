@@ -116,8 +116,10 @@ int fd_force(const fd_problem *p, const fd_options *o, double *logdet, double *f
              double *force_im, void *ws, size_t ws_bytes, int32_t *status, void *stream);
 
 /* The stabilised factorisation B_{N_t}...B_1 = X diag(D) T (eq.
- * def_matrix_as_product with T = Y^{-1}): X unitary, D >= 0 sorted by the
- * pivoting, |det T| = 1.  X, T: N*N complex row-major; D: N doubles.         */
+ * def_matrix_as_product with T = Y^{-1}): X unitary, D >= 0 in decreasing
+ * order up to the conditioning of one stabilisation interval (the columns are
+ * pre-sorted before each QR), |det T| = 1.  X, T: N*N complex row-major;
+ * D: N doubles.                                                              */
 int fd_udv(const fd_problem *p, const fd_options *o, double *X, double *D, double *T,
            void *ws, size_t ws_bytes, int32_t *status, void *stream);
 

@@ -243,10 +243,18 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
         c.scr = cs[k];
         chain.push_back(c);
       }
+      // checkpoint k (row k*c) carries G~ forward over the first half of the
+      // gap to the next checkpoint and backward over the second half of the
+      // gap from the previous one (cyclically for k = 0), so no G~ is carried
+      // across more than about c/2 slices
+      const int last_gap = q.Nt - (nc - 1) * o.c;
       for (int k = 0; k < nc; ++k) {
         Item f = blank_item(fdet::IK_FORCE, i);
+        const int gap_fwd = (k + 1 < nc) ? o.c : last_gap;
+        const int gap_bwd = (k > 0) ? o.c : last_gap;
         f.t0 = k * o.c;
-        f.t1 = std::min((k + 1) * o.c, q.Nt);
+        f.t1 = f.t0 + (gap_fwd + 1) / 2;
+        f.nb = (nc == 1) ? q.Nt - (q.Nt + 1) / 2 : gap_bwd / 2;
         f.a = make_udv(pre ? (double*)((char*)pre + ub * k) : nullptr, Np);
         f.b = make_udv(suf ? (double*)((char*)suf + ub * k) : nullptr, Np);
         f.scr = fs[k];

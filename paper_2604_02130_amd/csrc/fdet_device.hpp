@@ -55,6 +55,13 @@ struct Smem {
   double candn[NWAVE];
   int candi[NWAVE];
   double red[4 * NWAVE];
+  double gck[32];       // per-lane-group pivot candidates (register QR)
+  double gcn[32];
+  int gcc[32];
+  double ubr[MAXN];     // reflector broadcast buffer (register QR)
+  double ubi[MAXN];
+  double rdr[MAXN];     // diagonal of R by position (register QR)
+  double rdi[MAXN];
   double a0r, a0i;
   int nref;
   int flag;

@@ -16,10 +16,56 @@
 //   IK_EXPORT   copy a UDV triple out in the caller's layout.
 #include "fdet_device.hpp"
 #include "fdet_plan.h"
+#include "fdet_regqr.hpp"
 
 namespace fdet {
 
 constexpr double kPi = 3.14159265358979323846;
+
+// Size classes: N <= NC.  Classes up to 128 keep the matrix being factorised
+// in registers and stage products through LDS (fdet_regqr.hpp); the 512
+// class works on device memory (fdet_device.hpp).
+template <int NC>
+__device__ void qr_factor(CMat W, int N, const double* keys, SmemC<NC>& S) {
+  if constexpr (NC <= 128) rq_qrp<NC>(W, N, keys, S);
+  else wg_qrp(W, N, keys, S);
+}
+
+template <int NC>
+__device__ void qr_form_q(CMat W, int N, CMat Q, SmemC<NC>& S) {
+  if constexpr (NC <= 128) {
+    rq_form_q<NC>(N, Q, S);
+    __syncthreads();
+  } else {
+    wg_form_q(W, N, Q, S);
+  }
+}
+
+// C = A B with A, B real or complex (AC, BC)
+template <int NC, bool AC, bool BC, class LA, class LB, class ST>
+__device__ void mm(int Np, LA la, LB lb, ST st, SmemC<NC>& S) {
+  if constexpr (NC <= 128) {
+    gemm_lds<NC, AC, BC>(Np, la, lb, st, S.big);
+  } else {
+    if constexpr (AC && BC) gemm_cc(Np, la, lb, st);
+    else if constexpr (AC) gemm_cr(Np, la, lb, st);
+    else if constexpr (BC) gemm_rc(Np, la, lb, st);
+    else gemm_rr(Np, la, lb, st);
+  }
+}
+
+// Y <- R^{-1} Q^H Y for the factor in W
+template <int NC>
+__device__ void qr_solve(CMat W, int N, CMat Y, SmemC<NC>& S) {
+  if constexpr (NC <= 128) {
+    rq_solve<NC>(W, N, Y, S);
+  } else {
+    wg_apply_qh(W, N, Y, S);
+    __syncthreads();
+    wg_backsolve<512>(W, N, Y);
+  }
+  __syncthreads();
+}
 
 __device__ void status_merge(int32_t* st, int32_t code) {
   if (code == 0 || st == nullptr) return;
@@ -33,8 +79,8 @@ __device__ void status_merge(int32_t* st, int32_t code) {
   }
 }
 
-template <int MAXN>
-__device__ void load_phases(const Prob& P, int t, Smem<MAXN>& S) {
+template <int NC>
+__device__ void load_phases(const Prob& P, int t, SmemC<NC>& S) {
   for (int x = threadIdx.x; x < P.N; x += WG) {
     double sv, cv;
     sincos(P.phi[(size_t)t * P.N + x], &sv, &cv);
@@ -89,11 +135,11 @@ __device__ double block_max(double v, double* red) {
 // ---------------------------------------------------------------------------
 
 // out = E diag(e^{i phi_t}) in     (forward slice B_t)
-template <int MAXN>
-__device__ void slice_forward(const Prob& P, CMat in, CMat out, Smem<MAXN>& S) {
+template <int NC>
+__device__ void slice_forward(const Prob& P, CMat in, CMat out, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const double* E = P.E;
-  gemm_rc(
+  mm<NC, false, true>(
       Np, [&](int i, int k) { return (i < N && k < N) ? E[(size_t)k * Np + i] : 0.0; },
       [&](int k, int j, double& br, double& bi) {
         if (k < N && j < N) {
@@ -106,15 +152,15 @@ __device__ void slice_forward(const Prob& P, CMat in, CMat out, Smem<MAXN>& S) {
       },
       [&](int i, int j, double cr, double ci) {
         if (i < N && j < N) { out.r(i, j) = cr; out.m(i, j) = ci; }
-      });
+      }, S);
 }
 
 // out = diag(e^{-i phi_t}) E in    (B_t^H for real symmetric E)
-template <int MAXN>
-__device__ void slice_adjoint(const Prob& P, CMat in, CMat out, Smem<MAXN>& S) {
+template <int NC>
+__device__ void slice_adjoint(const Prob& P, CMat in, CMat out, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const double* E = P.E;
-  gemm_rc(
+  mm<NC, false, true>(
       Np, [&](int i, int k) { return (i < N && k < N) ? E[(size_t)k * Np + i] : 0.0; },
       [&](int k, int j, double& br, double& bi) {
         if (k < N && j < N) { br = in.r(k, j); bi = in.m(k, j); }
@@ -126,14 +172,14 @@ __device__ void slice_adjoint(const Prob& P, CMat in, CMat out, Smem<MAXN>& S) {
           out.r(i, j) = c * cr + s * ci;
           out.m(i, j) = c * ci - s * cr;
         }
-      });
+      }, S);
 }
 
 // After wg_qrp on W with keys: D_new (S.v2) = |R_ii| keys_i and the row scale
 // S.v3 = 1 / D_new used to build T' = D_new^{-1} R diag(keys) (unit-modulus
 // diagonal).  Returns nothing; flags a zero or non-finite scale in S.flag.
-template <int MAXN>
-__device__ void udv_scales(CMat W, int N, Smem<MAXN>& S) {
+template <int NC>
+__device__ void udv_scales(CMat W, int N, SmemC<NC>& S) {
   for (int i = threadIdx.x; i < N; i += WG) {
     const double a = hypot(W.r(i, i), W.m(i, i));
     const double d = a * S.csp[i];
@@ -144,9 +190,9 @@ __device__ void udv_scales(CMat W, int N, Smem<MAXN>& S) {
 }
 
 // To = T' Pi^T T2op with T'(i,k) = R(i,k) keys_k / D_new_i for k >= i.
-template <int MAXN, class LT2>
-__device__ void udv_new_t(CMat W, int N, int Np, LT2 t2, CMat To, Smem<MAXN>& S) {
-  gemm_cc(
+template <int NC, class LT2>
+__device__ void udv_new_t(CMat W, int N, int Np, LT2 t2, CMat To, SmemC<NC>& S) {
+  mm<NC, true, true>(
       Np,
       [&](int i, int k, double& ar, double& ai) {
         if (i < N && k < N && k >= i) {
@@ -163,40 +209,40 @@ __device__ void udv_new_t(CMat W, int N, int Np, LT2 t2, CMat To, Smem<MAXN>& S)
       },
       [&](int i, int j, double cr, double ci) {
         if (i < N && j < N) { To.r(i, j) = cr; To.m(i, j) = ci; }
-      });
+      }, S);
 }
 
 // ---------------------------------------------------------------------------
 // IK_CHAIN
 // ---------------------------------------------------------------------------
-template <int MAXN>
-__device__ void do_chain(const Prob& P, const Item& it, Smem<MAXN>& S);
+template <int NC>
+__device__ void do_chain(const Prob& P, const Item& it, SmemC<NC>& S);
 
-template <int MAXN>
+template <int NC>
 __device__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
-                         bool user_out, Smem<MAXN>& S);
+                         bool user_out, SmemC<NC>& S);
 
-template <int MAXN>
+template <int NC>
 __device__ void chain_chunk(const Prob& P, const Item& it, CMat X, CMat& Tc, CMat& Tt, double* D,
-                            CMat W, CMat Y2, int tfirst, int ns, bool adj, Smem<MAXN>& S) {
+                            CMat W, CMat Y2, int tfirst, int ns, bool adj, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   CMat src = X;
   CMat dst = (ns & 1) ? W : Y2;
   for (int q = 0; q < ns; ++q) {
     const int t = adj ? tfirst - q : tfirst + q;
-    load_phases(P, t, S);
+    load_phases<NC>(P, t, S);
     __syncthreads();
-    if (adj) slice_adjoint(P, src, dst, S);
-    else slice_forward(P, src, dst, S);
+    if (adj) slice_adjoint<NC>(P, src, dst, S);
+    else slice_forward<NC>(P, src, dst, S);
     __syncthreads();
     src = dst;
     dst = (dst.re == W.re) ? Y2 : W;
   }
-  wg_qrp<MAXN>(W, N, D, S);
-  udv_scales(W, N, S);
+  qr_factor<NC>(W, N, D, S);
+  udv_scales<NC>(W, N, S);
   __syncthreads();
-  wg_form_q<MAXN>(W, N, X, S);
-  udv_new_t<MAXN>(W, N, Np,
+  qr_form_q<NC>(W, N, X, S);
+  udv_new_t<NC>(W, N, Np,
                   [&](int r, int j, double& br, double& bi) { br = Tc.r(r, j); bi = Tc.m(r, j); },
                   Tt, S);
   __syncthreads();
@@ -213,8 +259,8 @@ __device__ void save_ckpt(double* dst, CMat X, CMat T, const double* D, int N, i
   for (int i = threadIdx.x; i < N; i += WG) Dc[i] = D[i];
 }
 
-template <int MAXN>
-__device__ void do_chain(const Prob& P, const Item& it, Smem<MAXN>& S) {
+template <int NC>
+__device__ void do_chain(const Prob& P, const Item& it, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const size_t cd = cmat_doubles(Np);
   CMat X = cmat_at(it.a.X, Np), T = cmat_at(it.a.T, Np);
@@ -241,9 +287,9 @@ __device__ void do_chain(const Prob& P, const Item& it, Smem<MAXN>& S) {
     if (ckpt && !adj) save_ckpt(it.ck + (size_t)kseg * it.ckstride, X, Tc, D, N, Np);
     if (ckpt && !adj) __syncthreads();
     if (!adj) {
-      for (int t = r0; t < r1; t += s) chain_chunk(P, it, X, Tc, Tt, D, W, Y2, t, min(s, r1 - t), false, S);
+      for (int t = r0; t < r1; t += s) chain_chunk<NC>(P, it, X, Tc, Tt, D, W, Y2, t, min(s, r1 - t), false, S);
     } else {
-      for (int t = r1 - 1; t >= r0; t -= s) chain_chunk(P, it, X, Tc, Tt, D, W, Y2, t, min(s, t - r0 + 1), true, S);
+      for (int t = r1 - 1; t >= r0; t -= s) chain_chunk<NC>(P, it, X, Tc, Tt, D, W, Y2, t, min(s, t - r0 + 1), true, S);
     }
     if (ckpt && adj) { save_ckpt(it.ck + (size_t)kseg * it.ckstride, X, Tc, D, N, Np); __syncthreads(); }
   }
@@ -254,7 +300,7 @@ __device__ void do_chain(const Prob& P, const Item& it, Smem<MAXN>& S) {
   if (threadIdx.x == 0 && S.flag) status_merge(P.status, -4);
   if (it.flags & IF_CLOSE_AFTER) {
     Udv U = it.a;
-    do_close<MAXN>(P, U, W, Y2, Tn, false, true, S);
+    do_close<NC>(P, U, W, Y2, Tn, false, true, S);
   }
 }
 
@@ -264,9 +310,9 @@ __device__ void do_chain(const Prob& P, const Item& it, Smem<MAXN>& S) {
 // second operand is given by the UDV (Xs, Ds, Ts) of its adjoint, i.e.
 // X2 = Ts^H, D2 = Ds, T2 = Xs^H.
 // ---------------------------------------------------------------------------
-template <int MAXN, bool B_ADJ>
+template <int NC, bool B_ADJ>
 __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMat Xo, CMat To,
-                             double* Do, Smem<MAXN>& S) {
+                             double* Do, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   CMat X1 = cmat_at(A1.X, Np), T1 = cmat_at(A1.T, Np);
   CMat X2 = cmat_at(A2.X, Np), T2 = cmat_at(A2.T, Np);
@@ -274,7 +320,7 @@ __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMa
   for (int i = threadIdx.x; i < N; i += WG) S.v1[i] = D1[i];
   __syncthreads();
   // bracket D1 (T1 X2): its column scale D2 is left to the pivoted QR keys
-  gemm_cc(
+  mm<NC, true, true>(
       Np,
       [&](int i, int k, double& ar, double& ai) {
         if (i < N && k < N) { ar = T1.r(i, k); ai = T1.m(i, k); }
@@ -290,14 +336,14 @@ __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMa
       },
       [&](int i, int j, double cr, double ci) {
         if (i < N && j < N) { W.r(i, j) = S.v1[i] * cr; W.m(i, j) = S.v1[i] * ci; }
-      });
+      }, S);
   __syncthreads();
-  wg_qrp<MAXN>(W, N, A2.D, S);
-  udv_scales(W, N, S);
+  qr_factor<NC>(W, N, A2.D, S);
+  udv_scales<NC>(W, N, S);
   __syncthreads();
-  wg_form_q<MAXN>(W, N, Qb, S);
+  qr_form_q<NC>(W, N, Qb, S);
   // X = X1 Q
-  gemm_cc(
+  mm<NC, true, true>(
       Np,
       [&](int i, int k, double& ar, double& ai) {
         if (i < N && k < N) { ar = X1.r(i, k); ai = X1.m(i, k); }
@@ -309,9 +355,9 @@ __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMa
       },
       [&](int i, int j, double cr, double ci) {
         if (i < N && j < N) { Xo.r(i, j) = cr; Xo.m(i, j) = ci; }
-      });
+      }, S);
   // T = T' Pi^T T2
-  udv_new_t<MAXN>(W, N, Np,
+  udv_new_t<NC>(W, N, Np,
                   [&](int r, int j, double& br, double& bi) {
                     if (B_ADJ) { br = X2.r(j, r); bi = -X2.m(j, r); }   // (Xs^H)(r,j)
                     else { br = T2.r(r, j); bi = T2.m(r, j); }
@@ -322,8 +368,8 @@ __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMa
   __syncthreads();
 }
 
-template <int MAXN>
-__device__ void do_combine(const Prob& P, const Item& it, Smem<MAXN>& S) {
+template <int NC>
+__device__ void do_combine(const Prob& P, const Item& it, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const size_t cd = cmat_doubles(Np);
   CMat W = cmat_at(it.scr, Np), Qb = cmat_at(it.scr + cd, Np);
@@ -331,7 +377,7 @@ __device__ void do_combine(const Prob& P, const Item& it, Smem<MAXN>& S) {
   double* Do = it.scr + 4 * cd;
   if (threadIdx.x == 0) S.flag = 0;
   // later segment (b) on the left, earlier (a) on the right; result into a
-  combine_core<MAXN, false>(P, it.b, it.a, W, Qb, Xo, To, Do, S);
+  combine_core<NC, false>(P, it.b, it.a, W, Qb, Xo, To, Do, S);
   copy_cmat(cmat_at(it.a.X, Np), Xo, N);
   copy_cmat(cmat_at(it.a.T, Np), To, N);
   for (int i = threadIdx.x; i < N; i += WG) it.a.D[i] = Do[i];
@@ -348,9 +394,9 @@ __device__ void do_combine(const Prob& P, const Item& it, Smem<MAXN>& S) {
 //   G = X Pi R^{-1} Q^H D_b^{-1} X^H.
 // This is Sec. 7 steps 4-6 with the rows of 1 + D T X divided by D_b first.
 // ---------------------------------------------------------------------------
-template <int MAXN>
+template <int NC>
 __device__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
-                         bool user_out, Smem<MAXN>& S) {
+                         bool user_out, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   CMat X = cmat_at(U.X, Np), T = cmat_at(U.T, Np);
   bool bad = false;
@@ -361,7 +407,7 @@ __device__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool 
     S.v2[i] = d < 1.0 ? d : 1.0;
   }
   __syncthreads();
-  gemm_cc(
+  mm<NC, true, true>(
       Np,
       [&](int i, int k, double& ar, double& ai) {
         if (i < N && k < N) { ar = T.r(i, k); ai = T.m(i, k); }
@@ -376,9 +422,9 @@ __device__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool 
           W.r(i, j) = S.v2[i] * cr + (i == j ? 1.0 / S.v1[i] : 0.0);
           W.m(i, j) = S.v2[i] * ci;
         }
-      });
+      }, S);
   __syncthreads();
-  wg_qrp<MAXN>(W, N, nullptr, S);
+  qr_factor<NC>(W, N, nullptr, S);
   // log det
   double lr = 0.0, li = 0.0, amin = INFINITY, amax = 0.0;
   for (int i = threadIdx.x; i < N; i += WG) {
@@ -426,13 +472,10 @@ __device__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool 
   }
   for (int r = threadIdx.x; r < N; r += WG) S.pinv[S.piv[r]] = r;
   __syncthreads();
-  wg_apply_qh<MAXN>(W, N, Yb, S);
-  __syncthreads();
-  wg_backsolve<MAXN>(W, N, Yb);
-  __syncthreads();
+  qr_solve<NC>(W, N, Yb, S);
   // G = X Pi Z: row a of (Pi Z) is row pinv[a] of Z
   double* Gu = P.G;
-  gemm_cc(
+  mm<NC, true, true>(
       Np,
       [&](int i, int k, double& ar, double& ai) {
         if (i < N && k < N) { ar = X.r(i, k); ai = X.m(i, k); }
@@ -452,15 +495,15 @@ __device__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool 
             Gint.m(i, j) = ci;
           }
         }
-      });
+      }, S);
   __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
 // IK_FORCE
 // ---------------------------------------------------------------------------
-template <int MAXN>
-__device__ void do_force(const Prob& P, const Item& it, Smem<MAXN>& S) {
+template <int NC>
+__device__ void do_force(const Prob& P, const Item& it, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const size_t cd = cmat_doubles(Np);
   CMat W = cmat_at(it.scr, Np), Qb = cmat_at(it.scr + cd, Np);
@@ -468,23 +511,29 @@ __device__ void do_force(const Prob& P, const Item& it, Smem<MAXN>& S) {
   double* Dc = it.scr + 4 * cd;
   if (threadIdx.x == 0) S.flag = 0;
   // G~ at the first slice of the interval: (1 + P_k S_k)^{-1}
-  combine_core<MAXN, true>(P, it.a, it.b, W, Qb, Xc, Tc, Dc, S);
+  combine_core<NC, true>(P, it.a, it.b, W, Qb, Xc, Tc, Dc, S);
   Udv U;
   U.X = Xc.re; U.T = Tc.re; U.D = Dc;
-  do_close<MAXN>(P, U, W, Qb, W, true, false, S);
-  CMat G = W, Y = Qb;
+  do_close<NC>(P, U, W, Qb, W, true, false, S);
+  // keep G~ of the checkpoint for the backward direction
+  copy_cmat(Tc, W, N);
   const double* E = P.E;
   const double* Ei = P.Einv;
-  for (int t = it.t0; t < it.t1; ++t) {
+  auto write_row = [&](CMat G, int t) {
     for (int x = threadIdx.x; x < N; x += WG) {
       P.force[(size_t)t * N + x] = G.m(x, x);
       if (P.force_im) P.force_im[(size_t)t * N + x] = 1.0 - G.r(x, x);
     }
+  };
+  // forward: G~ of row t+1 = B_t G~ B_t^{-1}, B_t = E diag(e^{i phi_t})
+  CMat G = W, Y = Qb;
+  for (int t = it.t0; t < it.t1; ++t) {
+    write_row(G, t);
     if (t + 1 >= it.t1) break;
-    load_phases(P, t, S);
+    load_phases<NC>(P, t, S);
     __syncthreads();
     // Y = E diag(e^{i phi}) G diag(e^{-i phi})
-    gemm_rc(
+    mm<NC, false, true>(
         Np, [&](int i, int k) { return (i < N && k < N) ? E[(size_t)k * Np + i] : 0.0; },
         [&](int k, int j, double& br, double& bi) {
           if (k < N && j < N) {
@@ -500,10 +549,10 @@ __device__ void do_force(const Prob& P, const Item& it, Smem<MAXN>& S) {
         },
         [&](int i, int j, double cr, double ci) {
           if (i < N && j < N) { Y.r(i, j) = cr; Y.m(i, j) = ci; }
-        });
+        }, S);
     __syncthreads();
     // G = Y E^{-1}
-    gemm_cr(
+    mm<NC, true, false>(
         Np,
         [&](int i, int k, double& ar, double& ai) {
           if (i < N && k < N) { ar = Y.r(i, k); ai = Y.m(i, k); }
@@ -512,8 +561,47 @@ __device__ void do_force(const Prob& P, const Item& it, Smem<MAXN>& S) {
         [&](int k, int j) { return (k < N && j < N) ? Ei[(size_t)j * Np + k] : 0.0; },
         [&](int i, int j, double cr, double ci) {
           if (i < N && j < N) { G.r(i, j) = cr; G.m(i, j) = ci; }
-        });
+        }, S);
     __syncthreads();
+  }
+  // backward: G~ of row t = B_t^{-1} G~ of row t+1 B_t (rows mod N_t)
+  G = Tc;
+  Y = Xc;
+  for (int b = 1; b <= it.nb; ++b) {
+    int t = it.t0 - b;
+    if (t < 0) t += P.Nt;
+    load_phases<NC>(P, t, S);
+    __syncthreads();
+    // Y = E^{-1} G
+    mm<NC, false, true>(
+        Np, [&](int i, int k) { return (i < N && k < N) ? Ei[(size_t)k * Np + i] : 0.0; },
+        [&](int k, int j, double& br, double& bi) {
+          if (k < N && j < N) { br = G.r(k, j); bi = G.m(k, j); }
+          else { br = 0.0; bi = 0.0; }
+        },
+        [&](int i, int j, double cr, double ci) {
+          if (i < N && j < N) { Y.r(i, j) = cr; Y.m(i, j) = ci; }
+        }, S);
+    __syncthreads();
+    // G = diag(e^{-i phi}) (Y E) diag(e^{i phi})
+    mm<NC, true, false>(
+        Np,
+        [&](int i, int k, double& ar, double& ai) {
+          if (i < N && k < N) { ar = Y.r(i, k); ai = Y.m(i, k); }
+          else { ar = 0.0; ai = 0.0; }
+        },
+        [&](int k, int j) { return (k < N && j < N) ? E[(size_t)j * Np + k] : 0.0; },
+        [&](int i, int j, double cr, double ci) {
+          if (i < N && j < N) {
+            // e^{i(phi_j - phi_i)}
+            const double c = S.phr[j] * S.phr[i] + S.phi_[j] * S.phi_[i];
+            const double s = S.phi_[j] * S.phr[i] - S.phr[j] * S.phi_[i];
+            G.r(i, j) = c * cr - s * ci;
+            G.m(i, j) = s * cr + c * ci;
+          }
+        }, S);
+    __syncthreads();
+    write_row(G, t);
   }
   if (threadIdx.x == 0 && S.flag) status_merge(P.status, -4);
 }
@@ -522,8 +610,8 @@ __device__ void do_force(const Prob& P, const Item& it, Smem<MAXN>& S) {
 // IK_EXPM: exp(sign dk K) = (Taylor_16(A / 2^q))^(2^q), A = sign dk K,
 // q chosen so that |A / 2^q|_1 <= 1/2 (truncation below 1e-19).
 // ---------------------------------------------------------------------------
-template <int MAXN>
-__device__ void do_expm(const Prob& P, const Item& it, Smem<MAXN>& S) {
+template <int NC>
+__device__ void do_expm(const Prob& P, const Item& it, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const double* K = P.K;
   double* B0 = it.scr;
@@ -551,22 +639,22 @@ __device__ void do_expm(const Prob& P, const Item& it, Smem<MAXN>& S) {
   double* nxt = B1;
   for (int k = 16; k >= 1; --k) {
     const double f = a / (double)k;
-    gemm_rr(
+    mm<NC, false, false>(
         Np, [&](int i, int kk) { return (i < N && kk < N) ? K[(size_t)i * N + kk] : 0.0; },
         [&](int kk, int j) { return (kk < N && j < N) ? cur[(size_t)j * Np + kk] : 0.0; },
         [&](int i, int j, double c) {
           if (i < N && j < N) nxt[(size_t)j * Np + i] = f * c + (i == j ? 1.0 : 0.0);
-        });
+        }, S);
     __syncthreads();
     double* t = cur; cur = nxt; nxt = t;
   }
   for (int r = 0; r < q; ++r) {
-    gemm_rr(
+    mm<NC, false, false>(
         Np, [&](int i, int kk) { return (i < N && kk < N) ? cur[(size_t)kk * Np + i] : 0.0; },
         [&](int kk, int j) { return (kk < N && j < N) ? cur[(size_t)j * Np + kk] : 0.0; },
         [&](int i, int j, double c) {
           if (i < N && j < N) nxt[(size_t)j * Np + i] = c;
-        });
+        }, S);
     __syncthreads();
     double* t = cur; cur = nxt; nxt = t;
   }
@@ -584,8 +672,8 @@ __device__ void do_expm(const Prob& P, const Item& it, Smem<MAXN>& S) {
 // ---------------------------------------------------------------------------
 // IK_EXPORT: X, D, T of slot a in the caller's layout.
 // ---------------------------------------------------------------------------
-template <int MAXN>
-__device__ void do_export(const Prob& P, const Item& it, Smem<MAXN>&) {
+template <int NC>
+__device__ void do_export(const Prob& P, const Item& it, SmemC<NC>&) {
   const int N = P.N, Np = P.Np;
   CMat X = cmat_at(it.a.X, Np), T = cmat_at(it.a.T, Np);
   for (int idx = threadIdx.x; idx < N * N; idx += WG) {
@@ -599,23 +687,23 @@ __device__ void do_export(const Prob& P, const Item& it, Smem<MAXN>&) {
 
 // One kernel per work-item kind, so that profiles and timings name the phase.
 #define FDET_KERNEL(NAME, BODY)                                                        \
-  template <int MAXN>                                                                  \
+  template <int NC>                                                                  \
   __global__ __launch_bounds__(WG) void NAME(const Prob* __restrict__ probs,           \
                                              const Item* __restrict__ items) {         \
-    __shared__ Smem<MAXN> S;                                                           \
+    __shared__ SmemC<NC> S;                                                           \
     const Item it = items[blockIdx.x];                                                 \
     const Prob P = probs[it.prob];                                                     \
     BODY;                                                                              \
   }
 
-FDET_KERNEL(k_expm, do_expm<MAXN>(P, it, S))
-FDET_KERNEL(k_chain, do_chain<MAXN>(P, it, S))
-FDET_KERNEL(k_combine, do_combine<MAXN>(P, it, S))
-FDET_KERNEL(k_close, do_close<MAXN>(P, it.a, cmat_at(it.scr, P.Np),
+FDET_KERNEL(k_expm, do_expm<NC>(P, it, S))
+FDET_KERNEL(k_chain, do_chain<NC>(P, it, S))
+FDET_KERNEL(k_combine, do_combine<NC>(P, it, S))
+FDET_KERNEL(k_close, do_close<NC>(P, it.a, cmat_at(it.scr, P.Np),
                                     cmat_at(it.scr + cmat_doubles(P.Np), P.Np),
                                     cmat_at(it.scr, P.Np), (it.flags & IF_WANT_G) != 0, true, S))
-FDET_KERNEL(k_force, do_force<MAXN>(P, it, S))
-FDET_KERNEL(k_export, do_export<MAXN>(P, it, S))
+FDET_KERNEL(k_force, do_force<NC>(P, it, S))
+FDET_KERNEL(k_export, do_export<NC>(P, it, S))
 
 __global__ void k_init_status(const Prob* __restrict__ probs, int nprob) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -625,18 +713,18 @@ __global__ void k_init_status(const Prob* __restrict__ probs, int nprob) {
 }  // namespace fdet
 
 // Launchers used by the host planner.
-template <int MAXN>
+template <int NC>
 static hipError_t launch_kind(int kind, const fdet::Prob* probs, const fdet::Item* items, int n,
                               hipStream_t st) {
   using namespace fdet;
   const dim3 g(n), b(WG);
   switch (kind) {
-    case IK_EXPM: hipLaunchKernelGGL(k_expm<MAXN>, g, b, 0, st, probs, items); break;
-    case IK_CHAIN: hipLaunchKernelGGL(k_chain<MAXN>, g, b, 0, st, probs, items); break;
-    case IK_COMBINE: hipLaunchKernelGGL(k_combine<MAXN>, g, b, 0, st, probs, items); break;
-    case IK_CLOSE: hipLaunchKernelGGL(k_close<MAXN>, g, b, 0, st, probs, items); break;
-    case IK_FORCE: hipLaunchKernelGGL(k_force<MAXN>, g, b, 0, st, probs, items); break;
-    case IK_EXPORT: hipLaunchKernelGGL(k_export<MAXN>, g, b, 0, st, probs, items); break;
+    case IK_EXPM: hipLaunchKernelGGL(k_expm<NC>, g, b, 0, st, probs, items); break;
+    case IK_CHAIN: hipLaunchKernelGGL(k_chain<NC>, g, b, 0, st, probs, items); break;
+    case IK_COMBINE: hipLaunchKernelGGL(k_combine<NC>, g, b, 0, st, probs, items); break;
+    case IK_CLOSE: hipLaunchKernelGGL(k_close<NC>, g, b, 0, st, probs, items); break;
+    case IK_FORCE: hipLaunchKernelGGL(k_force<NC>, g, b, 0, st, probs, items); break;
+    case IK_EXPORT: hipLaunchKernelGGL(k_export<NC>, g, b, 0, st, probs, items); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -645,6 +733,9 @@ static hipError_t launch_kind(int kind, const fdet::Prob* probs, const fdet::Ite
 extern "C" hipError_t fdet_launch_items(int maxn, int kind, const fdet::Prob* probs,
                                         const fdet::Item* items, int nitems, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
+  if (maxn <= 32) return launch_kind<32>(kind, probs, items, nitems, st);
+  if (maxn <= 64) return launch_kind<64>(kind, probs, items, nitems, st);
+  if (maxn <= 96) return launch_kind<96>(kind, probs, items, nitems, st);
   if (maxn <= 128) return launch_kind<128>(kind, probs, items, nitems, st);
   return launch_kind<512>(kind, probs, items, nitems, st);
 }

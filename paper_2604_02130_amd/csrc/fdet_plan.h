@@ -29,7 +29,7 @@ enum ItemKind : int32_t {
   IK_CHAIN = 1,     // stabilised product of a range of slices
   IK_COMBINE = 2,   // UDV(a) <- UDV(b) x UDV(a): stabilised product of two
   IK_CLOSE = 3,     // log det (+ G) from a UDV
-  IK_FORCE = 4,     // G~ at a checkpoint, then wrap over the checkpoint interval
+  IK_FORCE = 4,     // G~ at a checkpoint, then carried forward and backward
   IK_EXPORT = 5,    // copy a UDV out in user layout
 };
 
@@ -52,6 +52,7 @@ struct Item {
   int32_t kind, prob, flags, sign;
   int32_t t0, t1;       // slice rows [t0, t1)
   int32_t s, c;         // stabilisation and checkpoint intervals
+  int32_t nb, pad0;     // force: rows t0-1, ..., t0-nb (mod N_t) carried backward
   Udv a;                // state / first operand / result
   Udv b;                // second operand (combine, force suffix)
   double* ck;           // checkpoint array base (IF_CKPT)

@@ -1,0 +1,572 @@
+// Workgroup primitives for N <= 128 (one workgroup of WG = 512 threads):
+// a register-resident column-pivoted Householder QR, the explicit Q, the
+// solve with R and Q^H, and an LDS-staged FP64 MFMA product.
+//
+// QR layout: the workgroup is 32 groups of 16 lanes (4 per wave, one DPP row
+// each).  Physical column c of the matrix being factorised lives in group
+// c % 32, slot c / 32; lane l16 = lane % 16 holds rows l16 + 16 m.  A column
+// reduction is a 16-lane DPP reduction, so the four groups of a wave reduce
+// in the same instructions, and no column leaves the registers during the
+// factorisation.  Every Householder vector is written once into an LDS
+// triangle, which the explicit Q and the Q^H solve then read without any
+// device-memory round trip.
+//
+// After rq_qrp the factor is also written back to W in pivoted order:
+// column j holds R(0..j, j) and the tail of reflector j below the diagonal,
+// the same contract as the in-memory routine of fdet_device.hpp.
+#pragma once
+
+#include "fdet_device.hpp"
+
+namespace fdet {
+
+template <int NC>
+struct RegClass {
+  static constexpr int CPL = (NC + 31) / 32;   // columns per lane group
+  static constexpr int RPL = (NC + 15) / 16;   // rows per lane
+};
+
+constexpr int KP = 16;   // k-panel depth of the staged product (4 MFMA k-steps)
+
+// LDS row stride (doubles) of a staged panel: >= n and = 16 (mod 32), so the
+// two 16-lane rows read by a half-wave fall into different bank halves.
+__host__ __device__ constexpr int panel_stride(int n) { return n + ((16 - n % 32) + 32) % 32; }
+
+template <int NC>
+struct BigLds {
+  static constexpr int TRI = NC * (NC + 1) / 2;              // complex triangle
+  static constexpr int PANEL = 4 * KP * panel_stride(NC);    // two complex panels
+  static constexpr int N = (2 * TRI > PANEL) ? 2 * TRI : PANEL;
+  static constexpr int UB = 16 * ((NC + 15) / 16);           // one padded column
+};
+
+// Shared state of size class NC (N <= NC): the scalar arrays of Smem plus a
+// large area used as the reflector / R triangle or as the product's panels.
+template <int NC>
+struct SmemC : Smem<(NC <= 128 ? 128 : 512)> {
+  double big[NC <= 128 ? BigLds<NC>::N : 1];
+  // current reflector as a full column (zero above its row), two buffers
+  double ubr[2][NC <= 128 ? BigLds<NC>::UB : 1];
+  double ubi[2][NC <= 128 ? BigLds<NC>::UB : 1];
+};
+
+// index of (row r, column j) in the lower (reflector) triangle, r >= j
+template <int NC>
+__device__ __forceinline__ int tri_lo(int r, int j) { return j * NC - (j * (j - 1)) / 2 + (r - j); }
+// index of (row r, column i) in the upper (R) triangle, r <= i
+__device__ __forceinline__ int tri_up(int r, int i) { return (i * (i + 1)) / 2 + r; }
+
+// 32-bit DPP move applied to both halves of a double (every lane writes).
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 16 lanes of a DPP row, result in every lane: quad_perm
+// [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror.  Each step adds
+// a commuted pair, so all 16 lanes end with the same bits.
+__device__ __forceinline__ double red16(double v) {
+  v += dpp<0xB1>(v);
+  v += dpp<0x4E>(v);
+  v += dpp<0x141>(v);
+  v += dpp<0x140>(v);
+  return v;
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// best of the four lane groups of a wave: (key desc, column asc)
+__device__ __forceinline__ void wave_best4(double& k, double& n, int& c) {
+  double bk = readlane_d(k, 0), bn = readlane_d(n, 0);
+  int bc = __builtin_amdgcn_readlane(c, 0);
+#pragma unroll
+  for (int g = 1; g < 4; ++g) {
+    const double ok = readlane_d(k, 16 * g), on = readlane_d(n, 16 * g);
+    const int oc = __builtin_amdgcn_readlane(c, 16 * g);
+    if (ok > bk || (ok == bk && oc < bc)) { bk = ok; bn = on; bc = oc; }
+  }
+  k = bk; n = bn; c = bc;
+}
+
+// element m of a register array for a runtime m
+template <int R>
+__device__ __forceinline__ double pick(const double* a, int m) {
+  double v = 0.0;
+#pragma unroll
+  for (int k = 0; k < R; ++k) v = (k == m) ? a[k] : v;
+  return v;
+}
+
+// the same reflector on all CPL columns of a lane, reductions interleaved
+template <int CPL, int RPL>
+__device__ __forceinline__ void rq_reflect_all(double beta, const double* ur, const double* ui,
+                                               double (*yr)[RPL], double (*yi)[RPL], int m_lo) {
+  double wr[CPL], wi[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      if (m < m_lo) continue;
+      sr += ur[m] * yr[q][m] + ui[m] * yi[q][m];
+      si += ur[m] * yi[q][m] - ui[m] * yr[q][m];
+    }
+    wr[q] = sr;
+    wi[q] = si;
+  }
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    wr[q] = beta * red16(wr[q]);
+    wi[q] = beta * red16(wi[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      if (m < m_lo) continue;
+      yr[q][m] -= ur[m] * wr[q] - ui[m] * wi[q];
+      yi[q][m] -= ur[m] * wi[q] + ui[m] * wr[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// rq_qrp: pre-pivoted Householder QR of the N x N matrix in W.
+//
+// The columns are ordered once by key = |column| x keys[c] (keys == nullptr:
+// 1), decreasing, ties to the lower index, and then factorised without
+// further pivoting.  Householder QR treats every column independently of its
+// scale, so ordering by |column| x keys[c] is the pivot order of
+// W diag(keys) while all arithmetic stays on W.
+//
+// Same contract as wg_qrp (R in the upper triangle of W in pivoted column
+// order, S.u0r/u0i, S.beta, S.piv, S.csp, S.nref) plus S.pinv[c] = position
+// of physical column c, S.rdr/rdi = diagonal of R and reflector j in the LDS
+// triangle (rows >= j, row j holding u0).  Below the diagonal W holds no
+// reflector data on this path; consumers read the triangle.
+//
+// Per column: the wave holding the column forms the reflector (exact norm)
+// and publishes it (one barrier); every column then takes the update
+// a <- a - beta u (u^H a), branch-free over the columns of a lane.
+// ---------------------------------------------------------------------------
+template <int NC>
+__device__ void rq_qrp(CMat W, int N, const double* keys, SmemC<NC>& S) {
+  constexpr int CPL = RegClass<NC>::CPL, RPL = RegClass<NC>::RPL;
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int l16 = lane & 15, grp = wave * 4 + (lane >> 4);
+  double* tr = S.big;
+  double* ti = S.big + BigLds<NC>::TRI;
+
+  double ar[CPL][RPL], ai[CPL][RPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int c = grp + 32 * q;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      const int r = l16 + 16 * m;
+      const bool in = c < N && r < N;
+      ar[q][m] = in ? W.r(r, c) : 0.0;
+      ai[q][m] = in ? W.m(r, c) : 0.0;
+      s += ar[q][m] * ar[q][m] + ai[q][m] * ai[q][m];
+    }
+    s = red16(s);
+    if (c < N && l16 == 0) S.v3[c] = sqrt(s) * (keys ? keys[c] : 1.0);
+  }
+  __syncthreads();
+  // position of each column: rank by key (decreasing), ties to the lower index
+  for (int c = tid; c < N; c += WG) {
+    const double kc = S.v3[c];
+    int pos = 0;
+    for (int d = 0; d < N; ++d) {
+      const double kd = S.v3[d];
+      pos += (kd > kc || (kd == kc && d < c)) ? 1 : 0;
+    }
+    S.pinv[c] = pos;
+    S.piv[pos] = c;
+    S.csp[pos] = keys ? keys[c] : 1.0;
+  }
+  if (tid == 0) S.nref = 0;
+  for (int r = tid; r < 2 * BigLds<NC>::UB; r += WG) {
+    (&S.ubr[0][0])[r] = 0.0;
+    (&S.ubi[0][0])[r] = 0.0;
+  }
+  __syncthreads();
+
+  for (int j = 0; j < N; ++j) {
+    const int p = S.piv[j];
+    const int buf = j & 1;
+    // ---- the wave holding column p forms the reflector and publishes it
+    if (wave == ((p & 31) >> 2)) {
+      const int qp = p >> 5;
+      const int m_lo = j >> 4;
+      double xr = 0.0, xi = 0.0, s = 0.0;
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        if (q != qp) continue;
+        xr = pick<RPL>(ar[q], m_lo);
+        xi = pick<RPL>(ai[q], m_lo);
+#pragma unroll
+        for (int m = 0; m < RPL; ++m) {
+          const int r = l16 + 16 * m;
+          const double keep = (r >= j) ? 1.0 : 0.0;
+          s += keep * (ar[q][m] * ar[q][m] + ai[q][m] * ai[q][m]);
+        }
+      }
+      // every group of the wave reduced its own slot qp; take the owner's
+      const double alpha = readlane_d(sqrt(red16(s)), 16 * (p & 3));
+      const int src = 16 * (p & 3) + (j & 15);
+      const double a0r = readlane_d(xr, src);
+      const double a0i = readlane_d(xi, src);
+      const double aa0 = sqrt(a0r * a0r + a0i * a0i);
+      double er = 1.0, ei = 0.0;
+      if (aa0 > 0.0) { const double inv = 1.0 / aa0; er = a0r * inv; ei = a0i * inv; }
+      const bool refl = alpha > 0.0;
+      const double beta = refl ? 1.0 / (alpha * (alpha + aa0)) : 0.0;
+      const double u0r = a0r + er * alpha, u0i = a0i + ei * alpha;
+      if (grp == (p & 31)) {
+#pragma unroll
+        for (int q = 0; q < CPL; ++q) {
+          if (q != qp) continue;
+#pragma unroll
+          for (int m = 0; m < RPL; ++m) {
+            const int r = l16 + 16 * m;
+            double vr = (r > j) ? ar[q][m] : 0.0;
+            double vi = (r > j) ? ai[q][m] : 0.0;
+            if (r == j) { vr = u0r; vi = u0i; }
+            S.ubr[buf][r] = vr;
+            S.ubi[buf][r] = vi;
+            if (r >= j && r < N) {
+              tr[tri_lo<NC>(r, j)] = vr;
+              ti[tri_lo<NC>(r, j)] = vi;
+            }
+          }
+        }
+      }
+      if (lane == 0) {
+        S.rdr[j] = refl ? -er * alpha : 0.0;
+        S.rdi[j] = refl ? -ei * alpha : 0.0;
+        S.u0r[j] = refl ? u0r : 0.0;
+        S.u0i[j] = refl ? u0i : 0.0;
+        S.beta[j] = beta;
+        if (refl) S.nref += 1;
+      }
+    }
+    __syncthreads();
+
+    // ---- every column of every lane takes a <- a - beta u (u^H a).  The
+    // pivot column becomes (R_jj, ~0, ...); columns already factorised only
+    // change below their diagonal, which no consumer reads; u is zero above
+    // row j, so no row above j changes.
+    const double beta = S.beta[j];
+    double ur[RPL], ui[RPL];
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      ur[m] = S.ubr[buf][l16 + 16 * m];
+      ui[m] = S.ubi[buf][l16 + 16 * m];
+    }
+    rq_reflect_all<CPL, RPL>(beta, ur, ui, ar, ai, 0);
+  }
+  __syncthreads();
+
+  // the diagonal of R exactly as formed (the in-register value carries the
+  // rounding of the reflector applied to its own column)
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int c = grp + 32 * q;
+    if (c >= N) continue;
+    const int pos = S.pinv[c];
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      if (l16 + 16 * m == pos) { ar[q][m] = S.rdr[pos]; ai[q][m] = S.rdi[pos]; }
+    }
+  }
+
+  // ---- write R back in pivoted column order
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int c = grp + 32 * q;
+    if (c >= N) continue;
+    const int pos = S.pinv[c];
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      const int r = l16 + 16 * m;
+      if (r < N) { W.r(r, pos) = ar[q][m]; W.m(r, pos) = ai[q][m]; }
+    }
+  }
+  __syncthreads();
+}
+
+// reflector j (rows of this lane) from the LDS triangle
+template <int NC, int RPL>
+__device__ __forceinline__ void rq_load_u(const SmemC<NC>& S, int N, int j, int l16, double* ur,
+                                          double* ui) {
+  const double* tr = S.big;
+  const double* ti = S.big + BigLds<NC>::TRI;
+#pragma unroll
+  for (int m = 0; m < RPL; ++m) {
+    const int r = l16 + 16 * m;
+    const bool in = r >= j && r < N;
+    ur[m] = in ? tr[tri_lo<NC>(r, j)] : 0.0;
+    ui[m] = in ? ti[tri_lo<NC>(r, j)] : 0.0;
+  }
+}
+
+// y <- (I - beta u u^H) y on the rows of one lane group (u zero above m_lo)
+template <int RPL>
+__device__ __forceinline__ void rq_reflect(double beta, const double* ur, const double* ui,
+                                           double* yr, double* yi, int m_lo) {
+  double sr = 0.0, si = 0.0;
+#pragma unroll
+  for (int m = 0; m < RPL; ++m) {
+    if (m < m_lo) continue;
+    sr += ur[m] * yr[m] + ui[m] * yi[m];
+    si += ur[m] * yi[m] - ui[m] * yr[m];
+  }
+  const double wr = beta * red16(sr), wi = beta * red16(si);
+#pragma unroll
+  for (int m = 0; m < RPL; ++m) {
+    if (m < m_lo) continue;
+    yr[m] -= ur[m] * wr - ui[m] * wi;
+    yi[m] -= ur[m] * wi + ui[m] * wr;
+  }
+}
+
+// Q = H_0 ... H_{N-1} written to Q (backward accumulation).  Groups own
+// whole columns and read reflectors from LDS: no barrier inside.  The caller
+// synchronises after (Q complete).
+template <int NC>
+__device__ void rq_form_q(int N, CMat Q, const SmemC<NC>& S) {
+  constexpr int CPL = RegClass<NC>::CPL, RPL = RegClass<NC>::RPL;
+  const int lane = lane_id(), wave = wave_id();
+  const int l16 = lane & 15, grp = wave * 4 + (lane >> 4);
+  double qr[CPL][RPL], qi[CPL][RPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int c = grp + 32 * q;
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) { qr[q][m] = (l16 + 16 * m == c) ? 1.0 : 0.0; qi[q][m] = 0.0; }
+  }
+  for (int j = N - 1; j >= 0; --j) {
+    const double beta = S.beta[j];
+    if (beta == 0.0) continue;
+    double ur[RPL], ui[RPL];
+    rq_load_u<NC, RPL>(S, N, j, l16, ur, ui);
+    // columns c < j of Q are still unit vectors with zero rows >= j and
+    // padding columns are zero, so every column takes the update
+    rq_reflect_all<CPL, RPL>(beta, ur, ui, qr, qi, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int c = grp + 32 * q;
+    if (c >= N) continue;
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      const int r = l16 + 16 * m;
+      if (r < N) { Q.r(r, c) = qr[q][m]; Q.m(r, c) = qi[q][m]; }
+    }
+  }
+}
+
+// Y <- R^{-1} Q^H Y for the factor of rq_qrp; Y is loaded from and stored
+// to Yg.  Q^H is applied from the LDS reflectors; then R (from W) replaces
+// them in the LDS triangle for the back substitution.
+template <int NC>
+__device__ void rq_solve(CMat W, int N, CMat Yg, SmemC<NC>& S) {
+  constexpr int CPL = RegClass<NC>::CPL, RPL = RegClass<NC>::RPL;
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int l16 = lane & 15, grp = wave * 4 + (lane >> 4);
+  const int gbase = lane & ~15;
+  double yr[CPL][RPL], yi[CPL][RPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int c = grp + 32 * q;
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      const int r = l16 + 16 * m;
+      const bool in = c < N && r < N;
+      yr[q][m] = in ? Yg.r(r, c) : 0.0;
+      yi[q][m] = in ? Yg.m(r, c) : 0.0;
+    }
+  }
+  for (int j = 0; j < N; ++j) {
+    const double beta = S.beta[j];
+    if (beta == 0.0) continue;
+    double ur[RPL], ui[RPL];
+    rq_load_u<NC, RPL>(S, N, j, l16, ur, ui);
+    rq_reflect_all<CPL, RPL>(beta, ur, ui, yr, yi, 0);
+  }
+  __syncthreads();
+  // R into the LDS triangle (column i, rows 0..i)
+  double* tr = S.big;
+  double* ti = S.big + BigLds<NC>::TRI;
+  for (int idx = tid; idx < N * N; idx += WG) {
+    const int r = idx % N, i = idx / N;
+    if (r <= i) { tr[tri_up(r, i)] = W.r(r, i); ti[tri_up(r, i)] = W.m(r, i); }
+  }
+  __syncthreads();
+  for (int i = N - 1; i >= 0; --i) {
+    const double dr = S.rdr[i], di = S.rdi[i];
+    const double den = dr * dr + di * di;
+    const int mi = i >> 4, li = i & 15;
+    double cr[RPL], ci[RPL];
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      const int r = l16 + 16 * m;
+      const bool in = r < i;
+      cr[m] = in ? tr[tri_up(r, i)] : 0.0;
+      ci[m] = in ? ti[tri_up(r, i)] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const double vr = __shfl(pick<RPL>(yr[q], mi), gbase + li, 64);
+      const double vi = __shfl(pick<RPL>(yi[q], mi), gbase + li, 64);
+      const double zr = (vr * dr + vi * di) / den;
+      const double zi = (vi * dr - vr * di) / den;
+#pragma unroll
+      for (int m = 0; m < RPL; ++m) {
+        if (16 * m > i) continue;
+        const int r = l16 + 16 * m;
+        if (r == i) { yr[q][m] = zr; yi[q][m] = zi; }
+        yr[q][m] -= cr[m] * zr - ci[m] * zi;
+        yi[q][m] -= cr[m] * zi + ci[m] * zr;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int c = grp + 32 * q;
+    if (c >= N) continue;
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      const int r = l16 + 16 * m;
+      if (r < N) { Yg.r(r, c) = yr[q][m]; Yg.m(r, c) = yi[q][m]; }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged product C = A B on the FP64 matrix cores (Np <= 128).
+//
+// K is walked in panels of KP = 16: the whole workgroup fetches the next
+// A(:, k0:k0+16) and B(k0:k0+16, :) into registers while it multiplies the
+// current panels from LDS, so device-memory latency is paid once.  Each wave
+// keeps the accumulators of its output tiles (16 x 16, round-robin) across all
+// panels.  AC / BC: operand is complex.  Loaders: la(i,k,re,im) or la(i,k),
+// lb(k,j,re,im) or lb(k,j); store st(i,j,re,im) or st(i,j,v).
+// ---------------------------------------------------------------------------
+template <int NC, bool AC, bool BC, class LA, class LB, class ST>
+__device__ void gemm_lds(int Np, LA la, LB lb, ST st, double* lds) {
+  constexpr bool CC = AC || BC;   // complex result
+  // tiles per wave; at most 4 accumulator tiles are live per pass over K
+  constexpr int MAXT = ((NC / 16) * (NC / 16) + NWAVE - 1) / NWAVE;
+  constexpr int TP = MAXT < 4 ? MAXT : 4;
+  constexpr int PER = (NC * KP + WG - 1) / WG;   // panel elements per thread
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int li = lane & 15, lk = lane >> 4;
+  const int SD = panel_stride(Np);
+  double* Ar = lds;
+  double* Ai = Ar + KP * SD;
+  double* Br = Ar + (AC ? 2 : 1) * KP * SD;
+  double* Bi = Br + KP * SD;
+  const int nt = Np >> 4, ntiles = nt * nt;
+  const int nel = Np * KP;
+  const int npass = (ntiles + NWAVE * TP - 1) / (NWAVE * TP);
+
+  double fa_r[PER], fa_i[PER], fb_r[PER], fb_i[PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int e = tid + WG * x;
+      fa_r[x] = 0.0; fa_i[x] = 0.0; fb_r[x] = 0.0; fb_i[x] = 0.0;
+      if (e < nel) {
+        const int i = e % Np, kk = e / Np;            // A: rows fastest
+        if constexpr (AC) la(i, k0 + kk, fa_r[x], fa_i[x]);
+        else fa_r[x] = la(i, k0 + kk);
+        const int kb = e % KP, j = e / KP;            // B: k fastest
+        if constexpr (BC) lb(k0 + kb, j, fb_r[x], fb_i[x]);
+        else fb_r[x] = lb(k0 + kb, j);
+      }
+    }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int e = tid + WG * x;
+      if (e < nel) {
+        const int i = e % Np, kk = e / Np;
+        Ar[kk * SD + i] = fa_r[x];
+        if constexpr (AC) Ai[kk * SD + i] = fa_i[x];
+        const int kb = e % KP, j = e / KP;
+        Br[kb * SD + j] = fb_r[x];
+        if constexpr (BC) Bi[kb * SD + j] = fb_i[x];
+      }
+    }
+  };
+  for (int pass = 0; pass < npass; ++pass) {
+    v4d cr[TP], ci[TP];
+#pragma unroll
+    for (int t = 0; t < TP; ++t) {
+      cr[t] = v4d{0.0, 0.0, 0.0, 0.0};
+      ci[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    fetch(0);
+    for (int k0 = 0; k0 < Np; k0 += KP) {
+      __syncthreads();
+      stash();
+      __syncthreads();
+      if (k0 + KP < Np) fetch(k0 + KP);
+#pragma unroll
+      for (int sk = 0; sk < KP / 4; ++sk) {
+        const int kk = 4 * sk + lk;
+#pragma unroll
+        for (int t = 0; t < TP; ++t) {
+          const int tile = wave + NWAVE * (pass * TP + t);
+          if (tile >= ntiles) break;
+          const int i = ((tile % nt) << 4) + li, j = ((tile / nt) << 4) + li;
+          const double a_r = Ar[kk * SD + i];
+          const double b_r = Br[kk * SD + j];
+          if constexpr (AC && BC) {
+            const double a_i = Ai[kk * SD + i], b_i = Bi[kk * SD + j];
+            cr[t] = mfma4(a_r, b_r, cr[t]);
+            ci[t] = mfma4(a_r, b_i, ci[t]);
+            cr[t] = mfma4(-a_i, b_i, cr[t]);
+            ci[t] = mfma4(a_i, b_r, ci[t]);
+          } else if constexpr (AC) {
+            const double a_i = Ai[kk * SD + i];
+            cr[t] = mfma4(a_r, b_r, cr[t]);
+            ci[t] = mfma4(a_i, b_r, ci[t]);
+          } else if constexpr (BC) {
+            const double b_i = Bi[kk * SD + j];
+            cr[t] = mfma4(a_r, b_r, cr[t]);
+            ci[t] = mfma4(a_r, b_i, ci[t]);
+          } else {
+            cr[t] = mfma4(a_r, b_r, cr[t]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TP; ++t) {
+      const int tile = wave + NWAVE * (pass * TP + t);
+      if (tile >= ntiles) break;
+      const int r0 = ((tile % nt) << 4) + lk, c0 = ((tile / nt) << 4) + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if constexpr (CC) st(r0 + 4 * r, c0, cr[t][r], ci[t][r]);
+        else st(r0 + 4 * r, c0, cr[t][r]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace fdet
