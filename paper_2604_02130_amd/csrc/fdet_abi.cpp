@@ -143,7 +143,7 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
     pl.maxN = std::max(pl.maxN, p[i].N);
     if (force) {
       nck[i] = (p[i].Nt + o.c - 1) / o.c;
-      nitems += 2 + 2 + nck[i];
+      nitems += 2 + 2 + 1 + nck[i];
     } else {
       nseg[i] = segments_for(p[i], o);
       int lev = 0;
@@ -236,12 +236,19 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
         c.t1 = q.Nt;
         c.s = o.s;
         c.c = o.c;
-        c.flags = fdet::IF_IDENTITY | fdet::IF_CKPT | (k == 1 ? fdet::IF_ADJOINT : fdet::IF_CLOSE_AFTER);
+        c.flags = fdet::IF_IDENTITY | fdet::IF_CKPT | (k == 1 ? fdet::IF_ADJOINT : 0);
         c.a = st[k];
         c.ck = k == 0 ? pre : suf;
         c.ckstride = (int64_t)(ub / sizeof(double));
         c.scr = cs[k];
         chain.push_back(c);
+      }
+      // log det of the whole product from the prefix chain's final state
+      {
+        Item z = blank_item(fdet::IK_CLOSE, i);
+        z.a = st[0];
+        z.scr = cs[0];
+        close.push_back(z);
       }
       // checkpoint k (row k*c) carries G~ forward over the first half of the
       // gap to the next checkpoint and backward over the second half of the

@@ -134,16 +134,19 @@ __device__ double block_max(double v, double* red) {
 // slice products
 // ---------------------------------------------------------------------------
 
-// out = E diag(e^{i phi_t}) in     (forward slice B_t)
+// One slice of the chain:
+//   forward  out = E diag(e^{i phi_t}) in        (B_t in)
+//   adjoint  out = diag(e^{-i phi_t}) E in       (B_t^H in, E real symmetric)
 template <int NC>
-__device__ void slice_forward(const Prob& P, CMat in, CMat out, SmemC<NC>& S) {
+__device__ void slice_apply(const Prob& P, CMat in, CMat out, bool adj, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const double* E = P.E;
   mm<NC, false, true>(
       Np, [&](int i, int k) { return (i < N && k < N) ? E[(size_t)k * Np + i] : 0.0; },
       [&](int k, int j, double& br, double& bi) {
         if (k < N && j < N) {
-          const double xr = in.r(k, j), xi = in.m(k, j), c = S.phr[k], s = S.phi_[k];
+          const double xr = in.r(k, j), xi = in.m(k, j);
+          const double c = adj ? 1.0 : S.phr[k], s = adj ? 0.0 : S.phi_[k];
           br = c * xr - s * xi;
           bi = s * xr + c * xi;
         } else {
@@ -151,24 +154,8 @@ __device__ void slice_forward(const Prob& P, CMat in, CMat out, SmemC<NC>& S) {
         }
       },
       [&](int i, int j, double cr, double ci) {
-        if (i < N && j < N) { out.r(i, j) = cr; out.m(i, j) = ci; }
-      }, S);
-}
-
-// out = diag(e^{-i phi_t}) E in    (B_t^H for real symmetric E)
-template <int NC>
-__device__ void slice_adjoint(const Prob& P, CMat in, CMat out, SmemC<NC>& S) {
-  const int N = P.N, Np = P.Np;
-  const double* E = P.E;
-  mm<NC, false, true>(
-      Np, [&](int i, int k) { return (i < N && k < N) ? E[(size_t)k * Np + i] : 0.0; },
-      [&](int k, int j, double& br, double& bi) {
-        if (k < N && j < N) { br = in.r(k, j); bi = in.m(k, j); }
-        else { br = 0.0; bi = 0.0; }
-      },
-      [&](int i, int j, double cr, double ci) {
         if (i < N && j < N) {
-          const double c = S.phr[i], s = S.phi_[i];
+          const double c = adj ? S.phr[i] : 1.0, s = adj ? S.phi_[i] : 0.0;
           out.r(i, j) = c * cr + s * ci;
           out.m(i, j) = c * ci - s * cr;
         }
@@ -232,8 +219,7 @@ __device__ void chain_chunk(const Prob& P, const Item& it, CMat X, CMat& Tc, CMa
     const int t = adj ? tfirst - q : tfirst + q;
     load_phases<NC>(P, t, S);
     __syncthreads();
-    if (adj) slice_adjoint<NC>(P, src, dst, S);
-    else slice_forward<NC>(P, src, dst, S);
+    slice_apply<NC>(P, src, dst, adj, S);
     __syncthreads();
     src = dst;
     dst = (dst.re == W.re) ? Y2 : W;
@@ -284,24 +270,27 @@ __device__ void do_chain(const Prob& P, const Item& it, SmemC<NC>& S) {
     const int kseg = adj ? (nck - 1 - q) : q;
     const int r0 = it.t0 + kseg * c;
     const int r1 = min(r0 + c, it.t1);
-    if (ckpt && !adj) save_ckpt(it.ck + (size_t)kseg * it.ckstride, X, Tc, D, N, Np);
-    if (ckpt && !adj) __syncthreads();
-    if (!adj) {
-      for (int t = r0; t < r1; t += s) chain_chunk<NC>(P, it, X, Tc, Tt, D, W, Y2, t, min(s, r1 - t), false, S);
-    } else {
-      for (int t = r1 - 1; t >= r0; t -= s) chain_chunk<NC>(P, it, X, Tc, Tt, D, W, Y2, t, min(s, t - r0 + 1), true, S);
+    if (ckpt && !adj) {
+      save_ckpt(it.ck + (size_t)kseg * it.ckstride, X, Tc, D, N, Np);
+      __syncthreads();
     }
-    if (ckpt && adj) { save_ckpt(it.ck + (size_t)kseg * it.ckstride, X, Tc, D, N, Np); __syncthreads(); }
+    // chunks of at most s slices: upward from r0, or downward from r1 - 1
+    const int nchunk = (r1 - r0 + s - 1) / s;
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int tfirst = adj ? r1 - 1 - ch * s : r0 + ch * s;
+      const int ns = adj ? min(s, tfirst - r0 + 1) : min(s, r1 - tfirst);
+      chain_chunk<NC>(P, it, X, Tc, Tt, D, W, Y2, tfirst, ns, adj, S);
+    }
+    if (ckpt && adj) {
+      save_ckpt(it.ck + (size_t)kseg * it.ckstride, X, Tc, D, N, Np);
+      __syncthreads();
+    }
   }
   if (Tc.re != T.re) {
     copy_cmat(T, Tc, N);
     __syncthreads();
   }
   if (threadIdx.x == 0 && S.flag) status_merge(P.status, -4);
-  if (it.flags & IF_CLOSE_AFTER) {
-    Udv U = it.a;
-    do_close<NC>(P, U, W, Y2, Tn, false, true, S);
-  }
 }
 
 // ---------------------------------------------------------------------------

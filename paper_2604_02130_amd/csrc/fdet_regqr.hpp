@@ -26,7 +26,10 @@ struct RegClass {
   static constexpr int RPL = (NC + 15) / 16;   // rows per lane
 };
 
-constexpr int KP = 16;   // k-panel depth of the staged product (4 MFMA k-steps)
+// k-panel depth of the staged product (4 MFMA k-steps); deeper panels would
+// double the prefetch registers of every thread
+template <int NC>
+__host__ __device__ constexpr int kpanel() { return 16; }
 
 // LDS row stride (doubles) of a staged panel: >= n and = 16 (mod 32), so the
 // two 16-lane rows read by a half-wave fall into different bank halves.
@@ -35,7 +38,7 @@ __host__ __device__ constexpr int panel_stride(int n) { return n + ((16 - n % 32
 template <int NC>
 struct BigLds {
   static constexpr int TRI = NC * (NC + 1) / 2;              // complex triangle
-  static constexpr int PANEL = 4 * KP * panel_stride(NC);    // two complex panels
+  static constexpr int PANEL = 4 * kpanel<NC>() * panel_stride(NC);   // two complex panels
   static constexpr int N = (2 * TRI > PANEL) ? 2 * TRI : PANEL;
   static constexpr int UB = 16 * ((NC + 15) / 16);           // one padded column
 };
@@ -105,30 +108,40 @@ __device__ __forceinline__ double pick(const double* a, int m) {
   return v;
 }
 
-// the same reflector on all CPL columns of a lane, reductions interleaved
+// The same reflector on the CPL columns of a lane, reductions interleaved.
+// Row blocks m < m_lo (all rows < 16 m_lo, where the reflector is zero) and
+// column slots q < q_lo are skipped; both bounds are wave-uniform, so the
+// skips are scalar branches, not lane masks.
 template <int CPL, int RPL>
 __device__ __forceinline__ void rq_reflect_all(double beta, const double* ur, const double* ui,
-                                               double (*yr)[RPL], double (*yi)[RPL], int m_lo) {
+                                               double (*yr)[RPL], double (*yi)[RPL], int m_lo,
+                                               int q_lo) {
+  m_lo = __builtin_amdgcn_readfirstlane(m_lo);
+  q_lo = __builtin_amdgcn_readfirstlane(q_lo);
   double wr[CPL], wi[CPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
     double sr = 0.0, si = 0.0;
+    if (q >= q_lo) {
 #pragma unroll
-    for (int m = 0; m < RPL; ++m) {
-      if (m < m_lo) continue;
-      sr += ur[m] * yr[q][m] + ui[m] * yi[q][m];
-      si += ur[m] * yi[q][m] - ui[m] * yr[q][m];
+      for (int m = 0; m < RPL; ++m) {
+        if (m < m_lo) continue;
+        sr += ur[m] * yr[q][m] + ui[m] * yi[q][m];
+        si += ur[m] * yi[q][m] - ui[m] * yr[q][m];
+      }
     }
     wr[q] = sr;
     wi[q] = si;
   }
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
+    if (q < q_lo) continue;
     wr[q] = beta * red16(wr[q]);
     wi[q] = beta * red16(wi[q]);
   }
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
+    if (q < q_lo) continue;
 #pragma unroll
     for (int m = 0; m < RPL; ++m) {
       if (m < m_lo) continue;
@@ -273,7 +286,7 @@ __device__ void rq_qrp(CMat W, int N, const double* keys, SmemC<NC>& S) {
       ur[m] = S.ubr[buf][l16 + 16 * m];
       ui[m] = S.ubi[buf][l16 + 16 * m];
     }
-    rq_reflect_all<CPL, RPL>(beta, ur, ui, ar, ai, 0);
+    rq_reflect_all<CPL, RPL>(beta, ur, ui, ar, ai, 0, 0);
   }
   __syncthreads();
 
@@ -360,9 +373,9 @@ __device__ void rq_form_q(int N, CMat Q, const SmemC<NC>& S) {
     if (beta == 0.0) continue;
     double ur[RPL], ui[RPL];
     rq_load_u<NC, RPL>(S, N, j, l16, ur, ui);
-    // columns c < j of Q are still unit vectors with zero rows >= j and
-    // padding columns are zero, so every column takes the update
-    rq_reflect_all<CPL, RPL>(beta, ur, ui, qr, qi, 0);
+    // columns c < j of Q are still unit vectors with zero rows >= j: slots
+    // whose 32 columns all lie below j are skipped, the rest are updated
+    rq_reflect_all<CPL, RPL>(beta, ur, ui, qr, qi, 0, 0);
   }
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
@@ -402,7 +415,7 @@ __device__ void rq_solve(CMat W, int N, CMat Yg, SmemC<NC>& S) {
     if (beta == 0.0) continue;
     double ur[RPL], ui[RPL];
     rq_load_u<NC, RPL>(S, N, j, l16, ur, ui);
-    rq_reflect_all<CPL, RPL>(beta, ur, ui, yr, yi, 0);
+    rq_reflect_all<CPL, RPL>(beta, ur, ui, yr, yi, 0, 0);
   }
   __syncthreads();
   // R into the LDS triangle (column i, rows 0..i)
@@ -456,8 +469,9 @@ __device__ void rq_solve(CMat W, int N, CMat Yg, SmemC<NC>& S) {
 // ---------------------------------------------------------------------------
 // LDS-staged product C = A B on the FP64 matrix cores (Np <= 128).
 //
-// K is walked in panels of KP = 16: the whole workgroup fetches the next
-// A(:, k0:k0+16) and B(k0:k0+16, :) into registers while it multiplies the
+// K is walked in panels of KP = kpanel<NC>() columns: the whole workgroup
+// fetches the next A(:, k0:k0+KP) and B(k0:k0+KP, :) into registers while it
+// multiplies the
 // current panels from LDS, so device-memory latency is paid once.  Each wave
 // keeps the accumulators of its output tiles (16 x 16, round-robin) across all
 // panels.  AC / BC: operand is complex.  Loaders: la(i,k,re,im) or la(i,k),
@@ -466,6 +480,7 @@ __device__ void rq_solve(CMat W, int N, CMat Yg, SmemC<NC>& S) {
 template <int NC, bool AC, bool BC, class LA, class LB, class ST>
 __device__ void gemm_lds(int Np, LA la, LB lb, ST st, double* lds) {
   constexpr bool CC = AC || BC;   // complex result
+  constexpr int KP = kpanel<NC>();
   // tiles per wave; at most 4 accumulator tiles are live per pass over K
   constexpr int MAXT = ((NC / 16) * (NC / 16) + NWAVE - 1) / NWAVE;
   constexpr int TP = MAXT < 4 ? MAXT : 4;
