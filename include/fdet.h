@@ -75,12 +75,16 @@ typedef struct {
 
 typedef struct {
   int32_t s;            /* QR every s slices (Sec. 9 sporadic stabilisation);
-                           0 = 8.  Keep s*dk*spectral_radius(K) <= 6.          */
+                           0 = the tuned value for this shape (fd_autotune),
+                           else 8.  Keep s*dk*spectral_radius(K) <= 6.         */
   int32_t checkpoint;   /* force: UDV checkpoint interval c (0 = 16).  G~ is
                            carried across c slices, which amplifies rounding
                            like cond(B)^c: keep c*dk*spectral_radius(K) <= 6. */
   int32_t segments;     /* det/G: independent time segments per problem that
-                           are combined by stabilised products (0 = auto)      */
+                           are combined by stabilised products (0 = the tuned
+                           value for this shape, else a power of two near
+                           Nt/8, at most 32, fewer when the batch alone gives
+                           every compute unit two workgroups)                  */
   int32_t flags;        /* FD_REUSE_E                                          */
 } fd_options;
 
@@ -137,6 +141,45 @@ int fd_greens_batched(const fd_problem *p, int32_t nprob, const fd_options *o,
 int fd_force_batched(const fd_problem *p, int32_t nprob, const fd_options *o,
                      double *logdet, double *force, double *force_im, void *ws,
                      size_t ws_bytes, int32_t *status, void *stream);
+
+/* Prepared calls.  A plan fixes one call of kind `what` (FD_WHAT_LOGDET,
+ * FD_WHAT_GREENS or FD_WHAT_FORCE) on fixed problems, outputs and workspace,
+ * and uploads its work descriptors into the head of the workspace once
+ * (synchronously on `stream`; not allowed while `stream` is capturing).
+ * fd_plan_launch then only enqueues kernels (no copies, no fills), so it may
+ * be captured into a HIP graph and replayed; it reads K and phi at launch
+ * time, so the caller updates phi in place between launches (the molecular
+ * dynamics steps of HMC, Sec. 3.1).  Outputs as for the matching entry
+ * point; G / force that `what` does not produce are ignored and may be NULL.
+ * The workspace must not be used by any other call while the plan is alive;
+ * with FD_REUSE_E, exp(+-dk K) must already be in it from a call of the same
+ * kind and options.  fd_plan_destroy frees host memory only.               */
+typedef struct fd_plan fd_plan;
+int fd_plan_create(int32_t what, const fd_problem *p, int32_t nprob, const fd_options *o,
+                   double *logdet, double *G, double *force, double *force_im, void *ws,
+                   size_t ws_bytes, int32_t *status, void *stream, fd_plan **plan);
+int fd_plan_launch(const fd_plan *plan, void *stream);
+void fd_plan_destroy(fd_plan *plan);
+
+/* Autotuning of the stabilisation interval s (Sec. 9 leaves its choice to
+ * the conditioning: candidates 4, 8, 16 within s*dk*radius(K) <= 6, radius
+ * bounded by the largest absolute row sum of K) and of the time segments
+ * (1, 2, 4, ..., 64) for these problems and `what` (LOGDET, GREENS or FORCE;
+ * FORCE tunes s only).  Fields of `o` that are nonzero are kept fixed.  Each
+ * candidate runs once untimed and three times timed on `stream`; the median
+ * decides, candidates whose status is an error are skipped.  The winner is
+ * stored in the process-wide table that fields left at 0 consult (key: what,
+ * largest N, largest Nt, nprob, dk) and returned in *best / *best_ms (either
+ * may be NULL).  Synchronous; allocates and frees its own device memory, so
+ * it is a set-up call, never one for graph capture.
+ * fd_tune_save / fd_tune_load write / merge the table as text ("fdet-tune 1"
+ * and one line per entry); load returns the number of entries read or an
+ * error code.  fd_tune_clear empties the table.                             */
+int fd_autotune(int32_t what, const fd_problem *p, int32_t nprob, const fd_options *o,
+                void *stream, fd_options *best, float *best_ms);
+int fd_tune_save(const char *path);
+int fd_tune_load(const char *path);
+int fd_tune_clear(void);
 
 /* Text for a return/status code; the last error message of this thread.      */
 const char *fd_strerror(int code);

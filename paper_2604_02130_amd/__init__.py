@@ -35,6 +35,8 @@ SYMBOLS = (
     "fd_workspace_bytes", "fd_slice_exponential", "fd_logdet", "fd_greens", "fd_force",
     "fd_udv", "fd_logdet_batched", "fd_greens_batched", "fd_force_batched",
     "fd_strerror", "fd_last_error", "fd_version", "fd_profile_start", "fd_profile_stop",
+    "fd_plan_create", "fd_plan_launch", "fd_plan_destroy", "fd_autotune", "fd_tune_save",
+    "fd_tune_load", "fd_tune_clear",
 )
 
 PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export"}
@@ -94,6 +96,21 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fd_profile_start.restype = ctypes.c_int
     lib.fd_profile_stop.argtypes = [i32, vp, vp, vp]
     lib.fd_profile_stop.restype = ctypes.c_int
+    lib.fd_plan_create.argtypes = [i32, P, i32, O, vp, vp, vp, vp, vp, sz, vp, vp,
+                                   ctypes.POINTER(vp)]
+    lib.fd_plan_create.restype = ctypes.c_int
+    lib.fd_plan_launch.argtypes = [vp, vp]
+    lib.fd_plan_launch.restype = ctypes.c_int
+    lib.fd_plan_destroy.argtypes = [vp]
+    lib.fd_plan_destroy.restype = None
+    lib.fd_autotune.argtypes = [i32, P, i32, O, vp, O, ctypes.POINTER(ctypes.c_float)]
+    lib.fd_autotune.restype = ctypes.c_int
+    lib.fd_tune_save.argtypes = [ctypes.c_char_p]
+    lib.fd_tune_save.restype = ctypes.c_int
+    lib.fd_tune_load.argtypes = [ctypes.c_char_p]
+    lib.fd_tune_load.restype = ctypes.c_int
+    lib.fd_tune_clear.argtypes = []
+    lib.fd_tune_clear.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -352,3 +369,210 @@ def force_batched(problems, s=0, checkpoint=0, flags=0, check=True, ws: Workspac
         Fs.append(torch.complex(Fr[off:off + m], Fi[off:off + m]).view(p.Nt, p.N))
         off += m
     return Fs, torch.view_as_complex(ld)
+
+
+# ---------------------------------------------------------------------------
+# Prepared calls, graph replay, autograd and autotuning
+# ---------------------------------------------------------------------------
+_WHAT = {"logdet": FD_WHAT_LOGDET, "greens": FD_WHAT_GREENS, "force": FD_WHAT_FORCE}
+
+
+class Plan:
+    """One prepared call (fd_plan_create) on fixed problems, outputs and a
+    workspace of its own.  launch() only enqueues kernels, so it can be
+    captured in a graph; phi tensors are read at launch time and may be
+    updated in place between launches.
+
+    what: "logdet", "greens" or "force"; problems: list of (K, phi, dk).
+    reuse_e: compute exp(+-dk K) once now and skip it in every launch (K and
+    dk must then stay fixed).
+    """
+
+    def __init__(self, what, problems, s=0, checkpoint=0, segments=0, reuse_e=False):
+        torch = _torch()
+        self.lib = load_library()
+        self.what = _WHAT[what]
+        self.problems = list(problems)
+        self.probs = _batch(self.problems)
+        n = len(self.probs)
+        dev = self.problems[0][0].device
+        self.n = n
+        self.arr = (FdProblem * n)(*self.probs)
+        self.ld = torch.empty((n, 2), dtype=torch.float64, device=dev)
+        self.status = torch.empty(n, dtype=torch.int32, device=dev)
+        self.G = self.Fr = self.Fi = None
+        if self.what == FD_WHAT_GREENS:
+            self.G = torch.empty(sum(2 * p.N * p.N for p in self.probs), dtype=torch.float64,
+                                 device=dev)
+        if self.what == FD_WHAT_FORCE:
+            tot = sum(p.N * p.Nt for p in self.probs)
+            self.Fr = torch.empty(tot, dtype=torch.float64, device=dev)
+            self.Fi = torch.empty(tot, dtype=torch.float64, device=dev)
+        self.ws = Workspace()
+        need = workspace_bytes(self.probs, self.what, s=s, checkpoint=checkpoint,
+                               segments=segments)
+        self.wsp, self.wsn = self.ws.get(need, dev)
+        self.handle = ctypes.c_void_p(0)
+        if reuse_e:
+            # one full call fills exp(+-dk K) into this workspace
+            self._create(_opts(s=s, checkpoint=checkpoint, segments=segments))
+            self.launch()
+            torch.cuda.current_stream().synchronize()
+            _status_check(self.status, True)
+            self.lib.fd_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+        self._create(_opts(s=s, checkpoint=checkpoint, segments=segments,
+                           flags=FD_REUSE_E if reuse_e else 0))
+
+    def _create(self, o):
+        _check(self.lib.fd_plan_create(
+            self.what, self.arr, self.n, ctypes.byref(o), _ptr(self.ld), _ptr(self.G),
+            _ptr(self.Fr), _ptr(self.Fi), self.wsp, self.wsn, _ptr(self.status), _stream(),
+            ctypes.byref(self.handle)))
+
+    def launch(self):
+        """Enqueue the plan's kernels on the current stream."""
+        _check(self.lib.fd_plan_launch(self.handle, _stream()))
+
+    def results(self, check=False):
+        """Views of the outputs: logdet (n,) complex, plus [G_i] or [F_i]."""
+        torch = _torch()
+        _status_check(self.status, check)
+        ld = torch.view_as_complex(self.ld)
+        if self.what == FD_WHAT_GREENS:
+            out, off = [], 0
+            for p in self.probs:
+                m = 2 * p.N * p.N
+                out.append(torch.view_as_complex(self.G[off:off + m].view(p.N, p.N, 2)))
+                off += m
+            return ld, out
+        if self.what == FD_WHAT_FORCE:
+            out, off = [], 0
+            for p in self.probs:
+                m = p.N * p.Nt
+                out.append(torch.complex(self.Fr[off:off + m], self.Fi[off:off + m])
+                           .view(p.Nt, p.N))
+                off += m
+            return ld, out
+        return ld, []
+
+    def close(self):
+        if self.handle:
+            self.lib.fd_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Trajectory:
+    """The force and log det of a fixed K captured once as a graph and replayed
+    for each molecular-dynamics step of HMC (Sec. 3.1: every leapfrog step
+    needs dH/dphi at the current field).
+
+        traj = Trajectory(K, phi0, dk, s=8, checkpoint=16)
+        logdet, F = traj.step(phi)      # F: (Nt, N) complex, views of static outputs
+
+    exp(+-dk K) is computed once at construction; every replay runs the
+    chains, the checkpoint closes and the force sweep on the static copy of
+    phi (step() copies its argument in first).  Outputs are overwritten by the
+    next step(); clone them to keep them.
+    """
+
+    def __init__(self, K, phi, dk, s=0, checkpoint=0, what="force"):
+        torch = _torch()
+        self.phi = phi.clone()
+        self.plan = Plan(what, [(K, self.phi, dk)], s=s, checkpoint=checkpoint, reuse_e=True)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.plan.launch()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.plan.launch()
+        torch.cuda.synchronize()
+
+    def step(self, phi=None, check=True):
+        if phi is not None:
+            self.phi.copy_(phi)
+        self.graph.replay()
+        ld, outs = self.plan.results(check=check)
+        return ld[0], (outs[0] if outs else None)
+
+
+def _logdet_function():
+    torch = _torch()
+
+    class LogDet(torch.autograd.Function):
+        """log det M as a differentiable function of phi (K, dk fixed).
+
+        Forward computes log det M; when phi needs a gradient it runs the
+        force path, which yields log det M and F = d log det M / d phi in one
+        pass.  For a real loss L with upstream gradient g = dL/dRe + i dL/dIm,
+        the backward returns g.real * Re F + g.imag * Im F.
+        """
+
+        @staticmethod
+        def forward(ctx, phi, K, dk, s, checkpoint):
+            if ctx.needs_input_grad[0]:
+                F, ld = force(K, phi.detach(), dk, s=s, checkpoint=checkpoint, with_logdet=True)
+                ctx.save_for_backward(torch.view_as_real(F))
+            else:
+                ld = logdet(K, phi.detach(), dk, s=s)
+            return ld
+
+        @staticmethod
+        def backward(ctx, g):
+            (F,) = ctx.saved_tensors
+            g = g.to(torch.complex128)
+            return g.real * F[..., 0] + g.imag * F[..., 1], None, None, None, None
+
+    return LogDet
+
+
+_LogDet = None
+
+
+def log_det(phi, K, dk, s=0, checkpoint=0):
+    """Differentiable log det M (complex scalar); see LogDet."""
+    global _LogDet
+    if _LogDet is None:
+        _LogDet = _logdet_function()
+    return _LogDet.apply(phi, K, dk, int(s), int(checkpoint))
+
+
+def autotune(problems, what="greens", s=0, checkpoint=0, segments=0):
+    """Time candidate (s, segments) for these (K, phi, dk) problems on the GPU and
+    store the winner for later calls with those options left at 0.
+    Returns {"s", "segments", "checkpoint", "ms"}."""
+    _torch()
+    lib = load_library()
+    probs = _batch(problems)
+    arr = (FdProblem * len(probs))(*probs)
+    o = _opts(s=s, checkpoint=checkpoint, segments=segments)
+    best = FdOptions()
+    ms = ctypes.c_float(0.0)
+    _check(lib.fd_autotune(_WHAT[what], arr, len(probs), ctypes.byref(o), _stream(),
+                           ctypes.byref(best), ctypes.byref(ms)))
+    return {"s": best.s, "segments": best.segments, "checkpoint": best.checkpoint,
+            "ms": float(ms.value)}
+
+
+def tune_save(path: str):
+    _check(load_library().fd_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str) -> int:
+    n = load_library().fd_tune_load(os.fsencode(path))
+    if n < 0:
+        _check(n)
+    return n
+
+
+def tune_clear():
+    _check(load_library().fd_tune_clear())

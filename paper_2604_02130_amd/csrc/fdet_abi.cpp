@@ -6,6 +6,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -49,14 +52,84 @@ struct Opts {
   int s, c, segments, flags;
 };
 
-Opts resolve(const fd_options* o) {
-  Opts r{8, 16, 0, 0};
+// ---- tuned choices of (s, segments), keyed by the shape of a call
+struct TuneKey {
+  int what, maxN, maxNt, nprob;
+  long long dk_micro;
+  bool operator==(const TuneKey& o) const {
+    return what == o.what && maxN == o.maxN && maxNt == o.maxNt && nprob == o.nprob &&
+           dk_micro == o.dk_micro;
+  }
+};
+struct TuneVal {
+  int s, segments;
+  float ms;
+};
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, TuneVal>> g_tune;
+
+TuneKey tune_key(const fd_problem* p, int nprob, int what) {
+  TuneKey k{what, 0, 0, nprob, 0};
+  for (int i = 0; i < nprob; ++i) {
+    k.maxN = std::max(k.maxN, p[i].N);
+    k.maxNt = std::max(k.maxNt, p[i].Nt);
+  }
+  k.dk_micro = std::llround(p[0].dk * 1e6);
+  return k;
+}
+
+bool tune_lookup(const TuneKey& k, TuneVal& v) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (auto& e : g_tune)
+    if (e.first == k) { v = e.second; return true; }
+  return false;
+}
+
+void tune_store(const TuneKey& k, const TuneVal& v) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (auto& e : g_tune)
+    if (e.first == k) { e.second = v; return; }
+  g_tune.push_back({k, v});
+}
+
+int pow2_floor(int x) {
+  int r = 1;
+  while (2 * r <= x) r *= 2;
+  return r;
+}
+
+// Segments when neither the caller nor the tuner chose: a chain segment of
+// about 8 slices per QR interval balances chain and combine latency for one
+// problem; batches that already give every compute unit a workgroup per
+// problem need fewer segments.
+int default_segments(const fd_problem* p, int nprob) {
+  int maxNt = 1;
+  for (int i = 0; i < nprob; ++i) maxNt = std::max(maxNt, p[i].Nt);
+  int seg = std::min(32, pow2_floor(std::max(1, maxNt / 8)));
+  const int target = 512;   // two workgroups per compute unit
+  if (nprob * seg > target) seg = std::max(1, pow2_floor(std::max(1, target / nprob)));
+  return seg;
+}
+
+// Options of one call: explicit fields win, then a tuned entry for this
+// shape, then the defaults (s = 8, c = 16, default_segments).
+Opts resolve(const fd_options* o, const fd_problem* p = nullptr, int nprob = 0, int what = -1) {
+  Opts r{0, 16, 0, 0};
   if (o) {
     if (o->s > 0) r.s = o->s;
     if (o->checkpoint > 0) r.c = o->checkpoint;
     if (o->segments > 0) r.segments = o->segments;
     r.flags = o->flags;
   }
+  if (p && nprob > 0 && (r.s == 0 || r.segments == 0)) {
+    TuneVal v;
+    if (tune_lookup(tune_key(p, nprob, what), v)) {
+      if (r.s == 0) r.s = v.s;
+      if (r.segments == 0) r.segments = v.segments;
+    }
+    if (r.segments == 0) r.segments = default_segments(p, nprob);
+  }
+  if (r.s == 0) r.s = 8;
   return r;
 }
 
@@ -279,40 +352,57 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   pl.total = cur.off;
 }
 
-// Upload descriptors into the head of the workspace and launch every phase.
-int execute(Plan& pl, char* ws, hipStream_t st) {
+// Descriptors (problems, then the items of every phase) in the head of the
+// workspace; `first` receives the index of each phase's first item.
+std::vector<char> pack_descriptors(const Plan& pl, std::vector<size_t>& first) {
   std::vector<char> host(pl.desc_bytes, 0);
   const size_t pbytes = align_up(sizeof(Prob) * pl.probs.size());
   std::memcpy(host.data(), pl.probs.data(), sizeof(Prob) * pl.probs.size());
-  std::vector<size_t> first;
+  first.clear();
   size_t n = 0;
   for (auto& ph : pl.phases) {
     first.push_back(n);
     std::memcpy(host.data() + pbytes + n * sizeof(Item), ph.data(), ph.size() * sizeof(Item));
     n += ph.size();
   }
-  hipError_t e = hipMemcpyAsync(ws, host.data(), pl.desc_bytes, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+  return host;
+}
+
+// Kernel launches only (no copies or fills): the part a HIP graph captures.
+int launch_phases(const Plan& pl, const std::vector<size_t>& first, char* ws, hipStream_t st) {
+  const size_t pbytes = align_up(sizeof(Prob) * pl.probs.size());
   const Prob* dprobs = reinterpret_cast<const Prob*>(ws);
   const Item* ditems = reinterpret_cast<const Item*>(ws + pbytes);
-  e = fdet_launch_init_status(dprobs, (int)pl.probs.size(), st);
+  hipError_t e = fdet_launch_init_status(dprobs, (int)pl.probs.size(), st);
   if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  const bool prof = g_prof_on && hipStreamIsCapturing(st, &cap) == hipSuccess &&
+                    cap == hipStreamCaptureStatusNone;
   for (size_t k = 0; k < pl.phases.size(); ++k) {
     const int kind = pl.phases[k].front().kind;
     PhaseRec rec{kind, (int)pl.phases[k].size(), nullptr, nullptr};
-    if (g_prof_on) {
+    if (prof) {
       if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess)
         return fail(FD_ERR_HIP, "event creation failed");
       hipEventRecord(rec.a, st);
     }
     e = fdet_launch_items(pl.maxN, kind, dprobs, ditems + first[k], (int)pl.phases[k].size(), st);
     if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
-    if (g_prof_on) {
+    if (prof) {
       hipEventRecord(rec.b, st);
       g_prof.push_back(rec);
     }
   }
   return FD_OK;
+}
+
+// Upload descriptors into the head of the workspace and launch every phase.
+int execute(Plan& pl, char* ws, hipStream_t st) {
+  std::vector<size_t> first;
+  std::vector<char> host = pack_descriptors(pl, first);
+  hipError_t e = hipMemcpyAsync(ws, host.data(), pl.desc_bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+  return launch_phases(pl, first, ws, st);
 }
 
 int check_ws(void* ws, size_t ws_bytes, size_t need) {
@@ -340,16 +430,17 @@ struct Outs {
   int32_t* status = nullptr;
 };
 
-int run(const fd_problem* p, int nprob, const fd_options* opt, int what, const Outs& out, void* ws,
-        size_t ws_bytes, void* stream) {
-  const Opts o = resolve(opt);
+// Validate, lay out the workspace and attach the outputs.
+int prepare(const fd_problem* p, int nprob, const fd_options* opt, int what, const Outs& out,
+            void* ws, size_t ws_bytes, Plan& pl) {
+  if (!p || nprob < 1) return fail(FD_ERR_INVALID_ARG, "no problems given");
+  const Opts o = resolve(opt, p, nprob, what);
   int rc = validate(p, nprob, o);
   if (rc != FD_OK) return rc;
   Plan sizing;
   build_plan(p, nprob, o, what, nullptr, sizing);
   rc = check_ws(ws, ws_bytes, sizing.total);
   if (rc != FD_OK) return rc;
-  Plan pl;
   build_plan(p, nprob, o, what, static_cast<char*>(ws), pl);
   size_t goff = 0, foff = 0;
   for (int i = 0; i < nprob; ++i) {
@@ -366,19 +457,49 @@ int run(const fd_problem* p, int nprob, const fd_options* opt, int what, const O
     goff += (size_t)2 * p[i].N * p[i].N;
     foff += (size_t)p[i].Nt * p[i].N;
   }
+  return FD_OK;
+}
+
+int run(const fd_problem* p, int nprob, const fd_options* opt, int what, const Outs& out, void* ws,
+        size_t ws_bytes, void* stream) {
+  Plan pl;
+  int rc = prepare(p, nprob, opt, what, out, ws, ws_bytes, pl);
+  if (rc != FD_OK) return rc;
   return execute(pl, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+}
+
+// Gershgorin bound on the spectral radius of a real symmetric K (host copy).
+double radius_bound(const std::vector<double>& K, int N) {
+  double r = 0.0;
+  for (int i = 0; i < N; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < N; ++j) s += std::fabs(K[(size_t)i * N + j]);
+    r = std::max(r, s);
+  }
+  return r;
 }
 
 }  // namespace
 
+// A prepared call whose descriptors stay resident in its workspace.
+struct fd_plan {
+  Plan pl;
+  std::vector<size_t> first;
+  char* ws = nullptr;
+};
+
 extern "C" {
 
 size_t fd_workspace_bytes(const fd_problem* p, int32_t nprob, const fd_options* o, int32_t what) {
-  const Opts r = resolve(o);
   if (what < FD_WHAT_LOGDET || what > FD_WHAT_UDV) {
     fail(FD_ERR_INVALID_ARG, "unknown workspace kind");
     return 0;
   }
+  if (!p || nprob < 1) {
+    fail(FD_ERR_INVALID_ARG, "no problems given");
+    return 0;
+  }
+  const Opts r = resolve(o, p, nprob, what);
   if (validate(p, nprob, r) != FD_OK) return 0;
   Plan pl;
   build_plan(p, nprob, r, what, nullptr, pl);
@@ -462,6 +583,207 @@ int fd_force_batched(const fd_problem* p, int32_t nprob, const fd_options* o, do
   out.force_im = force_im;
   out.status = status;
   return run(p, nprob, o, FD_WHAT_FORCE, out, ws, ws_bytes, stream);
+}
+
+int fd_plan_create(int32_t what, const fd_problem* p, int32_t nprob, const fd_options* o,
+                   double* logdet, double* G, double* force, double* force_im, void* ws,
+                   size_t ws_bytes, int32_t* status, void* stream, fd_plan** plan) {
+  if (!plan) return fail(FD_ERR_INVALID_ARG, "plan must not be NULL");
+  *plan = nullptr;
+  if (what != FD_WHAT_LOGDET && what != FD_WHAT_GREENS && what != FD_WHAT_FORCE)
+    return fail(FD_ERR_INVALID_ARG, "a plan computes FD_WHAT_LOGDET, _GREENS or _FORCE");
+  if (!status) return fail(FD_ERR_INVALID_ARG, "status must be a device pointer");
+  if (what == FD_WHAT_LOGDET && !logdet) return fail(FD_ERR_INVALID_ARG, "logdet must be a device pointer");
+  if (what == FD_WHAT_GREENS && !G) return fail(FD_ERR_INVALID_ARG, "G must be a device pointer");
+  if (what == FD_WHAT_FORCE && !force) return fail(FD_ERR_INVALID_ARG, "force must be a device pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+    return fail(FD_ERR_INVALID_ARG, "create plans outside stream capture");
+  Outs out;
+  out.logdet = logdet;
+  out.G = what == FD_WHAT_GREENS ? G : nullptr;
+  out.force = what == FD_WHAT_FORCE ? force : nullptr;
+  out.force_im = what == FD_WHAT_FORCE ? force_im : nullptr;
+  out.status = status;
+  fd_plan* h = new fd_plan;
+  int rc = prepare(p, nprob, o, what, out, ws, ws_bytes, h->pl);
+  if (rc != FD_OK) { delete h; return rc; }
+  h->ws = static_cast<char*>(ws);
+  std::vector<char> host = pack_descriptors(h->pl, h->first);
+  hipError_t e = hipMemcpyAsync(ws, host.data(), h->pl.desc_bytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(FD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+  }
+  *plan = h;
+  return FD_OK;
+}
+
+int fd_plan_launch(const fd_plan* plan, void* stream) {
+  if (!plan) return fail(FD_ERR_INVALID_ARG, "plan must not be NULL");
+  return launch_phases(plan->pl, plan->first, plan->ws, static_cast<hipStream_t>(stream));
+}
+
+void fd_plan_destroy(fd_plan* plan) { delete plan; }
+
+int fd_autotune(int32_t what, const fd_problem* p, int32_t nprob, const fd_options* o,
+                void* stream, fd_options* best, float* best_ms) {
+  if (what != FD_WHAT_LOGDET && what != FD_WHAT_GREENS && what != FD_WHAT_FORCE)
+    return fail(FD_ERR_INVALID_ARG, "autotune covers FD_WHAT_LOGDET, _GREENS and _FORCE");
+  if (!p || nprob < 1) return fail(FD_ERR_INVALID_ARG, "no problems given");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+    return fail(FD_ERR_INVALID_ARG, "autotune outside stream capture");
+  fd_options base{0, 0, 0, 0};
+  if (o) base = *o;
+  base.flags &= ~FD_REUSE_E;
+  {
+    Opts chk = resolve(&base, p, nprob, what);
+    int rc = validate(p, nprob, chk);
+    if (rc != FD_OK) return rc;
+  }
+  // s candidates within s * dk * radius(K) <= 6
+  double worst = 0.0;
+  for (int i = 0; i < nprob; ++i) {
+    std::vector<double> K((size_t)p[i].N * p[i].N);
+    hipError_t e = hipMemcpy(K.data(), p[i].K, K.size() * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("reading K: ") + hipGetErrorString(e));
+    worst = std::max(worst, std::fabs(p[i].dk) * radius_bound(K, p[i].N));
+  }
+  std::vector<int> s_list, seg_list;
+  if (base.s > 0) s_list.push_back(base.s);
+  else
+    for (int s : {4, 8, 16})
+      if (s == 4 || s * worst <= 6.0) s_list.push_back(s);
+  int maxNt = 1;
+  for (int i = 0; i < nprob; ++i) maxNt = std::max(maxNt, p[i].Nt);
+  if (what == FD_WHAT_FORCE || base.segments > 0) seg_list.push_back(std::max(base.segments, 1));
+  else
+    for (int g = 1; g <= 64 && g <= maxNt; g *= 2) seg_list.push_back(g);
+
+  // outputs and the largest workspace
+  size_t ws_need = 0;
+  for (int s : s_list)
+    for (int g : seg_list) {
+      fd_options c = base;
+      c.s = s;
+      c.segments = g;
+      Plan pl;
+      build_plan(p, nprob, resolve(&c, p, nprob, what), what, nullptr, pl);
+      ws_need = std::max(ws_need, pl.total);
+    }
+  size_t gsz = 0, fsz = 0;
+  for (int i = 0; i < nprob; ++i) {
+    gsz += (size_t)2 * p[i].N * p[i].N;
+    fsz += (size_t)p[i].Nt * p[i].N;
+  }
+  void *ws = nullptr, *ld = nullptr, *out = nullptr, *stv = nullptr;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  auto cleanup = [&]() {
+    if (ws) hipFree(ws);
+    if (ld) hipFree(ld);
+    if (out) hipFree(out);
+    if (stv) hipFree(stv);
+    if (ea) hipEventDestroy(ea);
+    if (eb) hipEventDestroy(eb);
+  };
+  const size_t out_bytes = sizeof(double) * (what == FD_WHAT_FORCE ? fsz : std::max<size_t>(gsz, 1));
+  if (hipMalloc(&ws, ws_need) != hipSuccess || hipMalloc(&ld, sizeof(double) * 2 * nprob) != hipSuccess ||
+      hipMalloc(&out, out_bytes) != hipSuccess || hipMalloc(&stv, sizeof(int32_t) * nprob) != hipSuccess ||
+      hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess) {
+    cleanup();
+    return fail(FD_ERR_HIP, "autotune: device allocation failed");
+  }
+  float bms = -1.0f;
+  fd_options bopt = base;
+  std::vector<int32_t> hst(nprob);
+  for (int s : s_list)
+    for (int g : seg_list) {
+      fd_options c = base;
+      c.s = s;
+      c.segments = g;
+      float times[3] = {1e30f, 1e30f, 1e30f};
+      bool ok = true;
+      for (int rep = -1; rep < 3 && ok; ++rep) {
+        if (rep >= 0) hipEventRecord(ea, st);
+        int rc;
+        if (what == FD_WHAT_FORCE)
+          rc = fd_force_batched(p, nprob, &c, (double*)ld, (double*)out, nullptr, ws, ws_need,
+                                (int32_t*)stv, stream);
+        else if (what == FD_WHAT_GREENS)
+          rc = fd_greens_batched(p, nprob, &c, (double*)ld, (double*)out, ws, ws_need,
+                                 (int32_t*)stv, stream);
+        else
+          rc = fd_logdet_batched(p, nprob, &c, (double*)ld, ws, ws_need, (int32_t*)stv, stream);
+        if (rc != FD_OK) { cleanup(); return rc; }
+        if (rep >= 0) {
+          hipEventRecord(eb, st);
+          hipEventSynchronize(eb);
+          hipEventElapsedTime(&times[rep], ea, eb);
+        }
+        if (hipMemcpy(hst.data(), stv, sizeof(int32_t) * nprob, hipMemcpyDeviceToHost) != hipSuccess) {
+          cleanup();
+          return fail(FD_ERR_HIP, "autotune: reading status failed");
+        }
+        for (int32_t v : hst) ok = ok && v >= 0;
+      }
+      if (!ok) continue;
+      std::sort(times, times + 3);
+      if (bms < 0.0f || times[1] < bms) {
+        bms = times[1];
+        bopt = c;
+      }
+    }
+  cleanup();
+  if (bms < 0.0f) return fail(FD_ERR_UNSUPPORTED, "autotune: no candidate finished without error");
+  tune_store(tune_key(p, nprob, what), TuneVal{bopt.s, bopt.segments, bms});
+  if (best) *best = bopt;
+  if (best_ms) *best_ms = bms;
+  return FD_OK;
+}
+
+int fd_tune_save(const char* path) {
+  if (!path) return fail(FD_ERR_INVALID_ARG, "path must not be NULL");
+  std::ofstream f(path);
+  if (!f) return fail(FD_ERR_INVALID_ARG, std::string("cannot write ") + path);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  f << "fdet-tune 1\n";
+  for (auto& e : g_tune)
+    f << e.first.what << ' ' << e.first.maxN << ' ' << e.first.maxNt << ' ' << e.first.nprob << ' '
+      << e.first.dk_micro << ' ' << e.second.s << ' ' << e.second.segments << ' ' << e.second.ms
+      << '\n';
+  return f ? FD_OK : fail(FD_ERR_INVALID_ARG, std::string("write failed: ") + path);
+}
+
+int fd_tune_load(const char* path) {
+  if (!path) return fail(FD_ERR_INVALID_ARG, "path must not be NULL");
+  std::ifstream f(path);
+  if (!f) return fail(FD_ERR_INVALID_ARG, std::string("cannot read ") + path);
+  std::string magic;
+  int ver = 0;
+  f >> magic >> ver;
+  if (magic != "fdet-tune" || ver != 1) return fail(FD_ERR_INVALID_ARG, "not an fdet tune file");
+  int n = 0;
+  TuneKey k;
+  TuneVal v;
+  while (f >> k.what >> k.maxN >> k.maxNt >> k.nprob >> k.dk_micro >> v.s >> v.segments >> v.ms) {
+    if (k.what < FD_WHAT_LOGDET || k.what > FD_WHAT_FORCE || v.s < 1 || v.segments < 1 ||
+        k.maxN < 1 || k.maxN > FD_MAX_N)
+      return fail(FD_ERR_INVALID_ARG, "malformed tune entry");
+    tune_store(k, v);
+    ++n;
+  }
+  if (!f.eof()) return fail(FD_ERR_INVALID_ARG, "malformed tune file");
+  return n;
+}
+
+int fd_tune_clear(void) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune.clear();
+  return FD_OK;
 }
 
 const char* fd_strerror(int code) {

@@ -724,6 +724,7 @@ extern "C" hipError_t fdet_launch_items(int maxn, int kind, const fdet::Prob* pr
   if (nitems <= 0) return hipSuccess;
   if (maxn <= 32) return launch_kind<32>(kind, probs, items, nitems, st);
   if (maxn <= 64) return launch_kind<64>(kind, probs, items, nitems, st);
+  if (maxn <= 80) return launch_kind<80>(kind, probs, items, nitems, st);
   if (maxn <= 96) return launch_kind<96>(kind, probs, items, nitems, st);
   if (maxn <= 128) return launch_kind<128>(kind, probs, items, nitems, st);
   return launch_kind<512>(kind, probs, items, nitems, st);

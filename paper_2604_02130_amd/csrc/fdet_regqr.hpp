@@ -108,43 +108,46 @@ __device__ __forceinline__ double pick(const double* a, int m) {
   return v;
 }
 
-// The same reflector on the CPL columns of a lane, reductions interleaved.
-// Row blocks m < m_lo (all rows < 16 m_lo, where the reflector is zero) and
-// column slots q < q_lo are skipped; both bounds are wave-uniform, so the
-// skips are scalar branches, not lane masks.
-template <int CPL, int RPL>
+// compile-time loop: f(IC<B>{}), f(IC<B+1>{}), ..., f(IC<E-1>{})
+template <int V>
+struct IC {
+  static constexpr int value = V;
+};
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(IC<B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// The same reflector on the column slots q >= QLO of a lane, rows in blocks
+// m >= MLO (the reflector is zero on rows < 16 MLO), reductions interleaved.
+// Both bounds are template constants: the skipped work is not emitted.
+template <int CPL, int RPL, int MLO, int QLO>
 __device__ __forceinline__ void rq_reflect_all(double beta, const double* ur, const double* ui,
-                                               double (*yr)[RPL], double (*yi)[RPL], int m_lo,
-                                               int q_lo) {
-  m_lo = __builtin_amdgcn_readfirstlane(m_lo);
-  q_lo = __builtin_amdgcn_readfirstlane(q_lo);
+                                               double (*yr)[RPL], double (*yi)[RPL]) {
   double wr[CPL], wi[CPL];
 #pragma unroll
-  for (int q = 0; q < CPL; ++q) {
+  for (int q = QLO; q < CPL; ++q) {
     double sr = 0.0, si = 0.0;
-    if (q >= q_lo) {
 #pragma unroll
-      for (int m = 0; m < RPL; ++m) {
-        if (m < m_lo) continue;
-        sr += ur[m] * yr[q][m] + ui[m] * yi[q][m];
-        si += ur[m] * yi[q][m] - ui[m] * yr[q][m];
-      }
+    for (int m = MLO; m < RPL; ++m) {
+      sr += ur[m] * yr[q][m] + ui[m] * yi[q][m];
+      si += ur[m] * yi[q][m] - ui[m] * yr[q][m];
     }
     wr[q] = sr;
     wi[q] = si;
   }
 #pragma unroll
-  for (int q = 0; q < CPL; ++q) {
-    if (q < q_lo) continue;
+  for (int q = QLO; q < CPL; ++q) {
     wr[q] = beta * red16(wr[q]);
     wi[q] = beta * red16(wi[q]);
   }
 #pragma unroll
-  for (int q = 0; q < CPL; ++q) {
-    if (q < q_lo) continue;
+  for (int q = QLO; q < CPL; ++q) {
 #pragma unroll
-    for (int m = 0; m < RPL; ++m) {
-      if (m < m_lo) continue;
+    for (int m = MLO; m < RPL; ++m) {
       yr[q][m] -= ur[m] * wr[q] - ui[m] * wi[q];
       yi[q][m] -= ur[m] * wi[q] + ui[m] * wr[q];
     }
@@ -166,9 +169,15 @@ __device__ __forceinline__ void rq_reflect_all(double beta, const double* ur, co
 // triangle (rows >= j, row j holding u0).  Below the diagonal W holds no
 // reflector data on this path; consumers read the triangle.
 //
-// Per column: the wave holding the column forms the reflector (exact norm)
-// and publishes it (one barrier); every column then takes the update
-// a <- a - beta u (u^H a), branch-free over the columns of a lane.
+// The columns enter the registers already in pivot order: slot q of group g
+// holds position k = g + 32 q.  Step j runs in row phase JB = j / 16, where
+// the reflector is zero on row blocks m < JB and every slot q < JB / 2 holds
+// only positions < j (finished: their rows >= j are never read again), so
+// both are left out at compile time.
+//
+// Per column: the wave holding position j forms the reflector (exact norm)
+// and publishes it (one barrier); the remaining slots then take the update
+// a <- a - beta u (u^H a).
 // ---------------------------------------------------------------------------
 template <int NC>
 __device__ void rq_qrp(CMat W, int N, const double* keys, SmemC<NC>& S) {
@@ -178,7 +187,7 @@ __device__ void rq_qrp(CMat W, int N, const double* keys, SmemC<NC>& S) {
   double* tr = S.big;
   double* ti = S.big + BigLds<NC>::TRI;
 
-  double ar[CPL][RPL], ai[CPL][RPL];
+  // ---- pivot keys from memory
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
     const int c = grp + 32 * q;
@@ -186,10 +195,10 @@ __device__ void rq_qrp(CMat W, int N, const double* keys, SmemC<NC>& S) {
 #pragma unroll
     for (int m = 0; m < RPL; ++m) {
       const int r = l16 + 16 * m;
-      const bool in = c < N && r < N;
-      ar[q][m] = in ? W.r(r, c) : 0.0;
-      ai[q][m] = in ? W.m(r, c) : 0.0;
-      s += ar[q][m] * ar[q][m] + ai[q][m] * ai[q][m];
+      if (c < N && r < N) {
+        const double xr = W.r(r, c), xi = W.m(r, c);
+        s += xr * xr + xi * xi;
+      }
     }
     s = red16(s);
     if (c < N && l16 == 0) S.v3[c] = sqrt(s) * (keys ? keys[c] : 1.0);
@@ -208,124 +217,126 @@ __device__ void rq_qrp(CMat W, int N, const double* keys, SmemC<NC>& S) {
     S.csp[pos] = keys ? keys[c] : 1.0;
   }
   if (tid == 0) S.nref = 0;
-  for (int r = tid; r < 2 * BigLds<NC>::UB; r += WG) {
-    (&S.ubr[0][0])[r] = 0.0;
-    (&S.ubi[0][0])[r] = 0.0;
-  }
   __syncthreads();
 
-  for (int j = 0; j < N; ++j) {
-    const int p = S.piv[j];
-    const int buf = j & 1;
-    // ---- the wave holding column p forms the reflector and publishes it
-    if (wave == ((p & 31) >> 2)) {
-      const int qp = p >> 5;
-      const int m_lo = j >> 4;
-      double xr = 0.0, xi = 0.0, s = 0.0;
-#pragma unroll
-      for (int q = 0; q < CPL; ++q) {
-        if (q != qp) continue;
-        xr = pick<RPL>(ar[q], m_lo);
-        xi = pick<RPL>(ai[q], m_lo);
-#pragma unroll
-        for (int m = 0; m < RPL; ++m) {
-          const int r = l16 + 16 * m;
-          const double keep = (r >= j) ? 1.0 : 0.0;
-          s += keep * (ar[q][m] * ar[q][m] + ai[q][m] * ai[q][m]);
-        }
-      }
-      // every group of the wave reduced its own slot qp; take the owner's
-      const double alpha = readlane_d(sqrt(red16(s)), 16 * (p & 3));
-      const int src = 16 * (p & 3) + (j & 15);
-      const double a0r = readlane_d(xr, src);
-      const double a0i = readlane_d(xi, src);
-      const double aa0 = sqrt(a0r * a0r + a0i * a0i);
-      double er = 1.0, ei = 0.0;
-      if (aa0 > 0.0) { const double inv = 1.0 / aa0; er = a0r * inv; ei = a0i * inv; }
-      const bool refl = alpha > 0.0;
-      const double beta = refl ? 1.0 / (alpha * (alpha + aa0)) : 0.0;
-      const double u0r = a0r + er * alpha, u0i = a0i + ei * alpha;
-      if (grp == (p & 31)) {
-#pragma unroll
-        for (int q = 0; q < CPL; ++q) {
-          if (q != qp) continue;
-#pragma unroll
-          for (int m = 0; m < RPL; ++m) {
-            const int r = l16 + 16 * m;
-            double vr = (r > j) ? ar[q][m] : 0.0;
-            double vi = (r > j) ? ai[q][m] : 0.0;
-            if (r == j) { vr = u0r; vi = u0i; }
-            S.ubr[buf][r] = vr;
-            S.ubi[buf][r] = vi;
-            if (r >= j && r < N) {
-              tr[tri_lo<NC>(r, j)] = vr;
-              ti[tri_lo<NC>(r, j)] = vi;
-            }
-          }
-        }
-      }
-      if (lane == 0) {
-        S.rdr[j] = refl ? -er * alpha : 0.0;
-        S.rdi[j] = refl ? -ei * alpha : 0.0;
-        S.u0r[j] = refl ? u0r : 0.0;
-        S.u0i[j] = refl ? u0i : 0.0;
-        S.beta[j] = beta;
-        if (refl) S.nref += 1;
-      }
-    }
-    __syncthreads();
-
-    // ---- every column of every lane takes a <- a - beta u (u^H a).  The
-    // pivot column becomes (R_jj, ~0, ...); columns already factorised only
-    // change below their diagonal, which no consumer reads; u is zero above
-    // row j, so no row above j changes.
-    const double beta = S.beta[j];
-    double ur[RPL], ui[RPL];
-#pragma unroll
-    for (int m = 0; m < RPL; ++m) {
-      ur[m] = S.ubr[buf][l16 + 16 * m];
-      ui[m] = S.ubi[buf][l16 + 16 * m];
-    }
-    rq_reflect_all<CPL, RPL>(beta, ur, ui, ar, ai, 0, 0);
-  }
-  __syncthreads();
-
-  // the diagonal of R exactly as formed (the in-register value carries the
-  // rounding of the reflector applied to its own column)
+  // ---- registers in pivot order
+  double ar[CPL][RPL], ai[CPL][RPL];
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
-    const int c = grp + 32 * q;
-    if (c >= N) continue;
-    const int pos = S.pinv[c];
-#pragma unroll
-    for (int m = 0; m < RPL; ++m) {
-      if (l16 + 16 * m == pos) { ar[q][m] = S.rdr[pos]; ai[q][m] = S.rdi[pos]; }
-    }
-  }
-
-  // ---- write R back in pivoted column order
-#pragma unroll
-  for (int q = 0; q < CPL; ++q) {
-    const int c = grp + 32 * q;
-    if (c >= N) continue;
-    const int pos = S.pinv[c];
+    const int k = grp + 32 * q;
+    const int c = (k < N) ? S.piv[k] : 0;
 #pragma unroll
     for (int m = 0; m < RPL; ++m) {
       const int r = l16 + 16 * m;
-      if (r < N) { W.r(r, pos) = ar[q][m]; W.m(r, pos) = ai[q][m]; }
+      const bool in = k < N && r < N;
+      ar[q][m] = in ? W.r(r, c) : 0.0;
+      ai[q][m] = in ? W.m(r, c) : 0.0;
+    }
+  }
+
+  static_for<0, RPL>([&](auto jbc) {
+    constexpr int JB = decltype(jbc)::value;
+    constexpr int QLO = JB / 2;
+    const int jend = min(16 * JB + 16, N);
+    for (int j = 16 * JB; j < jend; ++j) {
+      const int buf = j & 1;
+      const int og = j & 31, qp = j >> 5;
+      // ---- the wave holding position j forms the reflector and publishes it
+      if (wave == (og >> 2)) {
+        double xr = 0.0, xi = 0.0, s = 0.0;
+#pragma unroll
+        for (int q = QLO; q < CPL; ++q) {
+          if (q != qp) continue;
+          xr = ar[q][JB];
+          xi = ai[q][JB];
+#pragma unroll
+          for (int m = JB; m < RPL; ++m) {
+            const int r = l16 + 16 * m;
+            const double keep = (r >= j) ? 1.0 : 0.0;
+            s += keep * (ar[q][m] * ar[q][m] + ai[q][m] * ai[q][m]);
+          }
+        }
+        // every group of the wave reduced its own slot qp; take the owner's
+        const double alpha = readlane_d(sqrt(red16(s)), 16 * (og & 3));
+        const int src = 16 * (og & 3) + (j & 15);
+        const double a0r = readlane_d(xr, src);
+        const double a0i = readlane_d(xi, src);
+        const double aa0 = sqrt(a0r * a0r + a0i * a0i);
+        double er = 1.0, ei = 0.0;
+        if (aa0 > 0.0) { const double inv = 1.0 / aa0; er = a0r * inv; ei = a0i * inv; }
+        const bool refl = alpha > 0.0;
+        const double beta = refl ? 1.0 / (alpha * (alpha + aa0)) : 0.0;
+        const double u0r = a0r + er * alpha, u0i = a0i + ei * alpha;
+        if (grp == og) {
+#pragma unroll
+          for (int q = QLO; q < CPL; ++q) {
+            if (q != qp) continue;
+#pragma unroll
+            for (int m = JB; m < RPL; ++m) {
+              const int r = l16 + 16 * m;
+              double vr = (r > j) ? ar[q][m] : 0.0;
+              double vi = (r > j) ? ai[q][m] : 0.0;
+              if (r == j) { vr = u0r; vi = u0i; }
+              S.ubr[buf][r] = vr;
+              S.ubi[buf][r] = vi;
+              if (r >= j && r < N) {
+                tr[tri_lo<NC>(r, j)] = vr;
+                ti[tri_lo<NC>(r, j)] = vi;
+              }
+            }
+          }
+        }
+        if (lane == 0) {
+          S.rdr[j] = refl ? -er * alpha : 0.0;
+          S.rdi[j] = refl ? -ei * alpha : 0.0;
+          S.u0r[j] = refl ? u0r : 0.0;
+          S.u0i[j] = refl ? u0i : 0.0;
+          S.beta[j] = beta;
+          if (refl) S.nref += 1;
+        }
+      }
+      __syncthreads();
+
+      // ---- the open slots take a <- a - beta u (u^H a).  u is zero above
+      // row j, so rows above j do not change; positions <= j only change
+      // below their diagonal, which no consumer reads.
+      const double beta = S.beta[j];
+      double ur[RPL], ui[RPL];
+#pragma unroll
+      for (int m = JB; m < RPL; ++m) {
+        ur[m] = S.ubr[buf][l16 + 16 * m];
+        ui[m] = S.ubi[buf][l16 + 16 * m];
+      }
+      rq_reflect_all<CPL, RPL, JB, QLO>(beta, ur, ui, ar, ai);
+    }
+  });
+  __syncthreads();
+
+  // ---- R back to W (position k = grp + 32 q), with the diagonal exactly as
+  // formed (the in-register value carries the rounding of the reflector
+  // applied to its own column)
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int k = grp + 32 * q;
+    if (k >= N) continue;
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      const int r = l16 + 16 * m;
+      if (r == k) { ar[q][m] = S.rdr[k]; ai[q][m] = S.rdi[k]; }
+      if (r < N) { W.r(r, k) = ar[q][m]; W.m(r, k) = ai[q][m]; }
     }
   }
   __syncthreads();
 }
 
-// reflector j (rows of this lane) from the LDS triangle
-template <int NC, int RPL>
+// reflector j (rows of this lane in blocks >= MLO) from the LDS triangle
+template <int NC, int RPL, int MLO>
 __device__ __forceinline__ void rq_load_u(const SmemC<NC>& S, int N, int j, int l16, double* ur,
                                           double* ui) {
   const double* tr = S.big;
   const double* ti = S.big + BigLds<NC>::TRI;
 #pragma unroll
-  for (int m = 0; m < RPL; ++m) {
+  for (int m = MLO; m < RPL; ++m) {
     const int r = l16 + 16 * m;
     const bool in = r >= j && r < N;
     ur[m] = in ? tr[tri_lo<NC>(r, j)] : 0.0;
@@ -333,29 +344,11 @@ __device__ __forceinline__ void rq_load_u(const SmemC<NC>& S, int N, int j, int 
   }
 }
 
-// y <- (I - beta u u^H) y on the rows of one lane group (u zero above m_lo)
-template <int RPL>
-__device__ __forceinline__ void rq_reflect(double beta, const double* ur, const double* ui,
-                                           double* yr, double* yi, int m_lo) {
-  double sr = 0.0, si = 0.0;
-#pragma unroll
-  for (int m = 0; m < RPL; ++m) {
-    if (m < m_lo) continue;
-    sr += ur[m] * yr[m] + ui[m] * yi[m];
-    si += ur[m] * yi[m] - ui[m] * yr[m];
-  }
-  const double wr = beta * red16(sr), wi = beta * red16(si);
-#pragma unroll
-  for (int m = 0; m < RPL; ++m) {
-    if (m < m_lo) continue;
-    yr[m] -= ur[m] * wr - ui[m] * wi;
-    yi[m] -= ur[m] * wi + ui[m] * wr;
-  }
-}
-
 // Q = H_0 ... H_{N-1} written to Q (backward accumulation).  Groups own
-// whole columns and read reflectors from LDS: no barrier inside.  The caller
-// synchronises after (Q complete).
+// whole columns and read reflectors from LDS: no barrier inside.  When H_j is
+// applied, columns c < j of the partial product are still e_c and every
+// column is zero on rows < j, so slots q < JB / 2 and row blocks < JB (JB =
+// j / 16) are left out.  The caller synchronises after (Q complete).
 template <int NC>
 __device__ void rq_form_q(int N, CMat Q, const SmemC<NC>& S) {
   constexpr int CPL = RegClass<NC>::CPL, RPL = RegClass<NC>::RPL;
@@ -368,15 +361,17 @@ __device__ void rq_form_q(int N, CMat Q, const SmemC<NC>& S) {
 #pragma unroll
     for (int m = 0; m < RPL; ++m) { qr[q][m] = (l16 + 16 * m == c) ? 1.0 : 0.0; qi[q][m] = 0.0; }
   }
-  for (int j = N - 1; j >= 0; --j) {
-    const double beta = S.beta[j];
-    if (beta == 0.0) continue;
-    double ur[RPL], ui[RPL];
-    rq_load_u<NC, RPL>(S, N, j, l16, ur, ui);
-    // columns c < j of Q are still unit vectors with zero rows >= j: slots
-    // whose 32 columns all lie below j are skipped, the rest are updated
-    rq_reflect_all<CPL, RPL>(beta, ur, ui, qr, qi, 0, 0);
-  }
+  static_for<0, RPL>([&](auto kc) {
+    constexpr int JB = RPL - 1 - decltype(kc)::value;
+    constexpr int QLO = JB / 2;
+    for (int j = min(16 * JB + 15, N - 1); j >= 16 * JB; --j) {
+      const double beta = S.beta[j];
+      if (beta == 0.0) continue;
+      double ur[RPL], ui[RPL];
+      rq_load_u<NC, RPL, JB>(S, N, j, l16, ur, ui);
+      rq_reflect_all<CPL, RPL, JB, QLO>(beta, ur, ui, qr, qi);
+    }
+  });
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
     const int c = grp + 32 * q;
@@ -390,8 +385,9 @@ __device__ void rq_form_q(int N, CMat Q, const SmemC<NC>& S) {
 }
 
 // Y <- R^{-1} Q^H Y for the factor of rq_qrp; Y is loaded from and stored
-// to Yg.  Q^H is applied from the LDS reflectors; then R (from W) replaces
-// them in the LDS triangle for the back substitution.
+// to Yg.  Q^H is applied from the LDS reflectors (H_j leaves rows < j alone);
+// then R (from W) replaces them in the LDS triangle for the back
+// substitution, which at row i only touches rows <= i.
 template <int NC>
 __device__ void rq_solve(CMat W, int N, CMat Yg, SmemC<NC>& S) {
   constexpr int CPL = RegClass<NC>::CPL, RPL = RegClass<NC>::RPL;
@@ -410,13 +406,17 @@ __device__ void rq_solve(CMat W, int N, CMat Yg, SmemC<NC>& S) {
       yi[q][m] = in ? Yg.m(r, c) : 0.0;
     }
   }
-  for (int j = 0; j < N; ++j) {
-    const double beta = S.beta[j];
-    if (beta == 0.0) continue;
-    double ur[RPL], ui[RPL];
-    rq_load_u<NC, RPL>(S, N, j, l16, ur, ui);
-    rq_reflect_all<CPL, RPL>(beta, ur, ui, yr, yi, 0, 0);
-  }
+  static_for<0, RPL>([&](auto jbc) {
+    constexpr int JB = decltype(jbc)::value;
+    const int jend = min(16 * JB + 16, N);
+    for (int j = 16 * JB; j < jend; ++j) {
+      const double beta = S.beta[j];
+      if (beta == 0.0) continue;
+      double ur[RPL], ui[RPL];
+      rq_load_u<NC, RPL, JB>(S, N, j, l16, ur, ui);
+      rq_reflect_all<CPL, RPL, JB, 0>(beta, ur, ui, yr, yi);
+    }
+  });
   __syncthreads();
   // R into the LDS triangle (column i, rows 0..i)
   double* tr = S.big;
@@ -426,34 +426,36 @@ __device__ void rq_solve(CMat W, int N, CMat Yg, SmemC<NC>& S) {
     if (r <= i) { tr[tri_up(r, i)] = W.r(r, i); ti[tri_up(r, i)] = W.m(r, i); }
   }
   __syncthreads();
-  for (int i = N - 1; i >= 0; --i) {
-    const double dr = S.rdr[i], di = S.rdi[i];
-    const double den = dr * dr + di * di;
-    const int mi = i >> 4, li = i & 15;
-    double cr[RPL], ci[RPL];
+  static_for<0, RPL>([&](auto kc) {
+    constexpr int IB = RPL - 1 - decltype(kc)::value;   // rows i in block IB
+    for (int i = min(16 * IB + 15, N - 1); i >= 16 * IB; --i) {
+      const double dr = S.rdr[i], di = S.rdi[i];
+      const double den = dr * dr + di * di;
+      const int li = i & 15;
+      double cr[IB + 1], ci[IB + 1];
 #pragma unroll
-    for (int m = 0; m < RPL; ++m) {
-      const int r = l16 + 16 * m;
-      const bool in = r < i;
-      cr[m] = in ? tr[tri_up(r, i)] : 0.0;
-      ci[m] = in ? ti[tri_up(r, i)] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < CPL; ++q) {
-      const double vr = __shfl(pick<RPL>(yr[q], mi), gbase + li, 64);
-      const double vi = __shfl(pick<RPL>(yi[q], mi), gbase + li, 64);
-      const double zr = (vr * dr + vi * di) / den;
-      const double zi = (vi * dr - vr * di) / den;
-#pragma unroll
-      for (int m = 0; m < RPL; ++m) {
-        if (16 * m > i) continue;
+      for (int m = 0; m <= IB; ++m) {
         const int r = l16 + 16 * m;
-        if (r == i) { yr[q][m] = zr; yi[q][m] = zi; }
-        yr[q][m] -= cr[m] * zr - ci[m] * zi;
-        yi[q][m] -= cr[m] * zi + ci[m] * zr;
+        const bool in = r < i;
+        cr[m] = in ? tr[tri_up(r, i)] : 0.0;
+        ci[m] = in ? ti[tri_up(r, i)] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const double vr = __shfl(yr[q][IB], gbase + li, 64);
+        const double vi = __shfl(yi[q][IB], gbase + li, 64);
+        const double zr = (vr * dr + vi * di) / den;
+        const double zi = (vi * dr - vr * di) / den;
+#pragma unroll
+        for (int m = 0; m <= IB; ++m) {
+          const int r = l16 + 16 * m;
+          if (r == i) { yr[q][m] = zr; yi[q][m] = zi; }
+          yr[q][m] -= cr[m] * zr - ci[m] * zi;
+          yi[q][m] -= cr[m] * zi + ci[m] * zr;
+        }
       }
     }
-  }
+  });
 #pragma unroll
   for (int q = 0; q < CPL; ++q) {
     const int c = grp + 32 * q;
