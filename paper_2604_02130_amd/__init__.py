@@ -524,7 +524,7 @@ def _logdet_function():
                 ctx.save_for_backward(torch.view_as_real(F))
             else:
                 ld = logdet(K, phi.detach(), dk, s=s)
-            return ld
+            return ld.clone()
 
         @staticmethod
         def backward(ctx, g):

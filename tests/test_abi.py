@@ -108,3 +108,50 @@ def test_python_layer_requires_gpu_tensors():
     phi = torch.zeros((2, 4), dtype=torch.float64)
     with pytest.raises(fd.FdError):
         fd.greens(K, phi, 0.1)
+
+
+def test_tune_table_roundtrip(lib, tmp_path):
+    """The tuned-choice table loads, saves and steers the default segments."""
+    fd.tune_clear()
+    p = prob(128, 16)
+    auto = fd.workspace_bytes([p], fd.FD_WHAT_GREENS)
+    eight = fd.workspace_bytes([p], fd.FD_WHAT_GREENS, segments=8)
+    assert auto != eight
+    src = tmp_path / "t.txt"
+    # what maxN maxNt nprob dk_micro s segments ms
+    src.write_text("fdet-tune 1\n1 128 16 1 125000 4 8 1.5\n2 18 16 1 125000 16 1 0.25\n")
+    assert fd.tune_load(str(src)) == 2
+    assert fd.workspace_bytes([p], fd.FD_WHAT_GREENS) == eight
+    out = tmp_path / "u.txt"
+    fd.tune_save(str(out))
+    lines = out.read_text().split("\n")
+    assert lines[0] == "fdet-tune 1"
+    assert "1 128 16 1 125000 4 8 1.5" in lines
+    fd.tune_clear()
+    assert fd.workspace_bytes([p], fd.FD_WHAT_GREENS) == auto
+    bad = tmp_path / "bad.txt"
+    bad.write_text("fdet-tune 1\n1 128 16 1 125000 0 8 1.5\n")
+    with pytest.raises(fd.FdError):
+        fd.tune_load(str(bad))
+    bad.write_text("something else\n")
+    with pytest.raises(fd.FdError):
+        fd.tune_load(str(bad))
+    fd.tune_clear()
+
+
+def test_plan_and_autotune_reject_bad_arguments(lib):
+    p = prob()
+    o = fd.FdOptions(0, 0, 0, 0)
+    h = ctypes.c_void_p(0)
+    assert lib.fd_plan_create(fd.FD_WHAT_GREENS, ctypes.byref(p), 1, ctypes.byref(o), 0x10, 0x20,
+                              None, None, 0x10000, 1 << 30, 0x40, None, None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_plan_create(fd.FD_WHAT_UDV, ctypes.byref(p), 1, ctypes.byref(o), 0x10, 0x20,
+                              None, None, 0x10000, 1 << 30, 0x40, None,
+                              ctypes.byref(h)) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_plan_create(fd.FD_WHAT_FORCE, ctypes.byref(p), 1, ctypes.byref(o), 0x10, None,
+                              None, None, 0x10000, 1 << 30, 0x40, None,
+                              ctypes.byref(h)) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_plan_launch(None, None) == fd.FD_ERR_INVALID_ARG
+    best = fd.FdOptions()
+    assert lib.fd_autotune(fd.FD_WHAT_UDV, ctypes.byref(p), 1, None, None, ctypes.byref(best),
+                           None) == fd.FD_ERR_INVALID_ARG

@@ -5,6 +5,7 @@ imaginary part compared modulo 2 pi) <= 1e-10, max-abs error of G <= 1e-10,
 max-abs error of the force against the oracle gradient <= 1e-10, and against
 central finite differences (h = 1e-6) <= 1e-6.
 """
+import functools
 import math
 
 import numpy as np
@@ -154,13 +155,20 @@ def test_plain_det_workload(fd):
     check_ld(ld2, lo)
 
 
-@pytest.mark.parametrize("seg", [1, 8])
+@functools.lru_cache(maxsize=None)
+def low_temperature_reference():
+    w = WORKLOADS["lowT_L6"]
+    return O.sporadic_logdet_greens(w.K(), w.dk, w.phi(), 1)
+
+
+@pytest.mark.parametrize("seg", [1, 8, 32, 0])
 def test_low_temperature_workload(fd, seg):
-    """L = 6 (N = 72), N_t = 256, beta = 32, s = 8: the full-size single config."""
+    """L = 6 (N = 72), N_t = 256, beta = 32, s = 8: the full-size single config
+    (segments 0 = the library's default choice)."""
     w = WORKLOADS["lowT_L6"]
     K, phi = w.K(), w.phi()
     ld, G = gpu_greens(fd, K, phi, w.dk, s=w.s, segments=seg)
-    lo, Go = O.sporadic_logdet_greens(K, w.dk, phi, 1)
+    lo, Go = low_temperature_reference()
     check_ld(ld, lo)
     check_G(G, Go)
     # invariants of the bipartite, traceless honeycomb K
