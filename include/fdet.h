@@ -81,10 +81,12 @@ typedef struct {
                            carried across c slices, which amplifies rounding
                            like cond(B)^c: keep c*dk*spectral_radius(K) <= 6. */
   int32_t segments;     /* det/G: independent time segments per problem that
-                           are combined by stabilised products (0 = the tuned
-                           value for this shape, else a power of two near
-                           Nt/8, at most 32, fewer when the batch alone gives
-                           every compute unit two workgroups)                  */
+                           are combined by stabilised products.  0 = the tuned
+                           value for this shape; else, for one problem, a
+                           power of two near Nt/8 (at most 32), and for a
+                           batch, per problem in proportion to its chain work
+                           max(N,32)^2 Nt, so that the batch's chains fill the
+                           compute units about once (at most min(32, Nt/4))  */
   int32_t flags;        /* FD_REUSE_E                                          */
 } fd_options;
 

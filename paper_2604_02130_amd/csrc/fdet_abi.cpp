@@ -98,17 +98,28 @@ int pow2_floor(int x) {
   return r;
 }
 
-// Segments when neither the caller nor the tuner chose: a chain segment of
-// about 8 slices per QR interval balances chain and combine latency for one
-// problem; batches that already give every compute unit a workgroup per
-// problem need fewer segments.
+// Segments of a single problem when neither the caller nor the tuner chose:
+// a chain segment of about 8 slices per QR interval balances chain and
+// combine latency.
 int default_segments(const fd_problem* p, int nprob) {
   int maxNt = 1;
   for (int i = 0; i < nprob; ++i) maxNt = std::max(maxNt, p[i].Nt);
-  int seg = std::min(32, pow2_floor(std::max(1, maxNt / 8)));
-  const int target = 512;   // two workgroups per compute unit
-  if (nprob * seg > target) seg = std::max(1, pow2_floor(std::max(1, target / nprob)));
-  return seg;
+  return std::min(32, pow2_floor(std::max(1, maxNt / 8)));
+}
+
+int device_cu_count() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+    return 256;
+  return n;
+}
+
+// Chain work of one problem in arbitrary units: a slice costs about
+// max(N, 32)^2 on one workgroup (latency-bound below N = 128).
+double chain_cost(const fd_problem& p) {
+  const double m = std::max(p.N, 32);
+  return m * m * (double)p.Nt;
 }
 
 // Options of one call: explicit fields win, then a tuned entry for this
@@ -127,17 +138,31 @@ Opts resolve(const fd_options* o, const fd_problem* p = nullptr, int nprob = 0, 
       if (r.s == 0) r.s = v.s;
       if (r.segments == 0) r.segments = v.segments;
     }
-    if (r.segments == 0) r.segments = default_segments(p, nprob);
+    if (r.segments == 0 && nprob == 1) r.segments = default_segments(p, nprob);
   }
   if (r.s == 0) r.s = 8;
   return r;
 }
 
-// Number of independent time segments of one problem (det / G / UDV).
-int segments_for(const fd_problem& p, const Opts& o) {
-  int nseg = o.segments > 0 ? o.segments : 1;
-  nseg = std::min(nseg, p.Nt);
-  return std::max(nseg, 1);
+// Time segments of every problem (det / G / UDV).  Explicit or tuned: the
+// same count for all.  Automatic for a batch: each problem gets segments in
+// proportion to its chain work, so that the chains of the whole batch fill
+// the compute units about once and no long problem is left running alone.
+std::vector<int> plan_segments(const fd_problem* p, int nprob, const Opts& o) {
+  std::vector<int> seg(nprob, 1);
+  if (o.segments > 0) {
+    for (int i = 0; i < nprob; ++i) seg[i] = std::max(1, std::min(o.segments, p[i].Nt));
+    return seg;
+  }
+  double total = 0.0;
+  for (int i = 0; i < nprob; ++i) total += chain_cost(p[i]);
+  const double target = total / device_cu_count();
+  for (int i = 0; i < nprob; ++i) {
+    const int cap = std::max(1, std::min(32, p[i].Nt / 4));
+    const int want = (int)std::ceil(chain_cost(p[i]) / target - 1e-9);
+    seg[i] = std::max(1, std::min(cap, want));
+  }
+  return seg;
 }
 
 // Offsets are computed against `base`; with base == nullptr only sizes matter.
@@ -210,7 +235,7 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   size_t nitems = 0;
   // count items to size the descriptor region
   const bool force = what == FD_WHAT_FORCE;
-  std::vector<int> nseg(nprob), nck(nprob);
+  std::vector<int> nseg = plan_segments(p, nprob, o), nck(nprob);
   int maxlev = 0;
   for (int i = 0; i < nprob; ++i) {
     pl.maxN = std::max(pl.maxN, p[i].N);
@@ -218,7 +243,6 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
       nck[i] = (p[i].Nt + o.c - 1) / o.c;
       nitems += 2 + 2 + 1 + nck[i];
     } else {
-      nseg[i] = segments_for(p[i], o);
       int lev = 0;
       while ((1 << lev) < nseg[i]) ++lev;
       maxlev = std::max(maxlev, lev);
@@ -342,6 +366,14 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
       }
     }
   }
+  // longest work per workgroup first: the dispatcher hands out workgroups in
+  // order, so the batch's long chains start first (longest-processing-time)
+  auto work = [&](const Item& it) {
+    const double m = std::max(pl.probs[it.prob].N, 32);
+    return m * m * (double)(it.t1 - it.t0);
+  };
+  std::stable_sort(chain.begin(), chain.end(),
+                   [&](const Item& a, const Item& b) { return work(a) > work(b); });
   pl.phases.clear();
   if (!expm.empty()) pl.phases.push_back(expm);
   pl.phases.push_back(chain);

@@ -22,6 +22,12 @@ namespace fdet {
 
 constexpr double kPi = 3.14159265358979323846;
 
+// 1 / k!, k = 0..16 (each quotient rounded once at compile time)
+__constant__ double kInvFact[17] = {
+    1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0,
+    1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0, 1.0 / 479001600.0,
+    1.0 / 6227020800.0, 1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0};
+
 // Size classes: N <= NC.  Classes up to 128 keep the matrix being factorised
 // in registers and stage products through LDS (fdet_regqr.hpp); the 512
 // class works on device memory (fdet_device.hpp).
@@ -203,10 +209,10 @@ __device__ void udv_new_t(CMat W, int N, int Np, LT2 t2, CMat To, SmemC<NC>& S) 
 // IK_CHAIN
 // ---------------------------------------------------------------------------
 template <int NC>
-__device__ void do_chain(const Prob& P, const Item& it, SmemC<NC>& S);
+__device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC>& S);
 
 template <int NC>
-__device__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
+__device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
                          bool user_out, SmemC<NC>& S);
 
 template <int NC>
@@ -246,7 +252,7 @@ __device__ void save_ckpt(double* dst, CMat X, CMat T, const double* D, int N, i
 }
 
 template <int NC>
-__device__ void do_chain(const Prob& P, const Item& it, SmemC<NC>& S) {
+__device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const size_t cd = cmat_doubles(Np);
   CMat X = cmat_at(it.a.X, Np), T = cmat_at(it.a.T, Np);
@@ -358,7 +364,7 @@ __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMa
 }
 
 template <int NC>
-__device__ void do_combine(const Prob& P, const Item& it, SmemC<NC>& S) {
+__device__ __forceinline__ void do_combine(const Prob& P, const Item& it, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const size_t cd = cmat_doubles(Np);
   CMat W = cmat_at(it.scr, Np), Qb = cmat_at(it.scr + cd, Np);
@@ -384,7 +390,7 @@ __device__ void do_combine(const Prob& P, const Item& it, SmemC<NC>& S) {
 // This is Sec. 7 steps 4-6 with the rows of 1 + D T X divided by D_b first.
 // ---------------------------------------------------------------------------
 template <int NC>
-__device__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
+__device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
                          bool user_out, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   CMat X = cmat_at(U.X, Np), T = cmat_at(U.T, Np);
@@ -492,7 +498,7 @@ __device__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool 
 // IK_FORCE
 // ---------------------------------------------------------------------------
 template <int NC>
-__device__ void do_force(const Prob& P, const Item& it, SmemC<NC>& S) {
+__device__ __forceinline__ void do_force(const Prob& P, const Item& it, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const size_t cd = cmat_doubles(Np);
   CMat W = cmat_at(it.scr, Np), Qb = cmat_at(it.scr + cd, Np);
@@ -600,11 +606,9 @@ __device__ void do_force(const Prob& P, const Item& it, SmemC<NC>& S) {
 // q chosen so that |A / 2^q|_1 <= 1/2 (truncation below 1e-19).
 // ---------------------------------------------------------------------------
 template <int NC>
-__device__ void do_expm(const Prob& P, const Item& it, SmemC<NC>& S) {
+__device__ __forceinline__ void do_expm(const Prob& P, const Item& it, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const double* K = P.K;
-  double* B0 = it.scr;
-  double* B1 = it.scr + (size_t)Np * Np;
   double* out = (it.sign > 0) ? P.E : P.Einv;
   // 1-norm of dk K
   double cm = 0.0;
@@ -618,21 +622,53 @@ __device__ void do_expm(const Prob& P, const Item& it, SmemC<NC>& S) {
   double scaled = nrm;
   while (scaled > 0.5 && q < 1000) { scaled *= 0.5; ++q; }
   const double a = (double)it.sign * P.dk * ldexp(1.0, -q);
-  // Horner: Y <- 1 + (a/k) K Y, k = 16..1, starting from Y = 1
+  // Degree-16 Taylor polynomial of A = a K by Paterson-Stockmeyer with block
+  // 4: A^2, A^3, A^4, then Horner in A^4 over C_j = sum_i A^i / (4j + i)!,
+  // i = 0..3 (C_4 = I / 16!): six products instead of sixteen.
+  const size_t n2 = (size_t)Np * Np;
+  double* Ab = it.scr;
+  double* A2 = Ab + n2;
+  double* A3 = Ab + 2 * n2;
+  double* A4 = Ab + 3 * n2;
+  double* R0 = Ab + 4 * n2;
+  double* R1 = Ab + 5 * n2;
   for (int idx = threadIdx.x; idx < N * N; idx += WG) {
     const int i = idx % N, j = idx / N;
-    B0[(size_t)j * Np + i] = (i == j) ? 1.0 : 0.0;
+    Ab[(size_t)j * Np + i] = a * K[(size_t)i * N + j];
   }
   __syncthreads();
-  double* cur = B0;
-  double* nxt = B1;
-  for (int k = 16; k >= 1; --k) {
-    const double f = a / (double)k;
+  auto ld = [&](const double* M) {
+    return [=](int i, int k) { return (i < N && k < N) ? M[(size_t)k * Np + i] : 0.0; };
+  };
+  auto put = [&](double* M) {
+    return [=](int i, int j, double c) {
+      if (i < N && j < N) M[(size_t)j * Np + i] = c;
+    };
+  };
+  mm<NC, false, false>(Np, ld(Ab), ld(Ab), put(A2), S);
+  __syncthreads();
+  mm<NC, false, false>(Np, ld(A2), ld(Ab), put(A3), S);
+  __syncthreads();
+  mm<NC, false, false>(Np, ld(A2), ld(A2), put(A4), S);
+  __syncthreads();
+  // C_j(i, j') at one element
+  auto cj = [&](int jb, int i, int jj) {
+    const size_t o = (size_t)jj * Np + i;
+    return ((i == jj) ? kInvFact[4 * jb] : 0.0) + Ab[o] * kInvFact[4 * jb + 1] +
+           A2[o] * kInvFact[4 * jb + 2] + A3[o] * kInvFact[4 * jb + 3];
+  };
+  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
+    const int i = idx % N, j = idx / N;
+    R0[(size_t)j * Np + i] = A4[(size_t)j * Np + i] * kInvFact[16] + cj(3, i, j);
+  }
+  __syncthreads();
+  double* cur = R0;
+  double* nxt = R1;
+  for (int jb = 2; jb >= 0; --jb) {
     mm<NC, false, false>(
-        Np, [&](int i, int kk) { return (i < N && kk < N) ? K[(size_t)i * N + kk] : 0.0; },
-        [&](int kk, int j) { return (kk < N && j < N) ? cur[(size_t)j * Np + kk] : 0.0; },
+        Np, ld(cur), ld(A4),
         [&](int i, int j, double c) {
-          if (i < N && j < N) nxt[(size_t)j * Np + i] = f * c + (i == j ? 1.0 : 0.0);
+          if (i < N && j < N) nxt[(size_t)j * Np + i] = c + cj(jb, i, j);
         }, S);
     __syncthreads();
     double* t = cur; cur = nxt; nxt = t;
@@ -662,7 +698,7 @@ __device__ void do_expm(const Prob& P, const Item& it, SmemC<NC>& S) {
 // IK_EXPORT: X, D, T of slot a in the caller's layout.
 // ---------------------------------------------------------------------------
 template <int NC>
-__device__ void do_export(const Prob& P, const Item& it, SmemC<NC>&) {
+__device__ __forceinline__ void do_export(const Prob& P, const Item& it, SmemC<NC>&) {
   const int N = P.N, Np = P.Np;
   CMat X = cmat_at(it.a.X, Np), T = cmat_at(it.a.T, Np);
   for (int idx = threadIdx.x; idx < N * N; idx += WG) {
@@ -674,25 +710,47 @@ __device__ void do_export(const Prob& P, const Item& it, SmemC<NC>&) {
     if (P.outD) P.outD[i] = it.a.D[i];
 }
 
+// Size class of one item inside a launch of class NC: an item with N <= C
+// for a smaller class C runs that class's code on the same shared memory
+// (SmemC<C> is a prefix-compatible, smaller layout), so a batch of mixed
+// sizes pays for each item's own size, not for the largest one.
+template <int NC, class F>
+__device__ __forceinline__ void by_class(int n, F&& f) {
+  if constexpr (NC > 128) {
+    f(IC<NC>{});
+  } else {
+    if constexpr (NC > 32) if (n <= 32) { f(IC<32>{}); return; }
+    if constexpr (NC > 64) if (n <= 64) { f(IC<64>{}); return; }
+    if constexpr (NC > 80) if (n <= 80) { f(IC<80>{}); return; }
+    if constexpr (NC > 96) if (n <= 96) { f(IC<96>{}); return; }
+    f(IC<NC>{});
+  }
+}
+
 // One kernel per work-item kind, so that profiles and timings name the phase.
 #define FDET_KERNEL(NAME, BODY)                                                        \
   template <int NC>                                                                  \
   __global__ __launch_bounds__(WG) void NAME(const Prob* __restrict__ probs,           \
                                              const Item* __restrict__ items) {         \
-    __shared__ SmemC<NC> S;                                                           \
+    __shared__ SmemC<NC> S_;                                                          \
     const Item it = items[blockIdx.x];                                                 \
     const Prob P = probs[it.prob];                                                     \
-    BODY;                                                                              \
+    by_class<NC>(P.N, [&](auto cls) {                                                  \
+      constexpr int C = decltype(cls)::value;                                          \
+      static_assert(sizeof(SmemC<C>) <= sizeof(SmemC<NC>), "class layout");           \
+      SmemC<C>& S = *reinterpret_cast<SmemC<C>*>(&S_);                                 \
+      BODY;                                                                            \
+    });                                                                                \
   }
 
-FDET_KERNEL(k_expm, do_expm<NC>(P, it, S))
-FDET_KERNEL(k_chain, do_chain<NC>(P, it, S))
-FDET_KERNEL(k_combine, do_combine<NC>(P, it, S))
-FDET_KERNEL(k_close, do_close<NC>(P, it.a, cmat_at(it.scr, P.Np),
-                                    cmat_at(it.scr + cmat_doubles(P.Np), P.Np),
-                                    cmat_at(it.scr, P.Np), (it.flags & IF_WANT_G) != 0, true, S))
-FDET_KERNEL(k_force, do_force<NC>(P, it, S))
-FDET_KERNEL(k_export, do_export<NC>(P, it, S))
+FDET_KERNEL(k_expm, do_expm<C>(P, it, S))
+FDET_KERNEL(k_chain, do_chain<C>(P, it, S))
+FDET_KERNEL(k_combine, do_combine<C>(P, it, S))
+FDET_KERNEL(k_close, do_close<C>(P, it.a, cmat_at(it.scr, P.Np),
+                                   cmat_at(it.scr + cmat_doubles(P.Np), P.Np),
+                                   cmat_at(it.scr, P.Np), (it.flags & IF_WANT_G) != 0, true, S))
+FDET_KERNEL(k_force, do_force<C>(P, it, S))
+FDET_KERNEL(k_export, do_export<C>(P, it, S))
 
 __global__ void k_init_status(const Prob* __restrict__ probs, int nprob) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

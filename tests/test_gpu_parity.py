@@ -289,8 +289,11 @@ def test_force_workload_sampled_and_fd(fd):
 # a7: batched launches
 # ---------------------------------------------------------------------------
 
-def test_batched_mixed_sizes(fd):
-    specs = [(3, 32, 2), (5, 16, 1), (2, 45, 3), (6, 64, 2), (3, 8, 1)]
+@pytest.mark.parametrize("segments", [2, 0])
+def test_batched_mixed_sizes(fd, segments):
+    """Mixed sizes in one launch sequence; segments 0 = per-problem segments
+    balanced by chain work."""
+    specs = [(3, 32, 2), (5, 16, 1), (2, 45, 3), (6, 64, 2), (3, 8, 1), (8, 40, 1)]
     probs, refs = [], []
     for i, (L, Nt, seg) in enumerate(specs):
         K = honeycomb_hopping(L)
@@ -298,12 +301,12 @@ def test_batched_mixed_sizes(fd):
         phi = sample_phi(900 + i, Nt, K.shape[0], dk, 3.0)
         probs.append((to_dev(K), to_dev(phi), dk))
         refs.append(O.stabilised_logdet_greens(K, dk, phi))
-    ld, Gs = fd.greens_batched(probs, s=4, segments=2)
+    ld, Gs = fd.greens_batched(probs, s=4, segments=segments)
     ld = ld.cpu().numpy()
     for i, (lo, Go) in enumerate(refs):
         check_ld(ld[i], lo)
         check_G(Gs[i].cpu().numpy(), Go)
-    ld2, _ = fd.greens_batched(probs, s=4, segments=2, want_g=False)
+    ld2, _ = fd.greens_batched(probs, s=4, segments=segments, want_g=False)
     assert np.array_equal(ld2.cpu().numpy(), ld)
 
 
