@@ -115,7 +115,10 @@ int fd_greens(const fd_problem *p, const fd_options *o, double *logdet, double *
  * phi_{t,x} enters only the right-most factor of B_t, so the derivative is
  * exact).  The G~_t come from UDV checkpoints every c slices of the prefix and
  * suffix products (Sec. 5, stabilised dense pre- and suffix) and are carried
- * between checkpoints by G~_{t+1} = B_t G~_t B_t^{-1}.
+ * between checkpoints by G~_{t+1} = B_t G~_t B_t^{-1}.  The checkpoint
+ * intervals are multiplied out in parallel and the prefix and suffix UDVs at
+ * every checkpoint follow from log2(ceil(N_t/c)) rounds of stabilised
+ * products (eq. prod_2_mat_stab is associative up to rounding).
  * force: device, Nt*N doubles, Re F (row t-1 = slice t).
  * force_im: NULL or Nt*N doubles, Im F.  logdet: NULL or 2 doubles.          */
 int fd_force(const fd_problem *p, const fd_options *o, double *logdet, double *force,

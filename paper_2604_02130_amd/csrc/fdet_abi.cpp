@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <mutex>
@@ -167,6 +168,7 @@ std::vector<int> plan_segments(const fd_problem* p, int nprob, const Opts& o) {
 
 // Offsets are computed against `base`; with base == nullptr only sizes matter.
 struct Plan {
+  size_t item_cap = 0;   // items the descriptor region was sized for
   std::vector<Prob> probs;
   std::vector<std::vector<Item>> phases;
   size_t desc_bytes = 0;
@@ -240,8 +242,15 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   for (int i = 0; i < nprob; ++i) {
     pl.maxN = std::max(pl.maxN, p[i].N);
     if (force) {
-      nck[i] = (p[i].Nt + o.c - 1) / o.c;
-      nitems += 2 + 2 + 1 + nck[i];
+      const int nc = (p[i].Nt + o.c - 1) / o.c;
+      nck[i] = nc;
+      size_t scan = 0;
+      int lev = 0;
+      for (; (1 << lev) < nc; ++lev) scan += 2 * (size_t)(nc - (1 << lev));
+      maxlev = std::max(maxlev, lev);
+      // 2 exponentials, 2 nc interval chains + the identity, the scans, the
+      // log-det close, nc force items
+      nitems += 2 + 2 * (size_t)nc + 1 + scan + 1 + nc;
     } else {
       int lev = 0;
       while ((1 << lev) < nseg[i]) ++lev;
@@ -250,6 +259,7 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
     }
   }
   pl.desc_bytes = align_up(sizeof(Prob) * nprob) + align_up(sizeof(Item) * nitems);
+  pl.item_cap = nitems;
   Cursor cur{base, align_up(pl.desc_bytes)};
 
   std::vector<Item> expm, chain, close, forcei;
@@ -285,7 +295,6 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
         c.t0 = (int)((long long)q.Nt * k / ns);
         c.t1 = (int)((long long)q.Nt * (k + 1) / ns);
         c.s = o.s;
-        c.c = o.c;
         c.flags = fdet::IF_IDENTITY;
         c.a = slot[k];
         c.scr = scr[k];
@@ -307,44 +316,88 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
       if (what == FD_WHAT_GREENS) z.flags = fdet::IF_WANT_G;
       close.push_back(z);
     } else {
+      // Checkpoint intervals [k c, (k+1) c): local products L_k and local
+      // adjoint products L_k^H in parallel, then inclusive scans of
+      // stabilised products (log2(nc) levels, Hillis-Steele):
+      //   prefix  Q_k = L_k ... L_0,        suffix  S_k = L_k^H ... L_{nc-1}^H,
+      // each entry in two buffers (read one, write the other per level).
+      // Checkpoint k uses Q_{k-1} (the identity for k = 0) and S_k.
       const int nc = nck[i];
       const size_t ub = udv_bytes(Np);
-      double* pre = cur.take(ub * nc);
-      double* suf = cur.take(ub * nc);
-      Udv st[2];
-      double* cs[2];
-      for (int k = 0; k < 2; ++k) {
-        st[k] = make_udv(cur.take(ub), Np);
-        cs[k] = cur.take(scratch_bytes(Np));
+      std::vector<Udv> fw[2], bw[2];
+      std::vector<double*> sf(nc), sb(nc);
+      for (int b = 0; b < 2; ++b) {
+        fw[b].resize(nc);
+        bw[b].resize(nc);
+        for (int k = 0; k < nc; ++k) {
+          fw[b][k] = make_udv(cur.take(ub), Np);
+          bw[b][k] = make_udv(cur.take(ub), Np);
+        }
       }
-      std::vector<double*> fs(nc);
-      for (int k = 0; k < nc; ++k) fs[k] = cur.take(scratch_bytes(Np));
+      const Udv ident = make_udv(cur.take(ub), Np);
+      for (int k = 0; k < nc; ++k) {
+        sf[k] = cur.take(scratch_bytes(Np));
+        sb[k] = cur.take(scratch_bytes(Np));
+      }
       if (!(o.flags & FD_REUSE_E)) {
         for (int sg = 0; sg < 2; ++sg) {
           Item e = blank_item(fdet::IK_EXPM, i);
           e.sign = sg == 0 ? 1 : -1;
-          e.scr = cs[sg];
+          e.scr = sg == 0 ? sf[0] : sb[0];
           expm.push_back(e);
         }
       }
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < nc; ++k) {
+        for (int dir = 0; dir < 2; ++dir) {
+          Item c = blank_item(fdet::IK_CHAIN, i);
+          c.t0 = k * o.c;
+          c.t1 = std::min(q.Nt, (k + 1) * o.c);
+          c.s = o.s;
+          c.flags = fdet::IF_IDENTITY | (dir == 1 ? fdet::IF_ADJOINT : 0);
+          c.a = dir == 0 ? fw[0][k] : bw[0][k];
+          c.scr = dir == 0 ? sf[k] : sb[k];
+          chain.push_back(c);
+        }
+      }
+      {
+        // empty range: the identity (writes no scratch, so sf[0] is shared)
         Item c = blank_item(fdet::IK_CHAIN, i);
-        c.t0 = 0;
-        c.t1 = q.Nt;
         c.s = o.s;
-        c.c = o.c;
-        c.flags = fdet::IF_IDENTITY | fdet::IF_CKPT | (k == 1 ? fdet::IF_ADJOINT : 0);
-        c.a = st[k];
-        c.ck = k == 0 ? pre : suf;
-        c.ckstride = (int64_t)(ub / sizeof(double));
-        c.scr = cs[k];
+        c.flags = fdet::IF_IDENTITY;
+        c.a = ident;
+        c.scr = sf[0];
         chain.push_back(c);
       }
-      // log det of the whole product from the prefix chain's final state
+      std::vector<int> cf(nc, 0), cb(nc, 0);   // buffer holding each entry
+      for (int l = 0; (1 << l) < nc; ++l) {
+        const int d = 1 << l;
+        std::vector<int> nf = cf, nb = cb;
+        for (int k = d; k < nc; ++k) {        // Q_k <- Q_k Q_{k-d}
+          Item c = blank_item(fdet::IK_COMBINE, i);
+          c.b = fw[cf[k]][k];
+          c.a = fw[cf[k - d]][k - d];
+          c.o = fw[1 - cf[k]][k];
+          c.scr = sf[k];
+          comb[l].push_back(c);
+          nf[k] = 1 - cf[k];
+        }
+        for (int k = 0; k + d < nc; ++k) {    // S_k <- S_k S_{k+d}
+          Item c = blank_item(fdet::IK_COMBINE, i);
+          c.b = bw[cb[k]][k];
+          c.a = bw[cb[k + d]][k + d];
+          c.o = bw[1 - cb[k]][k];
+          c.scr = sb[k];
+          comb[l].push_back(c);
+          nb[k] = 1 - cb[k];
+        }
+        cf = nf;
+        cb = nb;
+      }
+      // log det of the whole product from Q_{nc-1}
       {
         Item z = blank_item(fdet::IK_CLOSE, i);
-        z.a = st[0];
-        z.scr = cs[0];
+        z.a = fw[cf[nc - 1]][nc - 1];
+        z.scr = sf[0];
         close.push_back(z);
       }
       // checkpoint k (row k*c) carries G~ forward over the first half of the
@@ -359,9 +412,9 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
         f.t0 = k * o.c;
         f.t1 = f.t0 + (gap_fwd + 1) / 2;
         f.nb = (nc == 1) ? q.Nt - (q.Nt + 1) / 2 : gap_bwd / 2;
-        f.a = make_udv(pre ? (double*)((char*)pre + ub * k) : nullptr, Np);
-        f.b = make_udv(suf ? (double*)((char*)suf + ub * k) : nullptr, Np);
-        f.scr = fs[k];
+        f.a = k == 0 ? ident : fw[cf[k - 1]][k - 1];
+        f.b = bw[cb[k]][k];
+        f.scr = sf[k];
         forcei.push_back(f);
       }
     }
@@ -382,6 +435,12 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   if (!close.empty()) pl.phases.push_back(close);
   if (!forcei.empty()) pl.phases.push_back(forcei);
   pl.total = cur.off;
+  size_t n = 0;
+  for (auto& ph : pl.phases) n += ph.size();
+  if (n > pl.item_cap) {   // the counting pass above must cover every item
+    std::fprintf(stderr, "libfdet: %zu work items exceed the %zu counted\n", n, pl.item_cap);
+    std::abort();
+  }
 }
 
 // Descriptors (problems, then the items of every phase) in the head of the

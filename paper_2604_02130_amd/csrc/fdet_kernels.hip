@@ -243,14 +243,6 @@ __device__ void chain_chunk(const Prob& P, const Item& it, CMat X, CMat& Tc, CMa
   __syncthreads();
 }
 
-__device__ void save_ckpt(double* dst, CMat X, CMat T, const double* D, int N, int Np) {
-  CMat Xc = cmat_at(dst, Np), Tc = cmat_at(dst + cmat_doubles(Np), Np);
-  double* Dc = dst + 2 * cmat_doubles(Np);
-  copy_cmat(Xc, X, N);
-  copy_cmat(Tc, T, N);
-  for (int i = threadIdx.x; i < N; i += WG) Dc[i] = D[i];
-}
-
 template <int NC>
 __device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
@@ -259,7 +251,6 @@ __device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC
   double* D = it.a.D;
   CMat W = cmat_at(it.scr, Np), Y2 = cmat_at(it.scr + cd, Np), Tn = cmat_at(it.scr + 2 * cd, Np);
   const bool adj = (it.flags & IF_ADJOINT) != 0;
-  const bool ckpt = (it.flags & IF_CKPT) != 0;
   if (threadIdx.x == 0) S.flag = 0;
   if (it.flags & IF_IDENTITY) {
     set_identity(X, N);
@@ -268,29 +259,13 @@ __device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC
   }
   __syncthreads();
   CMat Tc = T, Tt = Tn;
-  const int rows = it.t1 - it.t0;
-  const int c = ckpt ? it.c : (rows > 0 ? rows : 1);
-  const int nck = (rows + c - 1) / c;
   const int s = it.s;
-  for (int q = 0; q < nck; ++q) {
-    const int kseg = adj ? (nck - 1 - q) : q;
-    const int r0 = it.t0 + kseg * c;
-    const int r1 = min(r0 + c, it.t1);
-    if (ckpt && !adj) {
-      save_ckpt(it.ck + (size_t)kseg * it.ckstride, X, Tc, D, N, Np);
-      __syncthreads();
-    }
-    // chunks of at most s slices: upward from r0, or downward from r1 - 1
-    const int nchunk = (r1 - r0 + s - 1) / s;
-    for (int ch = 0; ch < nchunk; ++ch) {
-      const int tfirst = adj ? r1 - 1 - ch * s : r0 + ch * s;
-      const int ns = adj ? min(s, tfirst - r0 + 1) : min(s, r1 - tfirst);
-      chain_chunk<NC>(P, it, X, Tc, Tt, D, W, Y2, tfirst, ns, adj, S);
-    }
-    if (ckpt && adj) {
-      save_ckpt(it.ck + (size_t)kseg * it.ckstride, X, Tc, D, N, Np);
-      __syncthreads();
-    }
+  // chunks of at most s slices: upward from t0, or downward from t1 - 1
+  const int nchunk = (it.t1 - it.t0 + s - 1) / s;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int tfirst = adj ? it.t1 - 1 - ch * s : it.t0 + ch * s;
+    const int ns = adj ? min(s, tfirst - it.t0 + 1) : min(s, it.t1 - tfirst);
+    chain_chunk<NC>(P, it, X, Tc, Tt, D, W, Y2, tfirst, ns, adj, S);
   }
   if (Tc.re != T.re) {
     copy_cmat(T, Tc, N);
@@ -371,11 +346,12 @@ __device__ __forceinline__ void do_combine(const Prob& P, const Item& it, SmemC<
   CMat Xo = cmat_at(it.scr + 2 * cd, Np), To = cmat_at(it.scr + 3 * cd, Np);
   double* Do = it.scr + 4 * cd;
   if (threadIdx.x == 0) S.flag = 0;
-  // later segment (b) on the left, earlier (a) on the right; result into a
+  // left factor b (the later slices), right factor a; result into o, or a
   combine_core<NC, false>(P, it.b, it.a, W, Qb, Xo, To, Do, S);
-  copy_cmat(cmat_at(it.a.X, Np), Xo, N);
-  copy_cmat(cmat_at(it.a.T, Np), To, N);
-  for (int i = threadIdx.x; i < N; i += WG) it.a.D[i] = Do[i];
+  const Udv& R = it.o.X ? it.o : it.a;
+  copy_cmat(cmat_at(R.X, Np), Xo, N);
+  copy_cmat(cmat_at(R.T, Np), To, N);
+  for (int i = threadIdx.x; i < N; i += WG) R.D[i] = Do[i];
   if (threadIdx.x == 0 && S.flag) status_merge(P.status, -4);
   __syncthreads();
 }

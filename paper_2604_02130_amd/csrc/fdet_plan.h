@@ -27,18 +27,17 @@ struct Prob {
 enum ItemKind : int32_t {
   IK_EXPM = 0,      // E (sign +1) or Einv (sign -1) of one problem
   IK_CHAIN = 1,     // stabilised product of a range of slices
-  IK_COMBINE = 2,   // UDV(a) <- UDV(b) x UDV(a): stabilised product of two
+  IK_COMBINE = 2,   // UDV(o or a) <- UDV(b) x UDV(a): stabilised product of two
   IK_CLOSE = 3,     // log det (+ G) from a UDV
-  IK_FORCE = 4,     // G~ at a checkpoint, then carried forward and backward
+  IK_FORCE = 4,     // G~ at a checkpoint from its prefix (a) and adjoint suffix (b),
+                    // then carried forward and backward
   IK_EXPORT = 5,    // copy a UDV out in user layout
 };
 
 enum ItemFlags : int32_t {
-  IF_ADJOINT = 1,      // chain: accumulate the adjoint of the suffix product
+  IF_ADJOINT = 1,      // chain: B_{t0}^H ... B_{t1-1}^H instead of B_{t1-1} ... B_{t0}
   IF_IDENTITY = 2,     // chain: start from the identity
-  IF_CKPT = 4,         // chain: write UDV checkpoints
   IF_WANT_G = 8,       // close: also form G
-  IF_CLOSE_AFTER = 16, // chain: close (log det only) at the end
 };
 
 // A UDV triple X diag(D) T in workspace layout.
@@ -51,12 +50,11 @@ struct Udv {
 struct Item {
   int32_t kind, prob, flags, sign;
   int32_t t0, t1;       // slice rows [t0, t1)
-  int32_t s, c;         // stabilisation and checkpoint intervals
-  int32_t nb, pad0;     // force: rows t0-1, ..., t0-nb (mod N_t) carried backward
-  Udv a;                // state / first operand / result
-  Udv b;                // second operand (combine, force suffix)
-  double* ck;           // checkpoint array base (IF_CKPT)
-  int64_t ckstride;     // doubles per checkpoint
+  int32_t s, pad0;      // stabilisation interval
+  int32_t nb, pad1;     // force: rows t0-1, ..., t0-nb (mod N_t) carried backward
+  Udv a;                // state / right operand / result
+  Udv b;                // left operand (combine), adjoint suffix (force)
+  Udv o;                // combine: result (X == nullptr: into a)
   double* scr;          // scratch: 4 cmats + 2*Np doubles
 };
 

@@ -155,3 +155,13 @@ def test_plan_and_autotune_reject_bad_arguments(lib):
     best = fd.FdOptions()
     assert lib.fd_autotune(fd.FD_WHAT_UDV, ctypes.byref(p), 1, None, None, ctypes.byref(best),
                            None) == fd.FD_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("Nt", [1, 5, 16, 17, 33, 256, 512])
+@pytest.mark.parametrize("c", [1, 3, 16, 64])
+def test_force_plan_layout(lib, Nt, c):
+    """The force plan (interval chains, prefix / suffix scans, checkpoint
+    items) fits the descriptor region it counted, for ragged N_t / c."""
+    n = fd.workspace_bytes([prob(18, Nt)], fd.FD_WHAT_FORCE, checkpoint=c)
+    m = fd.workspace_bytes([prob(18, Nt), prob(50, Nt + 3)], fd.FD_WHAT_FORCE, checkpoint=c)
+    assert 0 < n < m and n % 256 == 0
