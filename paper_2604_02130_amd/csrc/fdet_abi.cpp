@@ -47,7 +47,12 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int pad16(int n) { return (n + 15) / 16 * 16; }
 size_t cmat_bytes(int Np) { return (size_t)2 * Np * Np * sizeof(double); }
 size_t udv_bytes(int Np) { return align_up(2 * cmat_bytes(Np) + (size_t)Np * sizeof(double)); }
-size_t scratch_bytes(int Np) { return align_up(4 * cmat_bytes(Np) + (size_t)2 * Np * sizeof(double)); }
+// 4 complex matrices, 2 Np doubles, and the T factors of the 16-column
+// panels of a blocked QR (Np / 16 panels of 2 x 16 x 16 doubles)
+size_t scratch_bytes(int Np) {
+  return align_up(4 * cmat_bytes(Np) + (size_t)2 * Np * sizeof(double) +
+                  (size_t)(Np / 16) * 512 * sizeof(double));
+}
 
 struct Opts {
   int s, c, segments, flags;

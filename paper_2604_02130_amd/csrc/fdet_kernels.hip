@@ -17,6 +17,7 @@
 #include "fdet_device.hpp"
 #include "fdet_plan.h"
 #include "fdet_regqr.hpp"
+#include "fdet_large.hpp"
 
 namespace fdet {
 
@@ -30,47 +31,49 @@ __constant__ double kInvFact[17] = {
 
 // Size classes: N <= NC.  Classes up to 128 keep the matrix being factorised
 // in registers and stage products through LDS (fdet_regqr.hpp); the 512
-// class works on device memory (fdet_device.hpp).
+// class works on device memory with blocked, MFMA-based factorisations
+// (fdet_large.hpp).  F is a free complex matrix and tst the per-item store of
+// the panels' T factors, both used by the 512 class only.
 template <int NC>
-__device__ void qr_factor(CMat W, int N, const double* keys, SmemC<NC>& S) {
+__device__ __forceinline__ void qr_factor(CMat W, int N, const double* keys, CMat F, double* tst,
+                                          SmemC<NC>& S) {
   if constexpr (NC <= 128) rq_qrp<NC>(W, N, keys, S);
-  else wg_qrp(W, N, keys, S);
+  else lg_qrp<NC>(W, N, keys, F, tst, S);
 }
 
 template <int NC>
-__device__ void qr_form_q(CMat W, int N, CMat Q, SmemC<NC>& S) {
-  if constexpr (NC <= 128) {
-    rq_form_q<NC>(N, Q, S);
-    __syncthreads();
-  } else {
-    wg_form_q(W, N, Q, S);
-  }
+__device__ __forceinline__ void qr_form_q(CMat W, int N, CMat Q, CMat F, const double* tst,
+                                          SmemC<NC>& S) {
+  if constexpr (NC <= 128) rq_form_q<NC>(N, Q, S);
+  else lg_form_q<NC>(W, N, Q, F, tst, S);
+  __syncthreads();
 }
 
 // C = A B with A, B real or complex (AC, BC)
 template <int NC, bool AC, bool BC, class LA, class LB, class ST>
-__device__ void mm(int Np, LA la, LB lb, ST st, SmemC<NC>& S) {
-  if constexpr (NC <= 128) {
-    gemm_lds<NC, AC, BC>(Np, la, lb, st, S.big);
-  } else {
-    if constexpr (AC && BC) gemm_cc(Np, la, lb, st);
-    else if constexpr (AC) gemm_cr(Np, la, lb, st);
-    else if constexpr (BC) gemm_rc(Np, la, lb, st);
-    else gemm_rr(Np, la, lb, st);
-  }
+__device__ __forceinline__ void mm(int Np, LA la, LB lb, ST st, SmemC<NC>& S) {
+  if constexpr (NC <= 128) gemm_lds<NC, AC, BC>(Np, la, lb, st, S.big);
+  else lg_gemm<128, 128, AC, BC>(Np, Np, Np, la, lb, st, S.big);
 }
 
 // Y <- R^{-1} Q^H Y for the factor in W
 template <int NC>
-__device__ void qr_solve(CMat W, int N, CMat Y, SmemC<NC>& S) {
+__device__ __forceinline__ void qr_solve(CMat W, int N, CMat Y, CMat F, const double* tst,
+                                         SmemC<NC>& S) {
   if constexpr (NC <= 128) {
     rq_solve<NC>(W, N, Y, S);
   } else {
-    wg_apply_qh(W, N, Y, S);
+    lg_apply_qh<NC>(W, N, Y, F, tst, S);
     __syncthreads();
-    wg_backsolve<512>(W, N, Y);
+    lg_backsolve<NC>(W, N, Y, S);
   }
   __syncthreads();
+}
+
+// per-item store of T factors: after the 4 matrices and 2 Np doubles of the
+// item's scratch
+__device__ __forceinline__ double* tstore(double* scr, int Np) {
+  return scr + 4 * cmat_doubles(Np) + 2 * (size_t)Np;
 }
 
 __device__ void status_merge(int32_t* st, int32_t code) {
@@ -213,7 +216,7 @@ __device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC
 
 template <int NC>
 __device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
-                         bool user_out, SmemC<NC>& S);
+                         bool user_out, double* tst, SmemC<NC>& S);
 
 template <int NC>
 __device__ void chain_chunk(const Prob& P, const Item& it, CMat X, CMat& Tc, CMat& Tt, double* D,
@@ -230,10 +233,11 @@ __device__ void chain_chunk(const Prob& P, const Item& it, CMat X, CMat& Tc, CMa
     src = dst;
     dst = (dst.re == W.re) ? Y2 : W;
   }
-  qr_factor<NC>(W, N, D, S);
+  double* tst = tstore(it.scr, Np);
+  qr_factor<NC>(W, N, D, Y2, tst, S);
   udv_scales<NC>(W, N, S);
   __syncthreads();
-  qr_form_q<NC>(W, N, X, S);
+  qr_form_q<NC>(W, N, X, Y2, tst, S);
   udv_new_t<NC>(W, N, Np,
                   [&](int r, int j, double& br, double& bi) { br = Tc.r(r, j); bi = Tc.m(r, j); },
                   Tt, S);
@@ -282,7 +286,7 @@ __device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC
 // ---------------------------------------------------------------------------
 template <int NC, bool B_ADJ>
 __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMat Xo, CMat To,
-                             double* Do, SmemC<NC>& S) {
+                             double* Do, double* tst, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   CMat X1 = cmat_at(A1.X, Np), T1 = cmat_at(A1.T, Np);
   CMat X2 = cmat_at(A2.X, Np), T2 = cmat_at(A2.T, Np);
@@ -308,10 +312,11 @@ __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMa
         if (i < N && j < N) { W.r(i, j) = S.v1[i] * cr; W.m(i, j) = S.v1[i] * ci; }
       }, S);
   __syncthreads();
-  qr_factor<NC>(W, N, A2.D, S);
+  // To is written last, so it serves as the free matrix until then
+  qr_factor<NC>(W, N, A2.D, To, tst, S);
   udv_scales<NC>(W, N, S);
   __syncthreads();
-  qr_form_q<NC>(W, N, Qb, S);
+  qr_form_q<NC>(W, N, Qb, To, tst, S);
   // X = X1 Q
   mm<NC, true, true>(
       Np,
@@ -347,7 +352,7 @@ __device__ __forceinline__ void do_combine(const Prob& P, const Item& it, SmemC<
   double* Do = it.scr + 4 * cd;
   if (threadIdx.x == 0) S.flag = 0;
   // left factor b (the later slices), right factor a; result into o, or a
-  combine_core<NC, false>(P, it.b, it.a, W, Qb, Xo, To, Do, S);
+  combine_core<NC, false>(P, it.b, it.a, W, Qb, Xo, To, Do, tstore(it.scr, Np), S);
   const Udv& R = it.o.X ? it.o : it.a;
   copy_cmat(cmat_at(R.X, Np), Xo, N);
   copy_cmat(cmat_at(R.T, Np), To, N);
@@ -367,7 +372,7 @@ __device__ __forceinline__ void do_combine(const Prob& P, const Item& it, SmemC<
 // ---------------------------------------------------------------------------
 template <int NC>
 __device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
-                         bool user_out, SmemC<NC>& S) {
+                         bool user_out, double* tst, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   CMat X = cmat_at(U.X, Np), T = cmat_at(U.T, Np);
   bool bad = false;
@@ -395,7 +400,8 @@ __device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, 
         }
       }, S);
   __syncthreads();
-  qr_factor<NC>(W, N, nullptr, S);
+  // T of the UDV is not read again: it serves as the free matrix
+  qr_factor<NC>(W, N, nullptr, T, tst, S);
   // log det
   double lr = 0.0, li = 0.0, amin = INFINITY, amax = 0.0;
   for (int i = threadIdx.x; i < N; i += WG) {
@@ -443,7 +449,7 @@ __device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, 
   }
   for (int r = threadIdx.x; r < N; r += WG) S.pinv[S.piv[r]] = r;
   __syncthreads();
-  qr_solve<NC>(W, N, Yb, S);
+  qr_solve<NC>(W, N, Yb, T, tst, S);
   // G = X Pi Z: row a of (Pi Z) is row pinv[a] of Z
   double* Gu = P.G;
   mm<NC, true, true>(
@@ -482,10 +488,10 @@ __device__ __forceinline__ void do_force(const Prob& P, const Item& it, SmemC<NC
   double* Dc = it.scr + 4 * cd;
   if (threadIdx.x == 0) S.flag = 0;
   // G~ at the first slice of the interval: (1 + P_k S_k)^{-1}
-  combine_core<NC, true>(P, it.a, it.b, W, Qb, Xc, Tc, Dc, S);
+  combine_core<NC, true>(P, it.a, it.b, W, Qb, Xc, Tc, Dc, tstore(it.scr, Np), S);
   Udv U;
   U.X = Xc.re; U.T = Tc.re; U.D = Dc;
-  do_close<NC>(P, U, W, Qb, W, true, false, S);
+  do_close<NC>(P, U, W, Qb, W, true, false, tstore(it.scr, Np), S);
   // keep G~ of the checkpoint for the backward direction
   copy_cmat(Tc, W, N);
   const double* E = P.E;
@@ -724,7 +730,8 @@ FDET_KERNEL(k_chain, do_chain<C>(P, it, S))
 FDET_KERNEL(k_combine, do_combine<C>(P, it, S))
 FDET_KERNEL(k_close, do_close<C>(P, it.a, cmat_at(it.scr, P.Np),
                                    cmat_at(it.scr + cmat_doubles(P.Np), P.Np),
-                                   cmat_at(it.scr, P.Np), (it.flags & IF_WANT_G) != 0, true, S))
+                                   cmat_at(it.scr, P.Np), (it.flags & IF_WANT_G) != 0, true,
+                                   tstore(it.scr, P.Np), S))
 FDET_KERNEL(k_force, do_force<C>(P, it, S))
 FDET_KERNEL(k_export, do_export<C>(P, it, S))
 

@@ -1,0 +1,550 @@
+// Workgroup primitives for 128 < N <= 512 (one workgroup of WG = 512 threads
+// per work item, matrices in device memory):
+//   lg_gemm       macro-tiled FP64 MFMA product with LDS-staged K panels,
+//   lg_qrp        pre-pivoted blocked Householder QR (compact WY panels of
+//                 16 reflectors, trailing updates as MFMA products),
+//   lg_form_q     explicit Q by backward accumulation of the panels,
+//   lg_apply_qh   Y <- Q^H Y, panel by panel,
+//   lg_backsolve  Y <- R^{-1} Y, blocked by 16 rows.
+//
+// An unblocked QR streams the whole trailing matrix through device memory at
+// every column (N^3 / 3 complex loads and stores); here each panel touches it
+// twice, and all O(N^3) work runs on the matrix cores.
+//
+// Householder conventions are those of the in-register routines: reflector
+// H_j = I - beta_j u_j u_j^H with u_j = (0, .., 0, u0_j, W(j+1:, j)), the
+// tail stored below the diagonal of W, u0_j in S.u0r/u0i, beta_j in S.beta;
+// a panel of reflectors j0 .. j0+pw-1 is H_j0 ... H_{j0+pw-1} = I - V T V^H
+// with T upper triangular (pw x pw), stored per panel in `tst`.
+#pragma once
+
+#include "fdet_device.hpp"
+#include "fdet_regqr.hpp"
+
+namespace fdet {
+
+constexpr int LG_PW = 16;                        // panel width
+constexpr int LG_TDBL = 2 * LG_PW * LG_PW;       // doubles per stored T (re, im)
+
+__host__ __device__ constexpr int lg_tstore_doubles(int Np) { return (Np / LG_PW) * LG_TDBL; }
+
+// ---------------------------------------------------------------------------
+// C (M x Nc) = A (M x K) B (K x Nc), macro tiles TM x TN, K panels of 16
+// staged in LDS with a register prefetch of the next panel.  Loaders are only
+// called inside the logical sizes (la(i, k) with i < M, k < K, lb(k, j) with
+// k < K, j < Nc); st(i, j, ..) only for i < M, j < Nc.
+// ---------------------------------------------------------------------------
+template <int TM, int TN, bool AC, bool BC, class LA, class LB, class ST>
+__device__ void lg_gemm(int M, int Nc, int K, LA la, LB lb, ST st, double* lds) {
+  constexpr bool CC = AC || BC;
+  constexpr int KP = 16;
+  constexpr int SA = panel_stride(TM), SB = panel_stride(TN);
+  constexpr int TMT = TM / 16, TNT = TN / 16, NT = TMT * TNT;
+  constexpr int TPW = (NT + NWAVE - 1) / NWAVE;
+  constexpr int EA = TM * KP, EB = KP * TN;
+  constexpr int PA = (EA + WG - 1) / WG, PB = (EB + WG - 1) / WG;
+  static_assert((AC ? 2 : 1) * KP * SA + (BC ? 2 : 1) * KP * SB <= LG_BIG, "LDS staging");
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int li = lane & 15, lk = lane >> 4;
+  double* Ar = lds;
+  double* Ai = Ar + KP * SA;
+  double* Br = Ar + (AC ? 2 : 1) * KP * SA;
+  double* Bi = Br + KP * SB;
+  const int mtm = (M + TM - 1) / TM, mtn = (Nc + TN - 1) / TN;
+
+  double fa_r[PA], fa_i[PA], fb_r[PB], fb_i[PB];
+  for (int mt = 0; mt < mtm * mtn; ++mt) {
+    const int bm = (mt % mtm) * TM, bn = (mt / mtm) * TN;
+    auto fetch = [&](int k0) {
+#pragma unroll
+      for (int x = 0; x < PA; ++x) {
+        const int e = tid + WG * x;
+        fa_r[x] = 0.0; fa_i[x] = 0.0;
+        const int i = e % TM, kk = e / TM;          // A: rows fastest
+        if (e < EA && bm + i < M && k0 + kk < K) {
+          if constexpr (AC) la(bm + i, k0 + kk, fa_r[x], fa_i[x]);
+          else fa_r[x] = la(bm + i, k0 + kk);
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < PB; ++x) {
+        const int e = tid + WG * x;
+        fb_r[x] = 0.0; fb_i[x] = 0.0;
+        const int kb = e % KP, j = e / KP;          // B: k fastest
+        if (e < EB && k0 + kb < K && bn + j < Nc) {
+          if constexpr (BC) lb(k0 + kb, bn + j, fb_r[x], fb_i[x]);
+          else fb_r[x] = lb(k0 + kb, bn + j);
+        }
+      }
+    };
+    auto stash = [&]() {
+#pragma unroll
+      for (int x = 0; x < PA; ++x) {
+        const int e = tid + WG * x;
+        if (e < EA) {
+          const int i = e % TM, kk = e / TM;
+          Ar[kk * SA + i] = fa_r[x];
+          if constexpr (AC) Ai[kk * SA + i] = fa_i[x];
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < PB; ++x) {
+        const int e = tid + WG * x;
+        if (e < EB) {
+          const int kb = e % KP, j = e / KP;
+          Br[kb * SB + j] = fb_r[x];
+          if constexpr (BC) Bi[kb * SB + j] = fb_i[x];
+        }
+      }
+    };
+    v4d cr[TPW], ci[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      cr[t] = v4d{0.0, 0.0, 0.0, 0.0};
+      ci[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += KP) {
+      __syncthreads();
+      stash();
+      __syncthreads();
+      if (k0 + KP < K) fetch(k0 + KP);
+#pragma unroll
+      for (int sk = 0; sk < KP / 4; ++sk) {
+        const int kk = 4 * sk + lk;
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+          const int tile = wave + NWAVE * t;
+          if (tile >= NT) break;
+          const int i = ((tile % TMT) << 4) + li, j = ((tile / TMT) << 4) + li;
+          const double a_r = Ar[kk * SA + i];
+          const double b_r = Br[kk * SB + j];
+          if constexpr (AC && BC) {
+            const double a_i = Ai[kk * SA + i], b_i = Bi[kk * SB + j];
+            cr[t] = mfma4(a_r, b_r, cr[t]);
+            ci[t] = mfma4(a_r, b_i, ci[t]);
+            cr[t] = mfma4(-a_i, b_i, cr[t]);
+            ci[t] = mfma4(a_i, b_r, ci[t]);
+          } else if constexpr (AC) {
+            const double a_i = Ai[kk * SA + i];
+            cr[t] = mfma4(a_r, b_r, cr[t]);
+            ci[t] = mfma4(a_i, b_r, ci[t]);
+          } else if constexpr (BC) {
+            const double b_i = Bi[kk * SB + j];
+            cr[t] = mfma4(a_r, b_r, cr[t]);
+            ci[t] = mfma4(a_r, b_i, ci[t]);
+          } else {
+            cr[t] = mfma4(a_r, b_r, cr[t]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int tile = wave + NWAVE * t;
+      if (tile >= NT) break;
+      const int r0 = ((tile % TMT) << 4) + lk, c0 = ((tile / TMT) << 4) + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = bm + r0 + 4 * r, gj = bn + c0;
+        if (gi < M && gj < Nc) {
+          if constexpr (CC) st(gi, gj, cr[t][r], ci[t][r]);
+          else st(gi, gj, cr[t][r]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Reflector matrix V of the panel at j0 (pw columns): V(r, c) for rows r of
+// the whole matrix, zero above row j0 + c, u0 on it, the tail below.
+struct LgPanel {
+  CMat W;
+  const double* u0r;
+  const double* u0i;
+  int j0, pw;
+  __device__ __forceinline__ void v(int r, int c, double& vr, double& vi) const {
+    const int j = j0 + c;
+    if (r > j) { vr = W.r(r, j); vi = W.m(r, j); }
+    else if (r == j) { vr = u0r[j]; vi = u0i[j]; }
+    else { vr = 0.0; vi = 0.0; }
+  }
+};
+
+// Y(r0:r0+M, 0:Nc) <- (I - V T' V^H) Y for one panel, T' = T (op = 0) or T^H
+// (op = 1).  Rows of V and Y are offset by r0 = j0; F is a free complex
+// matrix (ld = its own) holding V^H Y, then T' V^H Y.
+template <int NC>
+__device__ void lg_apply_panel(const LgPanel& pn, const double* tp, CMat Y, int ycol0, int M, int Nc,
+                               CMat F, bool herm, SmemC<NC>& S) {
+  const int j0 = pn.j0, pw = pn.pw;
+  // F(0:pw, 0:Nc) = V^H Y
+  lg_gemm<16, 128, true, true>(
+      pw, Nc, M,
+      [&](int i, int k, double& ar, double& ai) {
+        double vr, vi;
+        pn.v(j0 + k, i, vr, vi);
+        ar = vr; ai = -vi;
+      },
+      [&](int k, int j, double& br, double& bi) {
+        br = Y.r(j0 + k, ycol0 + j); bi = Y.m(j0 + k, ycol0 + j);
+      },
+      [&](int i, int j, double cr, double ci) { F.r(i, j) = cr; F.m(i, j) = ci; }, S.big);
+  // F <- T' F, column by column (T' is pw x pw from tp: re then im, T(i, k)
+  // at [k * 16 + i])
+  double* tr = S.lgt;
+  double* ti = S.lgt + 256;
+  for (int e = threadIdx.x; e < 256; e += WG) { tr[e] = tp[e]; ti[e] = tp[256 + e]; }
+  __syncthreads();
+  for (int j = threadIdx.x; j < Nc; j += WG) {
+    double xr[LG_PW], xi[LG_PW];
+#pragma unroll
+    for (int k = 0; k < LG_PW; ++k) {
+      xr[k] = k < pw ? F.r(k, j) : 0.0;
+      xi[k] = k < pw ? F.m(k, j) : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < LG_PW; ++i) {
+      if (i >= pw) break;
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int k = 0; k < LG_PW; ++k) {
+        // T(i, k) (upper: k >= i) or T^H(i, k) = conj(T(k, i)) (k <= i)
+        double t_r, t_i;
+        if (!herm) { t_r = (k >= i) ? tr[k * 16 + i] : 0.0; t_i = (k >= i) ? ti[k * 16 + i] : 0.0; }
+        else { t_r = (k <= i) ? tr[i * 16 + k] : 0.0; t_i = (k <= i) ? -ti[i * 16 + k] : 0.0; }
+        sr += t_r * xr[k] - t_i * xi[k];
+        si += t_r * xi[k] + t_i * xr[k];
+      }
+      F.r(i, j) = sr;
+      F.m(i, j) = si;
+    }
+  }
+  __syncthreads();
+  // Y -= V F
+  lg_gemm<128, 128, true, true>(
+      M, Nc, pw,
+      [&](int i, int k, double& ar, double& ai) { pn.v(j0 + i, k, ar, ai); },
+      [&](int k, int j, double& br, double& bi) { br = F.r(k, j); bi = F.m(k, j); },
+      [&](int i, int j, double cr, double ci) {
+        Y.r(j0 + i, ycol0 + j) -= cr;
+        Y.m(j0 + i, ycol0 + j) -= ci;
+      }, S.big);
+}
+
+// Sum over the workgroup of NV values per thread; every thread receives the
+// NV sums.  Two LDS buffers alternate with `buf`, so consecutive calls need
+// no extra barrier.
+template <int NV, int NC>
+__device__ __forceinline__ void lg_block_sums(double* v, int buf, SmemC<NC>& S) {
+  static_assert(NV <= 32, "at most 32 values");
+  const int lane = lane_id(), wave = wave_id();
+  double* part = S.lgred + buf * (NWAVE * 32);
+  double* sums = S.lgsum + buf * 32;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double x = red16(v[k]);
+    x = readlane_d(x, 0) + readlane_d(x, 16) + readlane_d(x, 32) + readlane_d(x, 48);
+    if (lane == 0) part[wave * 32 + k] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) t += part[w * 32 + threadIdx.x];
+    sums[threadIdx.x] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = sums[k];
+}
+
+// ---------------------------------------------------------------------------
+// lg_qrp: pre-pivoted blocked Householder QR of the N x N matrix in W (same
+// contract as rq_qrp / wg_qrp: R in the upper triangle of W in pivoted column
+// order, reflector tails below it, S.u0r/u0i, S.beta, S.piv, S.pinv, S.csp,
+// S.rdr/rdi, S.nref), plus the T factor of every panel in tst.  F is a free
+// complex N x N matrix.
+// ---------------------------------------------------------------------------
+template <int NC>
+__device__ void lg_qrp(CMat W, int N, const double* keys, CMat F, double* tst, SmemC<NC>& S) {
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  // ---- pivot order by key = |column| x keys[c], decreasing, ties to the
+  // lower index (one wave per column)
+  for (int c = wave; c < N; c += NWAVE) {
+    double acc = 0.0;
+    for (int i = lane; i < N; i += 64) {
+      const double a = W.r(i, c), b = W.m(i, c);
+      acc += a * a + b * b;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) S.v3[c] = sqrt(acc) * (keys ? keys[c] : 1.0);
+  }
+  __syncthreads();
+  for (int c = tid; c < N; c += WG) {
+    const double kc = S.v3[c];
+    int pos = 0;
+    for (int d = 0; d < N; ++d) {
+      const double kd = S.v3[d];
+      pos += (kd > kc || (kd == kc && d < c)) ? 1 : 0;
+    }
+    S.pinv[c] = pos;
+    S.piv[pos] = c;
+    S.csp[pos] = keys ? keys[c] : 1.0;
+  }
+  if (tid == 0) S.nref = 0;
+  __syncthreads();
+  // ---- columns into pivot order (through F)
+  for (int idx = tid; idx < N * N; idx += WG) {
+    const int i = idx % N, k = idx / N;
+    const int c = S.piv[k];
+    F.r(i, k) = W.r(i, c);
+    F.m(i, k) = W.m(i, c);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < N * N; idx += WG) {
+    const int i = idx % N, k = idx / N;
+    W.r(i, k) = F.r(i, k);
+    W.m(i, k) = F.m(i, k);
+  }
+  __syncthreads();
+
+  const int r = tid;   // this thread's row of every panel
+  int step = 0;
+  for (int j0 = 0; j0 < N; j0 += LG_PW) {
+    const int pw = min(LG_PW, N - j0);
+    // ---- panel factorisation in registers (row r, columns j0 .. j0+pw-1)
+    double pr[LG_PW], pi[LG_PW];
+#pragma unroll
+    for (int c = 0; c < LG_PW; ++c) {
+      const bool in = r >= j0 && r < N && c < pw;
+      pr[c] = in ? W.r(r, j0 + c) : 0.0;
+      pi[c] = in ? W.m(r, j0 + c) : 0.0;
+    }
+    static_for<0, LG_PW>([&](auto jc) {
+      constexpr int JJ = decltype(jc)::value;
+      if (JJ >= pw) return;
+      const int j = j0 + JJ;
+      const int buf = step & 1;
+      ++step;
+      // row j of the panel, for the terms of row j in the sums below
+      double* rowj = S.lgrow + buf * 32;
+      if (r == j) {
+#pragma unroll
+        for (int c = JJ; c < LG_PW; ++c) { rowj[c] = pr[c]; rowj[16 + c] = pi[c]; }
+      }
+      // sums over rows below j: |a_jj|^2 and conj(a_jj) a_c for c > JJ
+      constexpr int NV = 1 + 2 * (LG_PW - 1 - JJ);
+      double v[NV];
+      const bool below = r > j && r < N;
+      v[0] = below ? pr[JJ] * pr[JJ] + pi[JJ] * pi[JJ] : 0.0;
+#pragma unroll
+      for (int c = JJ + 1; c < LG_PW; ++c) {
+        const int q = 1 + 2 * (c - JJ - 1);
+        v[q] = below ? pr[JJ] * pr[c] + pi[JJ] * pi[c] : 0.0;
+        v[q + 1] = below ? pr[JJ] * pi[c] - pi[JJ] * pr[c] : 0.0;
+      }
+      lg_block_sums<NV>(v, buf, S);
+      const double a0r = rowj[JJ], a0i = rowj[16 + JJ];
+      const double aa0 = sqrt(a0r * a0r + a0i * a0i);
+      const double alpha = sqrt(v[0] + aa0 * aa0);
+      double er = 1.0, ei = 0.0;
+      if (aa0 > 0.0) { const double inv = 1.0 / aa0; er = a0r * inv; ei = a0i * inv; }
+      const bool refl = alpha > 0.0;
+      const double beta = refl ? 1.0 / (alpha * (alpha + aa0)) : 0.0;
+      const double u0r = refl ? a0r + er * alpha : 0.0, u0i = refl ? a0i + ei * alpha : 0.0;
+      // apply H_j to the panel columns c > JJ: a_c -= beta u (u^H a_c),
+      // u^H a_c = (sum over rows below j) + conj(u0) a_jc
+      const double ur = (r == j) ? u0r : ((r > j && r < N) ? pr[JJ] : 0.0);
+      const double ui = (r == j) ? u0i : ((r > j && r < N) ? pi[JJ] : 0.0);
+#pragma unroll
+      for (int c = JJ + 1; c < LG_PW; ++c) {
+        const int q = 1 + 2 * (c - JJ - 1);
+        const double ajr = rowj[c], aji = rowj[16 + c];
+        const double dr = v[q] + u0r * ajr + u0i * aji;
+        const double di = v[q + 1] + u0r * aji - u0i * ajr;
+        const double wr = beta * dr, wi = beta * di;
+        pr[c] -= ur * wr - ui * wi;
+        pi[c] -= ur * wi + ui * wr;
+      }
+      if (r == j) {
+        pr[JJ] = refl ? -er * alpha : 0.0;
+        pi[JJ] = refl ? -ei * alpha : 0.0;
+      }
+      if (tid == 0) {
+        S.rdr[j] = refl ? -er * alpha : 0.0;
+        S.rdi[j] = refl ? -ei * alpha : 0.0;
+        S.u0r[j] = u0r;
+        S.u0i[j] = u0i;
+        S.beta[j] = beta;
+        if (refl) S.nref += 1;
+      }
+    });
+    // ---- panel back to W (rows >= j0)
+    if (r >= j0 && r < N) {
+#pragma unroll
+      for (int c = 0; c < LG_PW; ++c) {
+        if (c < pw) { W.r(r, j0 + c) = pr[c]; W.m(r, j0 + c) = pi[c]; }
+      }
+    }
+    __syncthreads();
+    const LgPanel pn{W, S.u0r, S.u0i, j0, pw};
+    // ---- T factor: Gm = V^H V on the matrix cores (rows split over the
+    // waves), then T(jj, jj) = beta_jj, T(0:jj, jj) = -beta_jj T(0:jj, 0:jj)
+    // Gm(0:jj, jj)
+    {
+      const int li = lane & 15, lk = lane >> 4;
+      v4d gr = {0.0, 0.0, 0.0, 0.0}, gi = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = j0 + 4 * wave; k0 < N; k0 += 4 * NWAVE) {
+        const int row = k0 + lk;
+        double vr = 0.0, vi = 0.0;
+        if (row < N && li < pw) pn.v(row, li, vr, vi);
+        // A = V^H (i = li, k = row), B = V (k = row, j = li)
+        gr = mfma4(vr, vr, gr);
+        gr = mfma4(vi, vi, gr);
+        gi = mfma4(vr, vi, gi);
+        gi = mfma4(-vi, vr, gi);
+      }
+      double* part = S.big;   // 8 waves x (re 256, im 256)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = lk + 4 * q, jcol = li;
+        part[wave * 512 + jcol * 16 + i] = gr[q];
+        part[wave * 512 + 256 + jcol * 16 + i] = gi[q];
+      }
+      __syncthreads();
+      double* gmr = S.lgt + 512;
+      double* gmi = S.lgt + 768;
+      if (tid < 256) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWAVE; ++w) { sr += part[w * 512 + tid]; si += part[w * 512 + 256 + tid]; }
+        gmr[tid] = sr;
+        gmi[tid] = si;
+      }
+      double* tr = S.lgt;
+      double* ti = S.lgt + 256;
+      if (tid < 256) { tr[tid] = 0.0; ti[tid] = 0.0; }
+      __syncthreads();
+      for (int jj = 0; jj < pw; ++jj) {
+        const double bj = S.beta[j0 + jj];
+        if (tid < jj) {
+          // T(i, jj) = -beta sum_{k=i}^{jj-1} T(i, k) Gm(k, jj)
+          const int i = tid;
+          double sr = 0.0, si = 0.0;
+          for (int k = i; k < jj; ++k) {
+            const double a_r = tr[k * 16 + i], a_i = ti[k * 16 + i];
+            const double b_r = gmr[jj * 16 + k], b_i = gmi[jj * 16 + k];
+            sr += a_r * b_r - a_i * b_i;
+            si += a_r * b_i + a_i * b_r;
+          }
+          tr[jj * 16 + i] = -bj * sr;
+          ti[jj * 16 + i] = -bj * si;
+        }
+        if (tid == jj) { tr[jj * 16 + jj] = bj; ti[jj * 16 + jj] = 0.0; }
+        __syncthreads();
+      }
+      double* tp = tst + (size_t)(j0 / LG_PW) * LG_TDBL;
+      if (tid < 256) { tp[tid] = tr[tid]; tp[256 + tid] = ti[tid]; }
+      __syncthreads();
+    }
+    // ---- trailing columns: A <- (I - V T^H V^H) A, A = W(j0:N, j0+pw:N)
+    const int nt = N - j0 - pw;
+    if (nt > 0) {
+      const double* tp = tst + (size_t)(j0 / LG_PW) * LG_TDBL;
+      lg_apply_panel<NC>(pn, tp, W, j0 + pw, N - j0, nt, F, true, S);
+    }
+  }
+  __syncthreads();
+}
+
+// Q = H_0 ... H_{N-1} explicitly into Q: backward over the panels, each
+// acting on Q(j0:N, j0:N) (columns left of j0 are still unit vectors there).
+template <int NC>
+__device__ void lg_form_q(CMat W, int N, CMat Q, CMat F, const double* tst, SmemC<NC>& S) {
+  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
+    const int i = idx % N, c = idx / N;
+    Q.r(i, c) = (i == c) ? 1.0 : 0.0;
+    Q.m(i, c) = 0.0;
+  }
+  __syncthreads();
+  const int np = (N + LG_PW - 1) / LG_PW;
+  for (int p = np - 1; p >= 0; --p) {
+    const int j0 = p * LG_PW, pw = min(LG_PW, N - j0);
+    const LgPanel pn{W, S.u0r, S.u0i, j0, pw};
+    lg_apply_panel<NC>(pn, tst + (size_t)p * LG_TDBL, Q, j0, N - j0, N - j0, F, false, S);
+  }
+}
+
+// Y <- Q^H Y (all N columns), forward over the panels.
+template <int NC>
+__device__ void lg_apply_qh(CMat W, int N, CMat Y, CMat F, const double* tst, SmemC<NC>& S) {
+  const int np = (N + LG_PW - 1) / LG_PW;
+  for (int p = 0; p < np; ++p) {
+    const int j0 = p * LG_PW, pw = min(LG_PW, N - j0);
+    const LgPanel pn{W, S.u0r, S.u0i, j0, pw};
+    lg_apply_panel<NC>(pn, tst + (size_t)p * LG_TDBL, Y, 0, N - j0, N, F, true, S);
+  }
+}
+
+// Y <- R^{-1} Y for the upper triangle R of W, by blocks of 16 rows from the
+// bottom: solve the diagonal block per column, then remove the block's
+// contribution from the rows above with one product.
+template <int NC>
+__device__ void lg_backsolve(CMat W, int N, CMat Y, SmemC<NC>& S) {
+  const int tid = threadIdx.x;
+  double* rr = S.lgt;          // R block, column-major 16 x 16
+  double* ri = S.lgt + 256;
+  const int nb = (N + LG_PW - 1) / LG_PW;
+  for (int b = nb - 1; b >= 0; --b) {
+    const int i0 = b * LG_PW, bw = min(LG_PW, N - i0);
+    if (tid < 256) {
+      const int i = tid % 16, k = tid / 16;
+      const bool in = i < bw && k < bw && i <= k;
+      rr[tid] = in ? W.r(i0 + i, i0 + k) : 0.0;
+      ri[tid] = in ? W.m(i0 + i, i0 + k) : 0.0;
+    }
+    __syncthreads();
+    for (int c = tid; c < N; c += WG) {
+      double yr[LG_PW], yi[LG_PW];
+#pragma unroll
+      for (int k = 0; k < LG_PW; ++k) {
+        yr[k] = k < bw ? Y.r(i0 + k, c) : 0.0;
+        yi[k] = k < bw ? Y.m(i0 + k, c) : 0.0;
+      }
+#pragma unroll
+      for (int i = LG_PW - 1; i >= 0; --i) {
+        if (i >= bw) continue;
+        double sr = yr[i], si = yi[i];
+#pragma unroll
+        for (int k = i + 1; k < LG_PW; ++k) {
+          const double a_r = rr[k * 16 + i], a_i = ri[k * 16 + i];
+          sr -= a_r * yr[k] - a_i * yi[k];
+          si -= a_r * yi[k] + a_i * yr[k];
+        }
+        const double dr = rr[i * 16 + i], di = ri[i * 16 + i];
+        const double den = dr * dr + di * di;
+        yr[i] = (sr * dr + si * di) / den;
+        yi[i] = (si * dr - sr * di) / den;
+      }
+#pragma unroll
+      for (int k = 0; k < LG_PW; ++k) {
+        if (k < bw) { Y.r(i0 + k, c) = yr[k]; Y.m(i0 + k, c) = yi[k]; }
+      }
+    }
+    __syncthreads();
+    if (i0 > 0) {
+      lg_gemm<128, 128, true, true>(
+          i0, N, bw,
+          [&](int i, int k, double& ar, double& ai) { ar = W.r(i, i0 + k); ai = W.m(i, i0 + k); },
+          [&](int k, int j, double& br, double& bi) { br = Y.r(i0 + k, j); bi = Y.m(i0 + k, j); },
+          [&](int i, int j, double cr, double ci) {
+            Y.r(i, j) -= cr;
+            Y.m(i, j) -= ci;
+          }, S.big);
+    }
+  }
+}
+
+}  // namespace fdet

@@ -43,14 +43,24 @@ struct BigLds {
   static constexpr int UB = 16 * ((NC + 15) / 16);           // one padded column
 };
 
+// LDS staging of the large class's macro-tiled product: two complex K panels
+// of 16 x 144 doubles (fdet_large.hpp)
+constexpr int LG_BIG = 2 * 2 * 16 * 144;
+
 // Shared state of size class NC (N <= NC): the scalar arrays of Smem plus a
 // large area used as the reflector / R triangle or as the product's panels.
 template <int NC>
 struct SmemC : Smem<(NC <= 128 ? 128 : 512)> {
-  double big[NC <= 128 ? BigLds<NC>::N : 1];
+  double big[NC <= 128 ? BigLds<NC>::N : LG_BIG];
   // current reflector as a full column (zero above its row), two buffers
   double ubr[2][NC <= 128 ? BigLds<NC>::UB : 1];
   double ubi[2][NC <= 128 ? BigLds<NC>::UB : 1];
+  // large class: T and V^H V of a panel (re, im), block-sum partials and
+  // sums, row j of a panel; two buffers each where consecutive steps overlap
+  double lgt[NC <= 128 ? 1 : 1024];
+  double lgred[NC <= 128 ? 1 : 2 * NWAVE * 32];
+  double lgsum[NC <= 128 ? 1 : 2 * 32];
+  double lgrow[NC <= 128 ? 1 : 2 * 32];
 };
 
 // index of (row r, column j) in the lower (reflector) triangle, r >= j

@@ -321,3 +321,29 @@ def test_batched_force(fd):
     Fs, _ = fd.force_batched(probs, s=4, checkpoint=8)
     for F, Fo in zip(Fs, refs):
         assert np.abs(F.cpu().numpy() - Fo).max() <= TOL_F
+
+
+# ---------------------------------------------------------------------------
+# N > 128: the large size class
+# ---------------------------------------------------------------------------
+
+# seeds with max |G| of a few: the absolute 1e-10 bar on G assumes O(1) entries
+@pytest.mark.parametrize("L,Nt,beta,s,seg,seed", [(9, 32, 4.0, 4, 2, 309), (10, 24, 3.0, 8, 1, 306)])
+def test_greens_large_class(fd, L, Nt, beta, s, seg, seed):
+    K = honeycomb_hopping(L)
+    dk = beta / Nt
+    phi = sample_phi(seed, Nt, K.shape[0], dk, 3.0)
+    ld, G = gpu_greens(fd, K, phi, dk, s=s, segments=seg)
+    lo, Go = O.stabilised_logdet_greens(K, dk, phi)
+    check_ld(ld, lo)
+    check_G(G, Go)
+
+
+def test_force_large_class(fd):
+    L, Nt, beta = 9, 16, 2.0
+    K = honeycomb_hopping(L)
+    dk = beta / Nt
+    phi = sample_phi(77, Nt, K.shape[0], dk, 3.0)
+    F = fd.force(to_dev(K), to_dev(phi), dk, s=4, checkpoint=8).cpu().numpy()
+    Fo = O.stabilised_force(K, dk, phi)
+    assert np.abs(F - Fo).max() <= TOL_F
