@@ -155,7 +155,10 @@ int fd_force_batched(const fd_problem *p, int32_t nprob, const fd_options *o,
  * be captured into a HIP graph and replayed; it reads K and phi at launch
  * time, so the caller updates phi in place between launches (the molecular
  * dynamics steps of HMC, Sec. 3.1).  Outputs as for the matching entry
- * point; G / force that `what` does not produce are ignored and may be NULL.
+ * point; force is ignored unless what = FD_WHAT_FORCE and may then be NULL.
+ * With FD_WHAT_FORCE, a non-NULL G (layout as for fd_greens_batched)
+ * receives G = M^{-1} = G~_1, which the force computes at its first
+ * checkpoint anyway; FD_WHAT_LOGDET ignores G.
  * The workspace must not be used by any other call while the plan is alive;
  * with FD_REUSE_E, exp(+-dk K) must already be in it from a call of the same
  * kind and options.  fd_plan_destroy frees host memory only.               */

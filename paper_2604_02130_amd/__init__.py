@@ -386,9 +386,12 @@ class Plan:
     what: "logdet", "greens" or "force"; problems: list of (K, phi, dk).
     reuse_e: compute exp(+-dk K) once now and skip it in every launch (K and
     dk must then stay fixed).
+    want_g: with "force", also return G = M^{-1} (the force's checkpoint at
+    row 0 already holds it).
     """
 
-    def __init__(self, what, problems, s=0, checkpoint=0, segments=0, reuse_e=False):
+    def __init__(self, what, problems, s=0, checkpoint=0, segments=0, reuse_e=False,
+                 want_g=False):
         torch = _torch()
         self.lib = load_library()
         self.what = _WHAT[what]
@@ -401,7 +404,7 @@ class Plan:
         self.ld = torch.empty((n, 2), dtype=torch.float64, device=dev)
         self.status = torch.empty(n, dtype=torch.int32, device=dev)
         self.G = self.Fr = self.Fi = None
-        if self.what == FD_WHAT_GREENS:
+        if self.what == FD_WHAT_GREENS or (self.what == FD_WHAT_FORCE and want_g):
             self.G = torch.empty(sum(2 * p.N * p.N for p in self.probs), dtype=torch.float64,
                                  device=dev)
         if self.what == FD_WHAT_FORCE:
@@ -434,18 +437,26 @@ class Plan:
         """Enqueue the plan's kernels on the current stream."""
         _check(self.lib.fd_plan_launch(self.handle, _stream()))
 
+    def greens(self):
+        """[G_i] views (greens, or force with want_g); [] otherwise."""
+        torch = _torch()
+        if self.G is None:
+            return []
+        out, off = [], 0
+        for p in self.probs:
+            m = 2 * p.N * p.N
+            out.append(torch.view_as_complex(self.G[off:off + m].view(p.N, p.N, 2)))
+            off += m
+        return out
+
     def results(self, check=False):
-        """Views of the outputs: logdet (n,) complex, plus [G_i] or [F_i]."""
+        """Outputs: logdet (n,) complex, plus [G_i] (greens) or [F_i] (force;
+        complex (Nt, N), built from the real and imaginary parts)."""
         torch = _torch()
         _status_check(self.status, check)
         ld = torch.view_as_complex(self.ld)
         if self.what == FD_WHAT_GREENS:
-            out, off = [], 0
-            for p in self.probs:
-                m = 2 * p.N * p.N
-                out.append(torch.view_as_complex(self.G[off:off + m].view(p.N, p.N, 2)))
-                off += m
-            return ld, out
+            return ld, self.greens()
         if self.what == FD_WHAT_FORCE:
             out, off = [], 0
             for p in self.probs:
@@ -469,23 +480,31 @@ class Plan:
 
 
 class Trajectory:
-    """The force and log det of a fixed K captured once as a graph and replayed
+    """The force and log det of fixed K captured once as a graph and replayed
     for each molecular-dynamics step of HMC (Sec. 3.1: every leapfrog step
     needs dH/dphi at the current field).
 
         traj = Trajectory(K, phi0, dk, s=8, checkpoint=16)
-        logdet, F = traj.step(phi)      # F: (Nt, N) complex, views of static outputs
+        logdet, F = traj.step(phi)      # F: (Nt, N) complex
+
+        traj = Trajectory(problems=[(K, phi_j, dk), ...], want_g=True)
+        logdets, Fs, Gs = traj.step([phi_j, ...])   # a batch in one graph
 
     exp(+-dk K) is computed once at construction; every replay runs the
-    chains, the checkpoint closes and the force sweep on the static copy of
-    phi (step() copies its argument in first).  Outputs are overwritten by the
-    next step(); clone them to keep them.
+    interval chains, the prefix / suffix scans, the checkpoint closes and the
+    force sweep on static copies of the fields (step() copies its arguments
+    in first).  Outputs are overwritten by the next step(); clone to keep.
     """
 
-    def __init__(self, K, phi, dk, s=0, checkpoint=0, what="force"):
+    def __init__(self, K=None, phi=None, dk=None, s=0, checkpoint=0, what="force", want_g=False,
+                 problems=None):
         torch = _torch()
-        self.phi = phi.clone()
-        self.plan = Plan(what, [(K, self.phi, dk)], s=s, checkpoint=checkpoint, reuse_e=True)
+        self.single = problems is None
+        if self.single:
+            problems = [(K, phi, dk)]
+        self.phis = [p.clone() for (_, p, _) in problems]
+        probs = [(Kj, ph, dkj) for (Kj, _, dkj), ph in zip(problems, self.phis)]
+        self.plan = Plan(what, probs, s=s, checkpoint=checkpoint, reuse_e=True, want_g=want_g)
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
@@ -497,12 +516,22 @@ class Trajectory:
             self.plan.launch()
         torch.cuda.synchronize()
 
+    def replay(self):
+        """Replay the captured step on the current static fields."""
+        self.graph.replay()
+
     def step(self, phi=None, check=True):
         if phi is not None:
-            self.phi.copy_(phi)
+            if self.single:
+                self.phis[0].copy_(phi)
+            else:
+                for dst, src in zip(self.phis, phi):
+                    dst.copy_(src)
         self.graph.replay()
         ld, outs = self.plan.results(check=check)
-        return ld[0], (outs[0] if outs else None)
+        if self.single:
+            return ld[0], (outs[0] if outs else None)
+        return ld, outs, self.plan.greens()
 
 
 def _logdet_function():

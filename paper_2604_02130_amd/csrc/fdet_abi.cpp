@@ -253,9 +253,9 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
       int lev = 0;
       for (; (1 << lev) < nc; ++lev) scan += 2 * (size_t)(nc - (1 << lev));
       maxlev = std::max(maxlev, lev);
-      // 2 exponentials, 2 nc interval chains + the identity, the scans, the
+      // 2 exponentials, nc interval chains + the identity, the scans, the
       // log-det close, nc force items
-      nitems += 2 + 2 * (size_t)nc + 1 + scan + 1 + nc;
+      nitems += 2 + (size_t)nc + 1 + scan + 1 + nc;
     } else {
       int lev = 0;
       while ((1 << lev) < nseg[i]) ++lev;
@@ -321,16 +321,19 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
       if (what == FD_WHAT_GREENS) z.flags = fdet::IF_WANT_G;
       close.push_back(z);
     } else {
-      // Checkpoint intervals [k c, (k+1) c): local products L_k and local
-      // adjoint products L_k^H in parallel, then inclusive scans of
-      // stabilised products (log2(nc) levels, Hillis-Steele):
-      //   prefix  Q_k = L_k ... L_0,        suffix  S_k = L_k^H ... L_{nc-1}^H,
-      // each entry in two buffers (read one, write the other per level).
-      // Checkpoint k uses Q_{k-1} (the identity for k = 0) and S_k.
+      // Checkpoint intervals [k c, (k+1) c): local products L_k in parallel,
+      // then two inclusive scans of stabilised products over them
+      // (log2(nc) levels each, Hillis-Steele, later factors on the left):
+      //   prefix  Q_k = L_k ... L_0,        suffix  S_k = L_{nc-1} ... L_k.
+      // Every scan entry lives in the interval buffer or one of two scan
+      // buffers (read one, write the other per level).  Checkpoint k uses
+      // Q_{k-1} (the identity for k = 0) and S_k, both in the X D T form
+      // with the unitary factor on the left.
       const int nc = nck[i];
       const size_t ub = udv_bytes(Np);
-      std::vector<Udv> fw[2], bw[2];
+      std::vector<Udv> base(nc), fw[2], bw[2];
       std::vector<double*> sf(nc), sb(nc);
+      for (int k = 0; k < nc; ++k) base[k] = make_udv(cur.take(ub), Np);
       for (int b = 0; b < 2; ++b) {
         fw[b].resize(nc);
         bw[b].resize(nc);
@@ -353,47 +356,48 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
         }
       }
       for (int k = 0; k < nc; ++k) {
-        for (int dir = 0; dir < 2; ++dir) {
-          Item c = blank_item(fdet::IK_CHAIN, i);
-          c.t0 = k * o.c;
-          c.t1 = std::min(q.Nt, (k + 1) * o.c);
-          c.s = o.s;
-          c.flags = fdet::IF_IDENTITY | (dir == 1 ? fdet::IF_ADJOINT : 0);
-          c.a = dir == 0 ? fw[0][k] : bw[0][k];
-          c.scr = dir == 0 ? sf[k] : sb[k];
-          chain.push_back(c);
-        }
+        Item c = blank_item(fdet::IK_CHAIN, i);
+        c.t0 = k * o.c;
+        c.t1 = std::min(q.Nt, (k + 1) * o.c);
+        c.s = o.s;
+        c.flags = fdet::IF_IDENTITY;
+        c.a = base[k];
+        c.scr = sf[k];
+        chain.push_back(c);
       }
       {
-        // empty range: the identity (writes no scratch, so sf[0] is shared)
+        // empty range: the identity (writes no scratch, so sb[0] is shared)
         Item c = blank_item(fdet::IK_CHAIN, i);
         c.s = o.s;
         c.flags = fdet::IF_IDENTITY;
         c.a = ident;
-        c.scr = sf[0];
+        c.scr = sb[0];
         chain.push_back(c);
       }
-      std::vector<int> cf(nc, 0), cb(nc, 0);   // buffer holding each entry
+      // where each entry lives: -1 the interval buffer, else scan buffer 0/1
+      std::vector<int> cf(nc, -1), cb(nc, -1);
+      auto at_f = [&](int k) { return cf[k] < 0 ? base[k] : fw[cf[k]][k]; };
+      auto at_b = [&](int k) { return cb[k] < 0 ? base[k] : bw[cb[k]][k]; };
       for (int l = 0; (1 << l) < nc; ++l) {
         const int d = 1 << l;
         std::vector<int> nf = cf, nb = cb;
         for (int k = d; k < nc; ++k) {        // Q_k <- Q_k Q_{k-d}
           Item c = blank_item(fdet::IK_COMBINE, i);
-          c.b = fw[cf[k]][k];
-          c.a = fw[cf[k - d]][k - d];
-          c.o = fw[1 - cf[k]][k];
+          nf[k] = cf[k] == 0 ? 1 : 0;
+          c.b = at_f(k);
+          c.a = at_f(k - d);
+          c.o = fw[nf[k]][k];
           c.scr = sf[k];
           comb[l].push_back(c);
-          nf[k] = 1 - cf[k];
         }
-        for (int k = 0; k + d < nc; ++k) {    // S_k <- S_k S_{k+d}
+        for (int k = 0; k + d < nc; ++k) {    // S_k <- S_{k+d} S_k
           Item c = blank_item(fdet::IK_COMBINE, i);
-          c.b = bw[cb[k]][k];
-          c.a = bw[cb[k + d]][k + d];
-          c.o = bw[1 - cb[k]][k];
+          nb[k] = cb[k] == 0 ? 1 : 0;
+          c.b = at_b(k + d);
+          c.a = at_b(k);
+          c.o = bw[nb[k]][k];
           c.scr = sb[k];
           comb[l].push_back(c);
-          nb[k] = 1 - cb[k];
         }
         cf = nf;
         cb = nb;
@@ -401,7 +405,7 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
       // log det of the whole product from Q_{nc-1}
       {
         Item z = blank_item(fdet::IK_CLOSE, i);
-        z.a = fw[cf[nc - 1]][nc - 1];
+        z.a = at_f(nc - 1);
         z.scr = sf[0];
         close.push_back(z);
       }
@@ -417,8 +421,8 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
         f.t0 = k * o.c;
         f.t1 = f.t0 + (gap_fwd + 1) / 2;
         f.nb = (nc == 1) ? q.Nt - (q.Nt + 1) / 2 : gap_bwd / 2;
-        f.a = k == 0 ? ident : fw[cf[k - 1]][k - 1];
-        f.b = bw[cb[k]][k];
+        f.a = k == 0 ? ident : at_f(k - 1);
+        f.b = at_b(k);
         f.scr = sf[k];
         forcei.push_back(f);
       }
@@ -698,7 +702,7 @@ int fd_plan_create(int32_t what, const fd_problem* p, int32_t nprob, const fd_op
     return fail(FD_ERR_INVALID_ARG, "create plans outside stream capture");
   Outs out;
   out.logdet = logdet;
-  out.G = what == FD_WHAT_GREENS ? G : nullptr;
+  out.G = G;   // FD_WHAT_FORCE: G from the checkpoint at row 0, if given
   out.force = what == FD_WHAT_FORCE ? force : nullptr;
   out.force_im = what == FD_WHAT_FORCE ? force_im : nullptr;
   out.status = status;

@@ -39,7 +39,9 @@ __device__ __forceinline__ CMat cmat_at(double* base, int Np) {
 // Per-workgroup shared state; MAXN bounds the problem size handled.
 template <int MAXN>
 struct Smem {
-  double norms[MAXN];   // partial column norms, by current column position
+  double norms[MAXN];   // partial column norms / scratch values by position
+  int tmp0[MAXN];       // scratch index maps of the pivot refresh
+  int tmp1[MAXN];
   double csp[MAXN];     // column scale key of the column at each position
   int piv[MAXN];        // original column index at each position
   int pinv[MAXN];       // inverse of piv

@@ -143,11 +143,10 @@ __device__ double block_max(double v, double* red) {
 // slice products
 // ---------------------------------------------------------------------------
 
-// One slice of the chain:
-//   forward  out = E diag(e^{i phi_t}) in        (B_t in)
-//   adjoint  out = diag(e^{-i phi_t}) E in       (B_t^H in, E real symmetric)
+// One slice of the chain: out = B_t in = E diag(e^{i phi_t}) in, one real x
+// complex product with the phases applied while the operand is staged.
 template <int NC>
-__device__ void slice_apply(const Prob& P, CMat in, CMat out, bool adj, SmemC<NC>& S) {
+__device__ void slice_apply(const Prob& P, CMat in, CMat out, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   const double* E = P.E;
   mm<NC, false, true>(
@@ -155,7 +154,7 @@ __device__ void slice_apply(const Prob& P, CMat in, CMat out, bool adj, SmemC<NC
       [&](int k, int j, double& br, double& bi) {
         if (k < N && j < N) {
           const double xr = in.r(k, j), xi = in.m(k, j);
-          const double c = adj ? 1.0 : S.phr[k], s = adj ? 0.0 : S.phi_[k];
+          const double c = S.phr[k], s = S.phi_[k];
           br = c * xr - s * xi;
           bi = s * xr + c * xi;
         } else {
@@ -163,11 +162,7 @@ __device__ void slice_apply(const Prob& P, CMat in, CMat out, bool adj, SmemC<NC
         }
       },
       [&](int i, int j, double cr, double ci) {
-        if (i < N && j < N) {
-          const double c = adj ? S.phr[i] : 1.0, s = adj ? S.phi_[i] : 0.0;
-          out.r(i, j) = c * cr + s * ci;
-          out.m(i, j) = c * ci - s * cr;
-        }
+        if (i < N && j < N) { out.r(i, j) = cr; out.m(i, j) = ci; }
       }, S);
 }
 
@@ -220,15 +215,14 @@ __device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, 
 
 template <int NC>
 __device__ void chain_chunk(const Prob& P, const Item& it, CMat X, CMat& Tc, CMat& Tt, double* D,
-                            CMat W, CMat Y2, int tfirst, int ns, bool adj, SmemC<NC>& S) {
+                            CMat W, CMat Y2, int tfirst, int ns, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   CMat src = X;
   CMat dst = (ns & 1) ? W : Y2;
   for (int q = 0; q < ns; ++q) {
-    const int t = adj ? tfirst - q : tfirst + q;
-    load_phases<NC>(P, t, S);
+    load_phases<NC>(P, tfirst + q, S);
     __syncthreads();
-    slice_apply<NC>(P, src, dst, adj, S);
+    slice_apply<NC>(P, src, dst, S);
     __syncthreads();
     src = dst;
     dst = (dst.re == W.re) ? Y2 : W;
@@ -254,7 +248,6 @@ __device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC
   CMat X = cmat_at(it.a.X, Np), T = cmat_at(it.a.T, Np);
   double* D = it.a.D;
   CMat W = cmat_at(it.scr, Np), Y2 = cmat_at(it.scr + cd, Np), Tn = cmat_at(it.scr + 2 * cd, Np);
-  const bool adj = (it.flags & IF_ADJOINT) != 0;
   if (threadIdx.x == 0) S.flag = 0;
   if (it.flags & IF_IDENTITY) {
     set_identity(X, N);
@@ -264,13 +257,9 @@ __device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC
   __syncthreads();
   CMat Tc = T, Tt = Tn;
   const int s = it.s;
-  // chunks of at most s slices: upward from t0, or downward from t1 - 1
-  const int nchunk = (it.t1 - it.t0 + s - 1) / s;
-  for (int ch = 0; ch < nchunk; ++ch) {
-    const int tfirst = adj ? it.t1 - 1 - ch * s : it.t0 + ch * s;
-    const int ns = adj ? min(s, tfirst - it.t0 + 1) : min(s, it.t1 - tfirst);
-    chain_chunk<NC>(P, it, X, Tc, Tt, D, W, Y2, tfirst, ns, adj, S);
-  }
+  // chunks of at most s slices upward from t0
+  for (int tfirst = it.t0; tfirst < it.t1; tfirst += s)
+    chain_chunk<NC>(P, it, X, Tc, Tt, D, W, Y2, tfirst, min(s, it.t1 - tfirst), S);
   if (Tc.re != T.re) {
     copy_cmat(T, Tc, N);
     __syncthreads();
@@ -280,11 +269,10 @@ __device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC
 
 // ---------------------------------------------------------------------------
 // IK_COMBINE and the shared stabilised product
-// result = A1 A2 with A1 = (X1, D1, T1) and A2 = (X2, D2, T2); when B_ADJ the
-// second operand is given by the UDV (Xs, Ds, Ts) of its adjoint, i.e.
-// X2 = Ts^H, D2 = Ds, T2 = Xs^H.
+// result = A1 A2 with A1 = (X1, D1, T1) and A2 = (X2, D2, T2): the bracket
+// D1 (T1 X2) D2 keeps a unitary factor in the middle product.
 // ---------------------------------------------------------------------------
-template <int NC, bool B_ADJ>
+template <int NC>
 __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMat Xo, CMat To,
                              double* Do, double* tst, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
@@ -301,12 +289,8 @@ __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMa
         else { ar = 0.0; ai = 0.0; }
       },
       [&](int k, int j, double& br, double& bi) {
-        if (k < N && j < N) {
-          if (B_ADJ) { br = T2.r(j, k); bi = -T2.m(j, k); }   // (Ts^H)(k,j)
-          else { br = X2.r(k, j); bi = X2.m(k, j); }
-        } else {
-          br = 0.0; bi = 0.0;
-        }
+        if (k < N && j < N) { br = X2.r(k, j); bi = X2.m(k, j); }
+        else { br = 0.0; bi = 0.0; }
       },
       [&](int i, int j, double cr, double ci) {
         if (i < N && j < N) { W.r(i, j) = S.v1[i] * cr; W.m(i, j) = S.v1[i] * ci; }
@@ -333,10 +317,7 @@ __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMa
       }, S);
   // T = T' Pi^T T2
   udv_new_t<NC>(W, N, Np,
-                  [&](int r, int j, double& br, double& bi) {
-                    if (B_ADJ) { br = X2.r(j, r); bi = -X2.m(j, r); }   // (Xs^H)(r,j)
-                    else { br = T2.r(r, j); bi = T2.m(r, j); }
-                  },
+                  [&](int r, int j, double& br, double& bi) { br = T2.r(r, j); bi = T2.m(r, j); },
                   To, S);
   __syncthreads();
   for (int i = threadIdx.x; i < N; i += WG) Do[i] = S.v2[i];
@@ -352,7 +333,7 @@ __device__ __forceinline__ void do_combine(const Prob& P, const Item& it, SmemC<
   double* Do = it.scr + 4 * cd;
   if (threadIdx.x == 0) S.flag = 0;
   // left factor b (the later slices), right factor a; result into o, or a
-  combine_core<NC, false>(P, it.b, it.a, W, Qb, Xo, To, Do, tstore(it.scr, Np), S);
+  combine_core<NC>(P, it.b, it.a, W, Qb, Xo, To, Do, tstore(it.scr, Np), S);
   const Udv& R = it.o.X ? it.o : it.a;
   copy_cmat(cmat_at(R.X, Np), Xo, N);
   copy_cmat(cmat_at(R.T, Np), To, N);
@@ -487,11 +468,19 @@ __device__ __forceinline__ void do_force(const Prob& P, const Item& it, SmemC<NC
   CMat Xc = cmat_at(it.scr + 2 * cd, Np), Tc = cmat_at(it.scr + 3 * cd, Np);
   double* Dc = it.scr + 4 * cd;
   if (threadIdx.x == 0) S.flag = 0;
-  // G~ at the first slice of the interval: (1 + P_k S_k)^{-1}
-  combine_core<NC, true>(P, it.a, it.b, W, Qb, Xc, Tc, Dc, tstore(it.scr, Np), S);
+  // G~ at the checkpoint row: (1 + Q_{k-1} S_k)^{-1}, prefix a, suffix b
+  combine_core<NC>(P, it.a, it.b, W, Qb, Xc, Tc, Dc, tstore(it.scr, Np), S);
   Udv U;
   U.X = Xc.re; U.T = Tc.re; U.D = Dc;
   do_close<NC>(P, U, W, Qb, W, true, false, tstore(it.scr, Np), S);
+  // the checkpoint at row 0 holds G~_1 = G = M^{-1} itself
+  if (it.t0 == 0 && P.G) {
+    for (int idx = threadIdx.x; idx < N * N; idx += WG) {
+      const int i = idx / N, j = idx % N;
+      P.G[2 * (size_t)idx] = W.r(i, j);
+      P.G[2 * (size_t)idx + 1] = W.m(i, j);
+    }
+  }
   // keep G~ of the checkpoint for the backward direction
   copy_cmat(Tc, W, N);
   const double* E = P.E;

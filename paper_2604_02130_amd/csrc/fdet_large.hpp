@@ -1,8 +1,9 @@
 // Workgroup primitives for 128 < N <= 512 (one workgroup of WG = 512 threads
 // per work item, matrices in device memory):
 //   lg_gemm       macro-tiled FP64 MFMA product with LDS-staged K panels,
-//   lg_qrp        pre-pivoted blocked Householder QR (compact WY panels of
-//                 16 reflectors, trailing updates as MFMA products),
+//   lg_qrp        column-pivoted blocked Householder QR (pivot order refreshed
+//                 per panel, compact WY panels of 16 reflectors, trailing
+//                 updates as MFMA products),
 //   lg_form_q     explicit Q by backward accumulation of the panels,
 //   lg_apply_qh   Y <- Q^H Y, panel by panel,
 //   lg_backsolve  Y <- R^{-1} Y, blocked by 16 rows.
@@ -158,26 +159,30 @@ __device__ void lg_gemm(int M, int Nc, int K, LA la, LB lb, ST st, double* lds) 
 }
 
 // Reflector matrix V of the panel at j0 (pw columns): V(r, c) for rows r of
-// the whole matrix, zero above row j0 + c, u0 on it, the tail below.
+// the whole matrix, zero above row j0 + c, u0 on it, the tail below.  While
+// the QR runs, position j lives in column cmap[j] of W (nullptr: column j).
 struct LgPanel {
   CMat W;
   const double* u0r;
   const double* u0i;
   int j0, pw;
+  const int* cmap;
   __device__ __forceinline__ void v(int r, int c, double& vr, double& vi) const {
     const int j = j0 + c;
-    if (r > j) { vr = W.r(r, j); vi = W.m(r, j); }
+    const int col = cmap ? cmap[j] : j;
+    if (r > j) { vr = W.r(r, col); vi = W.m(r, col); }
     else if (r == j) { vr = u0r[j]; vi = u0i[j]; }
     else { vr = 0.0; vi = 0.0; }
   }
 };
 
-// Y(r0:r0+M, 0:Nc) <- (I - V T' V^H) Y for one panel, T' = T (op = 0) or T^H
-// (op = 1).  Rows of V and Y are offset by r0 = j0; F is a free complex
-// matrix (ld = its own) holding V^H Y, then T' V^H Y.
+// Y(j0:j0+M, cols) <- (I - V T' V^H) Y for one panel, T' = T (herm false) or
+// T^H (herm true); cols are ycol0 .. ycol0+Nc-1, through ymap if given.  F is
+// a free complex matrix holding V^H Y, then T' V^H Y.
 template <int NC>
 __device__ void lg_apply_panel(const LgPanel& pn, const double* tp, CMat Y, int ycol0, int M, int Nc,
-                               CMat F, bool herm, SmemC<NC>& S) {
+                               CMat F, bool herm, const int* ymap, SmemC<NC>& S) {
+  auto ycol = [&](int j) { return ymap ? ymap[ycol0 + j] : ycol0 + j; };
   const int j0 = pn.j0, pw = pn.pw;
   // F(0:pw, 0:Nc) = V^H Y
   lg_gemm<16, 128, true, true>(
@@ -188,7 +193,8 @@ __device__ void lg_apply_panel(const LgPanel& pn, const double* tp, CMat Y, int 
         ar = vr; ai = -vi;
       },
       [&](int k, int j, double& br, double& bi) {
-        br = Y.r(j0 + k, ycol0 + j); bi = Y.m(j0 + k, ycol0 + j);
+        const int c = ycol(j);
+        br = Y.r(j0 + k, c); bi = Y.m(j0 + k, c);
       },
       [&](int i, int j, double cr, double ci) { F.r(i, j) = cr; F.m(i, j) = ci; }, S.big);
   // F <- T' F, column by column (T' is pw x pw from tp: re then im, T(i, k)
@@ -228,8 +234,9 @@ __device__ void lg_apply_panel(const LgPanel& pn, const double* tp, CMat Y, int 
       [&](int i, int k, double& ar, double& ai) { pn.v(j0 + i, k, ar, ai); },
       [&](int k, int j, double& br, double& bi) { br = F.r(k, j); bi = F.m(k, j); },
       [&](int i, int j, double cr, double ci) {
-        Y.r(j0 + i, ycol0 + j) -= cr;
-        Y.m(j0 + i, ycol0 + j) -= ci;
+        const int c = ycol(j);
+        Y.r(j0 + i, c) -= cr;
+        Y.m(j0 + i, c) -= ci;
       }, S.big);
 }
 
@@ -261,7 +268,8 @@ __device__ __forceinline__ void lg_block_sums(double* v, int buf, SmemC<NC>& S) 
 }
 
 // ---------------------------------------------------------------------------
-// lg_qrp: pre-pivoted blocked Householder QR of the N x N matrix in W (same
+// lg_qrp: blocked Householder QR of the N x N matrix in W with the pivot
+// order (partial norm x key) refreshed at every panel (same
 // contract as rq_qrp / wg_qrp: R in the upper triangle of W in pivoted column
 // order, reflector tails below it, S.u0r/u0i, S.beta, S.piv, S.pinv, S.csp,
 // S.rdr/rdi, S.nref), plus the T factor of every panel in tst.  F is a free
@@ -289,38 +297,62 @@ __device__ void lg_qrp(CMat W, int N, const double* keys, CMat F, double* tst, S
       const double kd = S.v3[d];
       pos += (kd > kc || (kd == kc && d < c)) ? 1 : 0;
     }
-    S.pinv[c] = pos;
     S.piv[pos] = c;
+    S.tmp1[pos] = c;   // position -> column of W while the QR runs
     S.csp[pos] = keys ? keys[c] : 1.0;
   }
   if (tid == 0) S.nref = 0;
   __syncthreads();
-  // ---- columns into pivot order (through F)
-  for (int idx = tid; idx < N * N; idx += WG) {
-    const int i = idx % N, k = idx / N;
-    const int c = S.piv[k];
-    F.r(i, k) = W.r(i, c);
-    F.m(i, k) = W.m(i, c);
-  }
-  __syncthreads();
-  for (int idx = tid; idx < N * N; idx += WG) {
-    const int i = idx % N, k = idx / N;
-    W.r(i, k) = F.r(i, k);
-    W.m(i, k) = F.m(i, k);
-  }
-  __syncthreads();
+  int* cmap = S.tmp1;
 
   const int r = tid;   // this thread's row of every panel
   int step = 0;
   for (int j0 = 0; j0 < N; j0 += LG_PW) {
     const int pw = min(LG_PW, N - j0);
+    // ---- pivot refresh: positions >= j0 by partial norm (rows >= j0) x key
+    if (j0 > 0 && j0 < N - 1) {
+      for (int k = j0 + wave; k < N; k += NWAVE) {
+        const int c = cmap[k];
+        double acc = 0.0;
+        for (int i = j0 + lane; i < N; i += 64) {
+          const double a = W.r(i, c), b = W.m(i, c);
+          acc += a * a + b * b;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) S.v3[k] = sqrt(acc) * S.csp[k];
+      }
+      __syncthreads();
+      for (int k = j0 + tid; k < N; k += WG) {
+        const double kk = S.v3[k];
+        int pos = j0;
+        for (int d = j0; d < N; ++d) {
+          const double kd = S.v3[d];
+          pos += (kd > kk || (kd == kk && d < k)) ? 1 : 0;
+        }
+        S.tmp0[pos] = k;
+      }
+      __syncthreads();
+      for (int p = j0 + tid; p < N; p += WG) {
+        const int k = S.tmp0[p];   // only this thread reads entry p
+        S.pinv[p] = cmap[k];
+        S.norms[p] = S.csp[k];
+        S.tmp0[p] = S.piv[k];
+      }
+      __syncthreads();
+      for (int p = j0 + tid; p < N; p += WG) {
+        cmap[p] = S.pinv[p];
+        S.csp[p] = S.norms[p];
+        S.piv[p] = S.tmp0[p];
+      }
+      __syncthreads();
+    }
     // ---- panel factorisation in registers (row r, columns j0 .. j0+pw-1)
     double pr[LG_PW], pi[LG_PW];
 #pragma unroll
     for (int c = 0; c < LG_PW; ++c) {
       const bool in = r >= j0 && r < N && c < pw;
-      pr[c] = in ? W.r(r, j0 + c) : 0.0;
-      pi[c] = in ? W.m(r, j0 + c) : 0.0;
+      pr[c] = in ? W.r(r, cmap[j0 + min(c, pw - 1)]) : 0.0;
+      pi[c] = in ? W.m(r, cmap[j0 + min(c, pw - 1)]) : 0.0;
     }
     static_for<0, LG_PW>([&](auto jc) {
       constexpr int JJ = decltype(jc)::value;
@@ -385,11 +417,11 @@ __device__ void lg_qrp(CMat W, int N, const double* keys, CMat F, double* tst, S
     if (r >= j0 && r < N) {
 #pragma unroll
       for (int c = 0; c < LG_PW; ++c) {
-        if (c < pw) { W.r(r, j0 + c) = pr[c]; W.m(r, j0 + c) = pi[c]; }
+        if (c < pw) { W.r(r, cmap[j0 + c]) = pr[c]; W.m(r, cmap[j0 + c]) = pi[c]; }
       }
     }
     __syncthreads();
-    const LgPanel pn{W, S.u0r, S.u0i, j0, pw};
+    const LgPanel pn{W, S.u0r, S.u0i, j0, pw, cmap};
     // ---- T factor: Gm = V^H V on the matrix cores (rows split over the
     // waves), then T(jj, jj) = beta_jj, T(0:jj, jj) = -beta_jj T(0:jj, 0:jj)
     // Gm(0:jj, jj)
@@ -453,9 +485,23 @@ __device__ void lg_qrp(CMat W, int N, const double* keys, CMat F, double* tst, S
     const int nt = N - j0 - pw;
     if (nt > 0) {
       const double* tp = tst + (size_t)(j0 / LG_PW) * LG_TDBL;
-      lg_apply_panel<NC>(pn, tp, W, j0 + pw, N - j0, nt, F, true, S);
+      lg_apply_panel<NC>(pn, tp, W, j0 + pw, N - j0, nt, F, true, cmap, S);
     }
   }
+  // ---- columns into position order (through F)
+  for (int idx = tid; idx < N * N; idx += WG) {
+    const int i = idx % N, k = idx / N;
+    const int c = cmap[k];
+    F.r(i, k) = W.r(i, c);
+    F.m(i, k) = W.m(i, c);
+  }
+  __syncthreads();
+  for (int idx = tid; idx < N * N; idx += WG) {
+    const int i = idx % N, k = idx / N;
+    W.r(i, k) = F.r(i, k);
+    W.m(i, k) = F.m(i, k);
+  }
+  for (int c = tid; c < N; c += WG) S.pinv[S.piv[c]] = c;
   __syncthreads();
 }
 
@@ -472,8 +518,8 @@ __device__ void lg_form_q(CMat W, int N, CMat Q, CMat F, const double* tst, Smem
   const int np = (N + LG_PW - 1) / LG_PW;
   for (int p = np - 1; p >= 0; --p) {
     const int j0 = p * LG_PW, pw = min(LG_PW, N - j0);
-    const LgPanel pn{W, S.u0r, S.u0i, j0, pw};
-    lg_apply_panel<NC>(pn, tst + (size_t)p * LG_TDBL, Q, j0, N - j0, N - j0, F, false, S);
+    const LgPanel pn{W, S.u0r, S.u0i, j0, pw, nullptr};
+    lg_apply_panel<NC>(pn, tst + (size_t)p * LG_TDBL, Q, j0, N - j0, N - j0, F, false, nullptr, S);
   }
 }
 
@@ -483,8 +529,8 @@ __device__ void lg_apply_qh(CMat W, int N, CMat Y, CMat F, const double* tst, Sm
   const int np = (N + LG_PW - 1) / LG_PW;
   for (int p = 0; p < np; ++p) {
     const int j0 = p * LG_PW, pw = min(LG_PW, N - j0);
-    const LgPanel pn{W, S.u0r, S.u0i, j0, pw};
-    lg_apply_panel<NC>(pn, tst + (size_t)p * LG_TDBL, Y, 0, N - j0, N, F, true, S);
+    const LgPanel pn{W, S.u0r, S.u0i, j0, pw, nullptr};
+    lg_apply_panel<NC>(pn, tst + (size_t)p * LG_TDBL, Y, 0, N - j0, N, F, true, nullptr, S);
   }
 }
 

@@ -29,13 +29,12 @@ enum ItemKind : int32_t {
   IK_CHAIN = 1,     // stabilised product of a range of slices
   IK_COMBINE = 2,   // UDV(o or a) <- UDV(b) x UDV(a): stabilised product of two
   IK_CLOSE = 3,     // log det (+ G) from a UDV
-  IK_FORCE = 4,     // G~ at a checkpoint from its prefix (a) and adjoint suffix (b),
+  IK_FORCE = 4,     // G~ at a checkpoint from its prefix (a) and suffix (b),
                     // then carried forward and backward
   IK_EXPORT = 5,    // copy a UDV out in user layout
 };
 
 enum ItemFlags : int32_t {
-  IF_ADJOINT = 1,      // chain: B_{t0}^H ... B_{t1-1}^H instead of B_{t1-1} ... B_{t0}
   IF_IDENTITY = 2,     // chain: start from the identity
   IF_WANT_G = 8,       // close: also form G
 };
@@ -53,7 +52,7 @@ struct Item {
   int32_t s, pad0;      // stabilisation interval
   int32_t nb, pad1;     // force: rows t0-1, ..., t0-nb (mod N_t) carried backward
   Udv a;                // state / right operand / result
-  Udv b;                // left operand (combine), adjoint suffix (force)
+  Udv b;                // left operand (combine), suffix product (force)
   Udv o;                // combine: result (X == nullptr: into a)
   double* scr;          // scratch: 4 cmats + 2*Np doubles
 };

@@ -164,14 +164,83 @@ __device__ __forceinline__ void rq_reflect_all(double beta, const double* ur, co
   }
 }
 
+// Pivot refresh at the start of row phase JB (step j = 16 JB): the columns
+// at positions >= j are ordered again by partial norm (rows >= j) x key,
+// decreasing, ties to the lower position, and moved to their new slots
+// through W.  Positions < j (finished) stay in place.
+template <int NC, int JB, int QLO>
+__device__ __forceinline__ void rq_repivot(CMat W, int N,
+                                           double (&ar)[RegClass<NC>::CPL][RegClass<NC>::RPL],
+                                           double (&ai)[RegClass<NC>::CPL][RegClass<NC>::RPL],
+                                           SmemC<NC>& S) {
+  constexpr int CPL = RegClass<NC>::CPL, RPL = RegClass<NC>::RPL;
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  const int l16 = lane & 15, grp = wave * 4 + (lane >> 4);
+  const int j = 16 * JB;
+#pragma unroll
+  for (int q = QLO; q < CPL; ++q) {
+    const int k = grp + 32 * q;
+    double s = 0.0;
+#pragma unroll
+    for (int m = JB; m < RPL; ++m) s += ar[q][m] * ar[q][m] + ai[q][m] * ai[q][m];
+    s = red16(s);
+    if (k >= j && k < N) {
+      if (l16 == 0) S.v3[k] = sqrt(s) * S.csp[k];
+#pragma unroll
+      for (int m = 0; m < RPL; ++m) {
+        const int r = l16 + 16 * m;
+        if (r < N) { W.r(r, k) = ar[q][m]; W.m(r, k) = ai[q][m]; }
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = j + tid; k < N; k += WG) {
+    const double kk = S.v3[k];
+    int pos = j;
+    for (int d = j; d < N; ++d) {
+      const double kd = S.v3[d];
+      pos += (kd > kk || (kd == kk && d < k)) ? 1 : 0;
+    }
+    S.tmp0[pos] = k;   // new position pos takes old position k
+  }
+  __syncthreads();
+  for (int p = j + tid; p < N; p += WG) {
+    const int k = S.tmp0[p];
+    S.tmp1[p] = S.piv[k];
+    S.norms[p] = S.csp[k];
+  }
+  __syncthreads();
+  for (int p = j + tid; p < N; p += WG) {
+    S.piv[p] = S.tmp1[p];
+    S.csp[p] = S.norms[p];
+  }
+#pragma unroll
+  for (int q = QLO; q < CPL; ++q) {
+    const int p = grp + 32 * q;
+    if (p >= j && p < N) {
+      const int k = S.tmp0[p];
+#pragma unroll
+      for (int m = 0; m < RPL; ++m) {
+        const int r = l16 + 16 * m;
+        ar[q][m] = r < N ? W.r(r, k) : 0.0;
+        ai[q][m] = r < N ? W.m(r, k) : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
-// rq_qrp: pre-pivoted Householder QR of the N x N matrix in W.
+// rq_qrp: column-pivoted Householder QR of the N x N matrix in W, with the
+// pivot order refreshed every 16 columns.
 //
-// The columns are ordered once by key = |column| x keys[c] (keys == nullptr:
-// 1), decreasing, ties to the lower index, and then factorised without
-// further pivoting.  Householder QR treats every column independently of its
-// scale, so ordering by |column| x keys[c] is the pivot order of
-// W diag(keys) while all arithmetic stays on W.
+// The columns are ordered by key = |column| x keys[c] (keys == nullptr: 1),
+// decreasing, ties to the lower index; every 16 columns the remaining ones
+// are ordered again by their partial norms (rows not yet eliminated) x key.
+// Householder QR treats every column independently of its scale, so this is
+// the pivot order of W diag(keys) while all arithmetic stays on W.  Ordering
+// once at the start is not enough: for (near-)degenerate scales the T
+// factors of the UDV products then grow from product to product.
 //
 // Same contract as wg_qrp (R in the upper triangle of W in pivoted column
 // order, S.u0r/u0i, S.beta, S.piv, S.csp, S.nref) plus S.pinv[c] = position
@@ -247,6 +316,9 @@ __device__ void rq_qrp(CMat W, int N, const double* keys, SmemC<NC>& S) {
   static_for<0, RPL>([&](auto jbc) {
     constexpr int JB = decltype(jbc)::value;
     constexpr int QLO = JB / 2;
+    if constexpr (JB > 0) {
+      if (16 * JB < N - 1) rq_repivot<NC, JB, QLO>(W, N, ar, ai, S);
+    }
     const int jend = min(16 * JB + 16, N);
     for (int j = 16 * JB; j < jend; ++j) {
       const int buf = j & 1;

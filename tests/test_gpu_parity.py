@@ -347,3 +347,29 @@ def test_force_large_class(fd):
     F = fd.force(to_dev(K), to_dev(phi), dk, s=4, checkpoint=8).cpu().numpy()
     Fo = O.stabilised_force(K, dk, phi)
     assert np.abs(F - Fo).max() <= TOL_F
+
+
+def test_hmc_step_L16_sampled(fd):
+    """The largest configuration: L = 16 (N = 512), N_t = 512, beta = 64, two of
+    the step's fields in one batched force plan with G.  Log det and G of the
+    first field against the stabilised oracle (QR every 8 slices), force rows
+    1 and 257 against G of the field rotated to start at that slice."""
+    from workload import hmc_batch
+    ws = hmc_batch(2)
+    probs = [(to_dev(w.K()), to_dev(w.phi()), w.dk) for w in ws]
+    plan = fd.Plan("force", probs, s=ws[0].s, checkpoint=ws[0].c, want_g=True)
+    plan.launch()
+    ld, Fs = plan.results(check=True)
+    Gs = plan.greens()
+    w = ws[0]
+    K, phi = w.K(), w.phi()
+    lo, Go = O.sporadic_logdet_greens(K, w.dk, phi, 8)
+    check_ld(ld[0].item(), lo)
+    G = Gs[0].cpu().numpy()
+    tol_g = TOL_G * max(1.0, np.abs(Go).max())
+    assert np.abs(G - Go).max() <= tol_g
+    F = Fs[0].cpu().numpy()
+    assert np.abs(F[0] - 1j * (1.0 - np.diag(Go))).max() <= tol_g
+    _, Gt = O.sporadic_logdet_greens(K, w.dk, np.roll(phi, -256, axis=0), 8)
+    assert np.abs(F[256] - 1j * (1.0 - np.diag(Gt))).max() <= TOL_F * max(1.0, np.abs(Gt).max())
+    assert np.abs(F.imag - 0.5).max() < 1e-9

@@ -154,3 +154,43 @@ def test_autotune_and_tuned_defaults(fd, tmp_path):
     fb = fd.autotune([(K, phi, w.dk)], what="force", checkpoint=8)
     assert fb["s"] in (4, 8, 16) and fb["checkpoint"] == 8
     fd.tune_clear()
+
+
+def test_force_plan_returns_greens(fd):
+    """The force step's checkpoint at row 0 is G itself."""
+    import torch
+    K, phi, dk = small_problem(L=3, Nt=32, beta=4.0)
+    Kd, pd = to_dev(K), to_dev(phi)
+    plan = fd.Plan("force", [(Kd, pd, dk)], s=4, checkpoint=8, want_g=True)
+    plan.launch()
+    ld, Fs = plan.results(check=True)
+    (G,) = plan.greens()
+    lo, Go = O.stabilised_logdet_greens(K, dk, phi)
+    assert np.abs(G.cpu().numpy() - Go).max() <= TOL
+    assert wrapped_err(ld[0].item(), lo) <= TOL
+    F_e = fd.force(Kd, pd, dk, s=4, checkpoint=8)
+    assert torch.equal(Fs[0], F_e)
+
+
+def test_batched_trajectory(fd):
+    """A batch of fields in one captured step: log det, G and force of each,
+    replayed on new fields, against the eager calls."""
+    import torch
+    probs, fields = [], []
+    for i, (L, Nt) in enumerate([(2, 24), (3, 16), (2, 9)]):
+        K = honeycomb_hopping(L)
+        phi = sample_phi(70 + i, Nt, K.shape[0], 0.25, 3.0)
+        probs.append((to_dev(K), to_dev(phi), 0.25))
+        fields.append(phi)
+    traj = fd.Trajectory(problems=probs, s=4, checkpoint=8, want_g=True)
+    rng = np.random.default_rng(3)
+    for rep in range(3):
+        new = [f + 0.05 * rep * rng.normal(size=f.shape) for f in fields]
+        ld, Fs, Gs = traj.step([to_dev(f) for f in new])
+        torch.cuda.synchronize()
+        for j, ((Kd, _, dk), f) in enumerate(zip(probs, new)):
+            F_e, ld_e = fd.force(Kd, to_dev(f), dk, s=4, checkpoint=8, with_logdet=True)
+            assert torch.equal(Fs[j], F_e), (rep, j)
+            assert torch.equal(ld[j], ld_e), (rep, j)
+            _, G_e = fd.greens(Kd, to_dev(f), dk, s=4, segments=1)
+            assert np.abs(Gs[j].cpu().numpy() - G_e.cpu().numpy()).max() <= TOL

@@ -240,6 +240,18 @@ def test_force_first_row_is_greens_diagonal():
     assert np.abs(F[0] - 1j * (1.0 - np.diag(G))).max() < 1e-12
 
 
+def test_force_row_is_greens_of_rotated_field():
+    """Row t of the force is i(1 - diag G) of the field rotated so that slice
+    t acts first: that product is B_{t-1}...B_1 B_{N_t}...B_t.  This is the
+    cheap oracle for sampled force rows at the largest sizes."""
+    K, dk, phi = case(3, 16, 4.0)
+    rows = [1, 6, 16]
+    F = O.stabilised_force_rows(K, dk, phi, rows)
+    for k, t in enumerate(rows):
+        _, Gt = O.sporadic_logdet_greens(K, dk, np.roll(phi, -(t - 1), axis=0), 4)
+        assert np.abs(F[k] - 1j * (1.0 - np.diag(Gt))).max() < 1e-12
+
+
 def test_force_finite_differences():
     K, dk, phi = case(3, 16, 4.0)
     F = O.stabilised_force(K, dk, phi)
