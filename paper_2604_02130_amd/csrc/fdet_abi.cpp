@@ -235,6 +235,97 @@ int validate(const fd_problem* p, int nprob, const Opts& o) {
   return FD_OK;
 }
 
+// ---- inclusive scans of stabilised products for the force checkpoints
+//
+// Sequence x_0 .. x_{n-1}; entry i is P_i = x_i o ... o x_0 where `later_left`
+// puts higher indices on the left (prefix Q_k = L_k ... L_0) or on the right
+// (suffix S_k = L_{n-1} ... L_k, run over i = n-1-k).  Groups of g entries:
+// a sequential scan inside each group (g - 1 levels), a Hillis-Steele scan
+// of the group totals (log2(n/g) levels, two buffers), then one product per
+// entry with the total of all earlier groups (one level).  g = 1 is a plain
+// Hillis-Steele scan (depth log2 n, n log2 n products); larger g does about
+// 2n products for a few more levels, which wins once a batch fills the GPU.
+//
+// Slots: [0, n) the inputs x_i, [n, 2n) entry buffers, [2n, 2n+G) and
+// [2n+G, 2n+2G) the two group-total buffers.
+struct ScanOp {
+  int level, left, right, out, scr;
+};
+
+struct ScanPlan {
+  std::vector<ScanOp> ops;
+  std::vector<int> final_slot;   // slot holding P_i at the end
+  int levels = 0;
+  bool uses_entries = false;
+};
+
+ScanPlan scan_schedule(int n, int g, bool later_left) {
+  ScanPlan sp;
+  const int G = (n + g - 1) / g;
+  std::vector<int> loc(n);
+  for (int i = 0; i < n; ++i) loc[i] = i;
+  auto push = [&](int level, int later, int earlier, int out, int scr) {
+    ScanOp op;
+    op.level = level;
+    op.left = later_left ? later : earlier;
+    op.right = later_left ? earlier : later;
+    op.out = out;
+    op.scr = scr;
+    sp.ops.push_back(op);
+    sp.levels = std::max(sp.levels, level + 1);
+  };
+  int level = 0;
+  // phase 1: inside each group
+  for (int l = 1; l < g; ++l, ++level) {
+    for (int b = 0; b < G; ++b) {
+      const int i = b * g + l;
+      if (i >= std::min(n, (b + 1) * g)) continue;
+      push(level, loc[i], loc[i - 1], n + i, i);
+      loc[i] = n + i;
+      sp.uses_entries = true;
+    }
+  }
+  // phase 2: group totals
+  std::vector<int> last(G), hloc(G), hbuf(G, -1);
+  for (int b = 0; b < G; ++b) {
+    last[b] = std::min(n, (b + 1) * g) - 1;
+    hloc[b] = loc[last[b]];
+  }
+  for (int d = 1; d < G; d *= 2, ++level) {
+    std::vector<int> nloc = hloc, nbuf = hbuf;
+    for (int b = d; b < G; ++b) {
+      nbuf[b] = hbuf[b] == 0 ? 1 : 0;
+      nloc[b] = 2 * n + nbuf[b] * G + b;
+      push(level, hloc[b], hloc[b - d], nloc[b], last[b]);
+    }
+    hloc = nloc;
+    hbuf = nbuf;
+  }
+  // phase 3: earlier groups' total into every entry but each group's last
+  bool any = false;
+  for (int b = 1; b < G; ++b) {
+    for (int i = b * g; i < last[b]; ++i) {
+      push(level, loc[i], hloc[b - 1], n + i, i);
+      loc[i] = n + i;
+      any = true;
+      sp.uses_entries = true;
+    }
+  }
+  if (any) ++level;
+  for (int b = 0; b < G; ++b) loc[last[b]] = hloc[b];
+  sp.final_slot = loc;
+  return sp;
+}
+
+// Group size of the checkpoint scans: plain Hillis-Steele while the scans of
+// the whole plan leave the compute units idle, groups of 4 once two rounds
+// of work items fill them.
+int scan_group(const fd_problem* p, int nprob, const Opts& o) {
+  long long items = 0;
+  for (int i = 0; i < nprob; ++i) items += 2LL * ((p[i].Nt + o.c - 1) / o.c);
+  return items >= 2LL * device_cu_count() ? 4 : 1;
+}
+
 // Build the layout and the work items.  `what` = FD_WHAT_*.
 void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* base, Plan& pl) {
   pl.probs.assign(nprob, Prob{});
@@ -243,16 +334,16 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   // count items to size the descriptor region
   const bool force = what == FD_WHAT_FORCE;
   std::vector<int> nseg = plan_segments(p, nprob, o), nck(nprob);
+  const int sgroup = force ? scan_group(p, nprob, o) : 1;
   int maxlev = 0;
   for (int i = 0; i < nprob; ++i) {
     pl.maxN = std::max(pl.maxN, p[i].N);
     if (force) {
       const int nc = (p[i].Nt + o.c - 1) / o.c;
       nck[i] = nc;
-      size_t scan = 0;
-      int lev = 0;
-      for (; (1 << lev) < nc; ++lev) scan += 2 * (size_t)(nc - (1 << lev));
-      maxlev = std::max(maxlev, lev);
+      const ScanPlan sp = scan_schedule(nc, sgroup, true);
+      const size_t scan = 2 * sp.ops.size();
+      maxlev = std::max(maxlev, sp.levels);
       // 2 exponentials, nc interval chains + the identity, the scans, the
       // log-det close, nc force items
       nitems += 2 + (size_t)nc + 1 + scan + 1 + nc;
@@ -331,18 +422,22 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
       // with the unitary factor on the left.
       const int nc = nck[i];
       const size_t ub = udv_bytes(Np);
-      std::vector<Udv> base(nc), fw[2], bw[2];
-      std::vector<double*> sf(nc), sb(nc);
+      const ScanPlan spf = scan_schedule(nc, sgroup, true);
+      const ScanPlan spb = scan_schedule(nc, sgroup, false);
+      const int G = (nc + sgroup - 1) / sgroup;
+      // slots of the two scans (see scan_schedule); inputs are shared
+      std::vector<Udv> base(nc), slf(2 * nc + 2 * G), slb(2 * nc + 2 * G);
       for (int k = 0; k < nc; ++k) base[k] = make_udv(cur.take(ub), Np);
-      for (int b = 0; b < 2; ++b) {
-        fw[b].resize(nc);
-        bw[b].resize(nc);
-        for (int k = 0; k < nc; ++k) {
-          fw[b][k] = make_udv(cur.take(ub), Np);
-          bw[b][k] = make_udv(cur.take(ub), Np);
-        }
+      for (int dir = 0; dir < 2; ++dir) {
+        std::vector<Udv>& sl = dir == 0 ? slf : slb;
+        // prefix sequence index i is interval i; suffix index i is nc-1-i
+        for (int i2 = 0; i2 < nc; ++i2) sl[i2] = base[dir == 0 ? i2 : nc - 1 - i2];
+        if (spf.uses_entries)
+          for (int i2 = 0; i2 < nc; ++i2) sl[nc + i2] = make_udv(cur.take(ub), Np);
+        for (int b = 0; b < 2 * G; ++b) sl[2 * nc + b] = make_udv(cur.take(ub), Np);
       }
       const Udv ident = make_udv(cur.take(ub), Np);
+      std::vector<double*> sf(nc), sb(nc);
       for (int k = 0; k < nc; ++k) {
         sf[k] = cur.take(scratch_bytes(Np));
         sb[k] = cur.take(scratch_bytes(Np));
@@ -374,34 +469,22 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
         c.scr = sb[0];
         chain.push_back(c);
       }
-      // where each entry lives: -1 the interval buffer, else scan buffer 0/1
-      std::vector<int> cf(nc, -1), cb(nc, -1);
-      auto at_f = [&](int k) { return cf[k] < 0 ? base[k] : fw[cf[k]][k]; };
-      auto at_b = [&](int k) { return cb[k] < 0 ? base[k] : bw[cb[k]][k]; };
-      for (int l = 0; (1 << l) < nc; ++l) {
-        const int d = 1 << l;
-        std::vector<int> nf = cf, nb = cb;
-        for (int k = d; k < nc; ++k) {        // Q_k <- Q_k Q_{k-d}
+      for (int dir = 0; dir < 2; ++dir) {
+        const ScanPlan& sp = dir == 0 ? spf : spb;
+        const std::vector<Udv>& sl = dir == 0 ? slf : slb;
+        const std::vector<double*>& sc = dir == 0 ? sf : sb;
+        for (const ScanOp& op : sp.ops) {
           Item c = blank_item(fdet::IK_COMBINE, i);
-          nf[k] = cf[k] == 0 ? 1 : 0;
-          c.b = at_f(k);
-          c.a = at_f(k - d);
-          c.o = fw[nf[k]][k];
-          c.scr = sf[k];
-          comb[l].push_back(c);
+          c.b = sl[op.left];
+          c.a = sl[op.right];
+          c.o = sl[op.out];
+          c.scr = sc[op.scr];
+          comb[op.level].push_back(c);
         }
-        for (int k = 0; k + d < nc; ++k) {    // S_k <- S_{k+d} S_k
-          Item c = blank_item(fdet::IK_COMBINE, i);
-          nb[k] = cb[k] == 0 ? 1 : 0;
-          c.b = at_b(k + d);
-          c.a = at_b(k);
-          c.o = bw[nb[k]][k];
-          c.scr = sb[k];
-          comb[l].push_back(c);
-        }
-        cf = nf;
-        cb = nb;
       }
+      // Q_k: prefix entry k; S_k: suffix entry nc-1-k
+      auto at_f = [&](int k) { return slf[spf.final_slot[k]]; };
+      auto at_b = [&](int k) { return slb[spb.final_slot[nc - 1 - k]]; };
       // log det of the whole product from Q_{nc-1}
       {
         Item z = blank_item(fdet::IK_CLOSE, i);

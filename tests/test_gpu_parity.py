@@ -373,3 +373,17 @@ def test_hmc_step_L16_sampled(fd):
     _, Gt = O.sporadic_logdet_greens(K, w.dk, np.roll(phi, -256, axis=0), 8)
     assert np.abs(F[256] - 1j * (1.0 - np.diag(Gt))).max() <= TOL_F * max(1.0, np.abs(Gt).max())
     assert np.abs(F.imag - 0.5).max() < 1e-9
+
+
+@pytest.mark.parametrize("Nt,c", [(300, 1), (301, 1)])
+def test_force_grouped_scan(fd, Nt, c):
+    """Enough checkpoint intervals that the prefix / suffix scans run in
+    groups (sequential in a group, log-depth over the group totals)."""
+    K = honeycomb_hopping(2)
+    dk = 0.1
+    phi = sample_phi(900 + Nt, Nt, 8, dk, 3.0)
+    F, ld = fd.force(to_dev(K), to_dev(phi), dk, s=4, checkpoint=c, with_logdet=True)
+    Fo = O.stabilised_force(K, dk, phi)
+    assert np.abs(F.cpu().numpy() - Fo).max() <= TOL_F
+    lo, _ = O.stabilised_logdet_greens(K, dk, phi)
+    check_ld(complex(ld.item()), lo)
