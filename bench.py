@@ -14,7 +14,10 @@ Printed as one JSON line, with
   force         HMC force evals/s (L = 8, N = 128, N_t = 256): checkpointed
                 adjoint (c = 16) against the plain per-slice inversion (c = 1),
   batched       256 mixed-size configurations: one launch sequence against
-                one configuration per call.
+                one configuration per call,
+  hmc_step      the largest configuration: 32 fields of L = 16 (N = 512),
+                N_t = 512, beta = 64; log det, G and force of every field in
+                one replay of a captured graph.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -70,14 +73,11 @@ def det_flops(N, Nt, s, nseg):
     return f + (nseg - 1) * combine_flops(N) + close_flops(N) + 12.0 * N ** 3
 
 
-def force_flops(N, Nt, s, c):
-    """Prefix and suffix chains with checkpoints, then per checkpoint interval
-    one combine + close + G, and two real-by-complex products (8N^3) per
-    carried slice."""
-    nck = math.ceil(Nt / c)
-    f = 2 * chain_flops(N, Nt, s) + 2 * 32.0 * N ** 3
-    f += nck * (combine_flops(N) + close_flops(N)) + (Nt - nck) * 8.0 * N ** 3
-    return f + close_flops(N, want_g=False)
+def alg_force_flops(N, Nt, s, c):
+    """Algorithmic FLOP of one force evaluation (log det, G and the force):
+    F_det + N^3 Nt (12 + 14.67/s + 64/c) -- a suffix chain, two products per
+    carried slice and a recomputation of G~ at every checkpoint."""
+    return alg_det_flops(N, Nt, s) + N ** 3 * Nt * (12.0 + (16 / 3 + 16 / 3 + 4.0) / s + 64.0 / c)
 
 
 def src_digest():
@@ -113,7 +113,8 @@ def main():
     ap.add_argument("--segments", type=int, default=0,
                     help="time segments (0 = chosen by the library's autotuner before timing)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the force and batched legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the force, batched and HMC legs")
+    ap.add_argument("--no-hmc", action="store_true", help="skip the 32-field L=16 HMC step")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -128,7 +129,7 @@ def main():
     import torch
 
     import paper_2604_02130_amd as fd
-    from workload import WORKLOADS, batched_mix
+    from workload import WORKLOADS, batched_mix, hmc_batch
 
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
@@ -288,7 +289,7 @@ def main():
             torch.cuda.synchronize()
             dt = (time.perf_counter() - a) / reps
             out[label] = {"force_evals_per_s": 1.0 / dt, "ms": dt * 1e3,
-                          "model_tflop_s": force_flops(wf.N, wf.Nt, wf.s, c) / dt / 1e12}
+                          "alg_tflop_s": alg_force_flops(wf.N, wf.Nt, wf.s, 16) / dt / 1e12}
             print(f"[bench] force {label}: {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
         out["workload"] = "force_L8: honeycomb L=8 (N=128), Nt=256, beta=32, U=3, s=8"
         out["adjoint_vs_plain"] = out["adjoint_c16"]["force_evals_per_s"] / out["plain_c1"]["force_evals_per_s"]
@@ -328,6 +329,38 @@ def main():
         }
         print(f"[bench] batched {dtb * 1e3:.1f} ms vs plain {dtp * 1e3:.1f} ms",
               file=sys.stderr, flush=True)
+
+        # ---------------- largest configuration: one HMC step of 32 fields
+        if not args.no_hmc:
+            hb = hmc_batch(32)
+            Kh = torch.from_numpy(hb[0].K()).to(dev)
+            hprobs = [(Kh, torch.from_numpy(wb.phi()).to(dev), wb.dk) for wb in hb]
+            a = time.perf_counter()
+            traj = fd.Trajectory(problems=hprobs, s=hb[0].s, checkpoint=hb[0].c, want_g=True)
+            setup = time.perf_counter() - a
+            traj.replay()
+            torch.cuda.synchronize()
+            reps = 2
+            a = time.perf_counter()
+            for _ in range(reps):
+                traj.replay()
+            torch.cuda.synchronize()
+            dth = (time.perf_counter() - a) / reps
+            st_h = traj.plan.status.cpu()
+            if int(st_h.min()) < 0:
+                raise SystemExit(f"HMC step status {st_h.tolist()}")
+            hflops = sum(alg_force_flops(wb.N, wb.Nt, wb.s, wb.c) for wb in hb)
+            result["hmc_step"] = {
+                "workload": "32 fields, honeycomb L=16 (N=512), Nt=512, beta=64, U=3, s=16, "
+                            "c=16; log det, G and full force per field in one graph replay",
+                "step_s": dth,
+                "force_evals_per_s": len(hb) / dth,
+                "alg_tflop_s": hflops / dth / 1e12,
+                "fp64_mfma_pct_peak": 100.0 * hflops / dth / PEAK_FP64_MFMA,
+                "setup_s": setup,
+            }
+            print(f"[bench] HMC step L16 x32: {dth:.3f} s", file=sys.stderr, flush=True)
+            del traj
 
     print(json.dumps(result), flush=True)
 

@@ -126,8 +126,8 @@ int fd_force(const fd_problem *p, const fd_options *o, double *logdet, double *f
 
 /* The stabilised factorisation B_{N_t}...B_1 = X diag(D) T (eq.
  * def_matrix_as_product with T = Y^{-1}): X unitary, D >= 0 in decreasing
- * order up to the conditioning of one stabilisation interval (the columns are
- * pre-sorted before each QR), |det T| = 1.  X, T: N*N complex row-major;
+ * order up to the conditioning of one stabilisation interval (the pivot order
+ * of each QR is refreshed every 16 columns), |det T| = 1.  X, T: N*N complex row-major;
  * D: N doubles.                                                              */
 int fd_udv(const fd_problem *p, const fd_options *o, double *X, double *D, double *T,
            void *ws, size_t ws_bytes, int32_t *status, void *stream);

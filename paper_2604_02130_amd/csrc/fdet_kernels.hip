@@ -166,7 +166,7 @@ __device__ void slice_apply(const Prob& P, CMat in, CMat out, SmemC<NC>& S) {
       }, S);
 }
 
-// After wg_qrp on W with keys: D_new (S.v2) = |R_ii| keys_i and the row scale
+// After the pivoted QR of W with keys: D_new (S.v2) = |R_ii| keys_i and the row scale
 // S.v3 = 1 / D_new used to build T' = D_new^{-1} R diag(keys) (unit-modulus
 // diagonal).  Returns nothing; flags a zero or non-finite scale in S.flag.
 template <int NC>

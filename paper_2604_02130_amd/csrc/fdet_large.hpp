@@ -269,11 +269,11 @@ __device__ __forceinline__ void lg_block_sums(double* v, int buf, SmemC<NC>& S) 
 
 // ---------------------------------------------------------------------------
 // lg_qrp: blocked Householder QR of the N x N matrix in W with the pivot
-// order (partial norm x key) refreshed at every panel (same
-// contract as rq_qrp / wg_qrp: R in the upper triangle of W in pivoted column
-// order, reflector tails below it, S.u0r/u0i, S.beta, S.piv, S.pinv, S.csp,
-// S.rdr/rdi, S.nref), plus the T factor of every panel in tst.  F is a free
-// complex N x N matrix.
+// order (partial norm x key) refreshed at every panel.  Output as rq_qrp's
+// (R in the upper triangle of W in pivoted column order, S.u0r/u0i, S.beta,
+// S.piv, S.pinv, S.csp, S.rdr/rdi, S.nref) but with the reflector tails
+// below the diagonal of W, plus the T factor of every panel in tst.  F is a
+// free complex N x N matrix.
 // ---------------------------------------------------------------------------
 template <int NC>
 __device__ void lg_qrp(CMat W, int N, const double* keys, CMat F, double* tst, SmemC<NC>& S) {

@@ -12,8 +12,7 @@
 // device-memory round trip.
 //
 // After rq_qrp the factor is also written back to W in pivoted order:
-// column j holds R(0..j, j) and the tail of reflector j below the diagonal,
-// the same contract as the in-memory routine of fdet_device.hpp.
+// column j holds R(0..j, j); the reflectors stay in the LDS triangle.
 #pragma once
 
 #include "fdet_device.hpp"
@@ -94,28 +93,6 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane((int)b, lane);
   const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// best of the four lane groups of a wave: (key desc, column asc)
-__device__ __forceinline__ void wave_best4(double& k, double& n, int& c) {
-  double bk = readlane_d(k, 0), bn = readlane_d(n, 0);
-  int bc = __builtin_amdgcn_readlane(c, 0);
-#pragma unroll
-  for (int g = 1; g < 4; ++g) {
-    const double ok = readlane_d(k, 16 * g), on = readlane_d(n, 16 * g);
-    const int oc = __builtin_amdgcn_readlane(c, 16 * g);
-    if (ok > bk || (ok == bk && oc < bc)) { bk = ok; bn = on; bc = oc; }
-  }
-  k = bk; n = bn; c = bc;
-}
-
-// element m of a register array for a runtime m
-template <int R>
-__device__ __forceinline__ double pick(const double* a, int m) {
-  double v = 0.0;
-#pragma unroll
-  for (int k = 0; k < R; ++k) v = (k == m) ? a[k] : v;
-  return v;
 }
 
 // compile-time loop: f(IC<B>{}), f(IC<B+1>{}), ..., f(IC<E-1>{})
@@ -242,11 +219,12 @@ __device__ __forceinline__ void rq_repivot(CMat W, int N,
 // once at the start is not enough: for (near-)degenerate scales the T
 // factors of the UDV products then grow from product to product.
 //
-// Same contract as wg_qrp (R in the upper triangle of W in pivoted column
-// order, S.u0r/u0i, S.beta, S.piv, S.csp, S.nref) plus S.pinv[c] = position
-// of physical column c, S.rdr/rdi = diagonal of R and reflector j in the LDS
-// triangle (rows >= j, row j holding u0).  Below the diagonal W holds no
-// reflector data on this path; consumers read the triangle.
+// Output: R in the upper triangle of W in pivoted column order, S.u0r/u0i
+// and S.beta of every reflector, S.piv (original column at each position),
+// S.csp (key at each position), S.nref (reflectors formed), S.rdr/rdi
+// (diagonal of R) and reflector j in the LDS triangle (rows >= j, row j
+// holding u0).  Below the diagonal W holds no reflector data on this path;
+// consumers read the triangle.
 //
 // The columns enter the registers already in pivot order: slot q of group g
 // holds position k = g + 32 q.  Step j runs in row phase JB = j / 16, where
