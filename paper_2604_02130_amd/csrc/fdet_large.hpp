@@ -30,13 +30,17 @@ constexpr int LG_TDBL = 2 * LG_PW * LG_PW;       // doubles per stored T (re, im
 __host__ __device__ constexpr int lg_tstore_doubles(int Np) { return (Np / LG_PW) * LG_TDBL; }
 
 // ---------------------------------------------------------------------------
-// C (M x Nc) = A (M x K) B (K x Nc), macro tiles TM x TN, K panels of 16
-// staged in LDS with a register prefetch of the next panel.  Loaders are only
-// called inside the logical sizes (la(i, k) with i < M, k < K, lb(k, j) with
-// k < K, j < Nc); st(i, j, ..) only for i < M, j < Nc.
+// C (M x Nc) = C0 + A (M x K) B (K x Nc), macro tiles TM x TN, K panels of 16
+// staged in LDS.  One flat loop runs over (macro tile, K panel) steps and
+// prefetches the next step's operands into registers while the current one
+// multiplies, so a new macro tile's loads overlap the previous tile's
+// products and stores.  Loaders are only called inside the logical sizes
+// (la(i, k) with i < M, k < K; lb(k, j) with k < K, j < Nc); st(i, j, ..) only
+// for i < M, j < Nc.  With INIT, in(i, j, ..) gives C0 (loaded into the
+// accumulators when a macro tile starts), else C0 = 0.
 // ---------------------------------------------------------------------------
-template <int TM, int TN, bool AC, bool BC, class LA, class LB, class ST>
-__device__ void lg_gemm(int M, int Nc, int K, LA la, LB lb, ST st, double* lds) {
+template <int TM, int TN, bool AC, bool BC, bool INIT, class LA, class LB, class ST, class IN>
+__device__ void lg_gemm_impl(int M, int Nc, int K, LA la, LB lb, ST st, IN in, double* lds) {
   constexpr bool CC = AC || BC;
   constexpr int KP = 16;
   constexpr int SA = panel_stride(TM), SB = panel_stride(TN);
@@ -52,110 +56,159 @@ __device__ void lg_gemm(int M, int Nc, int K, LA la, LB lb, ST st, double* lds) 
   double* Br = Ar + (AC ? 2 : 1) * KP * SA;
   double* Bi = Br + KP * SB;
   const int mtm = (M + TM - 1) / TM, mtn = (Nc + TN - 1) / TN;
+  const int npan = (K + KP - 1) / KP;
+  const int nsteps = mtm * mtn * npan;
 
   double fa_r[PA], fa_i[PA], fb_r[PB], fb_i[PB];
-  for (int mt = 0; mt < mtm * mtn; ++mt) {
+  auto fetch = [&](int step) {
+    const int mt = step / npan, k0 = (step % npan) * KP;
     const int bm = (mt % mtm) * TM, bn = (mt / mtm) * TN;
-    auto fetch = [&](int k0) {
 #pragma unroll
-      for (int x = 0; x < PA; ++x) {
-        const int e = tid + WG * x;
-        fa_r[x] = 0.0; fa_i[x] = 0.0;
-        const int i = e % TM, kk = e / TM;          // A: rows fastest
-        if (e < EA && bm + i < M && k0 + kk < K) {
-          if constexpr (AC) la(bm + i, k0 + kk, fa_r[x], fa_i[x]);
-          else fa_r[x] = la(bm + i, k0 + kk);
-        }
+    for (int x = 0; x < PA; ++x) {
+      const int e = tid + WG * x;
+      fa_r[x] = 0.0; fa_i[x] = 0.0;
+      const int i = e % TM, kk = e / TM;          // A: rows fastest
+      if (e < EA && bm + i < M && k0 + kk < K) {
+        if constexpr (AC) la(bm + i, k0 + kk, fa_r[x], fa_i[x]);
+        else fa_r[x] = la(bm + i, k0 + kk);
       }
-#pragma unroll
-      for (int x = 0; x < PB; ++x) {
-        const int e = tid + WG * x;
-        fb_r[x] = 0.0; fb_i[x] = 0.0;
-        const int kb = e % KP, j = e / KP;          // B: k fastest
-        if (e < EB && k0 + kb < K && bn + j < Nc) {
-          if constexpr (BC) lb(k0 + kb, bn + j, fb_r[x], fb_i[x]);
-          else fb_r[x] = lb(k0 + kb, bn + j);
-        }
-      }
-    };
-    auto stash = [&]() {
-#pragma unroll
-      for (int x = 0; x < PA; ++x) {
-        const int e = tid + WG * x;
-        if (e < EA) {
-          const int i = e % TM, kk = e / TM;
-          Ar[kk * SA + i] = fa_r[x];
-          if constexpr (AC) Ai[kk * SA + i] = fa_i[x];
-        }
-      }
-#pragma unroll
-      for (int x = 0; x < PB; ++x) {
-        const int e = tid + WG * x;
-        if (e < EB) {
-          const int kb = e % KP, j = e / KP;
-          Br[kb * SB + j] = fb_r[x];
-          if constexpr (BC) Bi[kb * SB + j] = fb_i[x];
-        }
-      }
-    };
-    v4d cr[TPW], ci[TPW];
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      cr[t] = v4d{0.0, 0.0, 0.0, 0.0};
-      ci[t] = v4d{0.0, 0.0, 0.0, 0.0};
     }
-    fetch(0);
-    for (int k0 = 0; k0 < K; k0 += KP) {
-      __syncthreads();
-      stash();
-      __syncthreads();
-      if (k0 + KP < K) fetch(k0 + KP);
 #pragma unroll
-      for (int sk = 0; sk < KP / 4; ++sk) {
-        const int kk = 4 * sk + lk;
+    for (int x = 0; x < PB; ++x) {
+      const int e = tid + WG * x;
+      fb_r[x] = 0.0; fb_i[x] = 0.0;
+      const int kb = e % KP, j = e / KP;          // B: k fastest
+      if (e < EB && k0 + kb < K && bn + j < Nc) {
+        if constexpr (BC) lb(k0 + kb, bn + j, fb_r[x], fb_i[x]);
+        else fb_r[x] = lb(k0 + kb, bn + j);
+      }
+    }
+  };
+  auto stash = [&]() {
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) {
+    for (int x = 0; x < PA; ++x) {
+      const int e = tid + WG * x;
+      if (e < EA) {
+        const int i = e % TM, kk = e / TM;
+        Ar[kk * SA + i] = fa_r[x];
+        if constexpr (AC) Ai[kk * SA + i] = fa_i[x];
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < PB; ++x) {
+      const int e = tid + WG * x;
+      if (e < EB) {
+        const int kb = e % KP, j = e / KP;
+        Br[kb * SB + j] = fb_r[x];
+        if constexpr (BC) Bi[kb * SB + j] = fb_i[x];
+      }
+    }
+  };
+  v4d cr[TPW], ci[TPW];
+  if (nsteps > 0) fetch(0);
+  for (int step = 0; step < nsteps; ++step) {
+    const int mt = step / npan, kp = step % npan;
+    const int bm = (mt % mtm) * TM, bn = (mt / mtm) * TN;
+    if (kp == 0) {
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        cr[t] = v4d{0.0, 0.0, 0.0, 0.0};
+        ci[t] = v4d{0.0, 0.0, 0.0, 0.0};
+        if constexpr (INIT) {
           const int tile = wave + NWAVE * t;
-          if (tile >= NT) break;
-          const int i = ((tile % TMT) << 4) + li, j = ((tile / TMT) << 4) + li;
-          const double a_r = Ar[kk * SA + i];
-          const double b_r = Br[kk * SB + j];
-          if constexpr (AC && BC) {
-            const double a_i = Ai[kk * SA + i], b_i = Bi[kk * SB + j];
-            cr[t] = mfma4(a_r, b_r, cr[t]);
-            ci[t] = mfma4(a_r, b_i, ci[t]);
-            cr[t] = mfma4(-a_i, b_i, cr[t]);
-            ci[t] = mfma4(a_i, b_r, ci[t]);
-          } else if constexpr (AC) {
-            const double a_i = Ai[kk * SA + i];
-            cr[t] = mfma4(a_r, b_r, cr[t]);
-            ci[t] = mfma4(a_i, b_r, ci[t]);
-          } else if constexpr (BC) {
-            const double b_i = Bi[kk * SB + j];
-            cr[t] = mfma4(a_r, b_r, cr[t]);
-            ci[t] = mfma4(a_r, b_i, ci[t]);
-          } else {
-            cr[t] = mfma4(a_r, b_r, cr[t]);
+          if (tile < NT) {
+            const int r0 = ((tile % TMT) << 4) + lk, c0 = ((tile / TMT) << 4) + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int gi = bm + r0 + 4 * r, gj = bn + c0;
+              if (gi < M && gj < Nc) {
+                double vr = 0.0, vi = 0.0;
+                if constexpr (CC) in(gi, gj, vr, vi);
+                else in(gi, gj, vr);
+                cr[t][r] = vr;
+                ci[t][r] = vi;
+              }
+            }
           }
         }
       }
     }
+    __syncthreads();
+    stash();
+    __syncthreads();
+    if (step + 1 < nsteps) fetch(step + 1);
+    // two k-steps at a time: fully unrolled, the hoisted LDS operands spill
+#pragma unroll 2
+    for (int sk = 0; sk < KP / 4; ++sk) {
+      const int kk = 4 * sk + lk;
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int tile = wave + NWAVE * t;
-      if (tile >= NT) break;
-      const int r0 = ((tile % TMT) << 4) + lk, c0 = ((tile / TMT) << 4) + li;
+      for (int t = 0; t < TPW; ++t) {
+        const int tile = wave + NWAVE * t;
+        if (tile >= NT) break;
+        const int i = ((tile % TMT) << 4) + li, j = ((tile / TMT) << 4) + li;
+        const double a_r = Ar[kk * SA + i];
+        const double b_r = Br[kk * SB + j];
+        if constexpr (AC && BC) {
+          const double a_i = Ai[kk * SA + i], b_i = Bi[kk * SB + j];
+          cr[t] = mfma4(a_r, b_r, cr[t]);
+          ci[t] = mfma4(a_r, b_i, ci[t]);
+          cr[t] = mfma4(-a_i, b_i, cr[t]);
+          ci[t] = mfma4(a_i, b_r, ci[t]);
+        } else if constexpr (AC) {
+          const double a_i = Ai[kk * SA + i];
+          cr[t] = mfma4(a_r, b_r, cr[t]);
+          ci[t] = mfma4(a_i, b_r, ci[t]);
+        } else if constexpr (BC) {
+          const double b_i = Bi[kk * SB + j];
+          cr[t] = mfma4(a_r, b_r, cr[t]);
+          ci[t] = mfma4(a_r, b_i, ci[t]);
+        } else {
+          cr[t] = mfma4(a_r, b_r, cr[t]);
+        }
+      }
+    }
+    if (kp == npan - 1) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gi = bm + r0 + 4 * r, gj = bn + c0;
-        if (gi < M && gj < Nc) {
-          if constexpr (CC) st(gi, gj, cr[t][r], ci[t][r]);
-          else st(gi, gj, cr[t][r]);
+      for (int t = 0; t < TPW; ++t) {
+        const int tile = wave + NWAVE * t;
+        if (tile >= NT) break;
+        const int r0 = ((tile % TMT) << 4) + lk, c0 = ((tile / TMT) << 4) + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gi = bm + r0 + 4 * r, gj = bn + c0;
+          if (gi < M && gj < Nc) {
+            if constexpr (CC) st(gi, gj, cr[t][r], ci[t][r]);
+            else st(gi, gj, cr[t][r]);
+          }
         }
       }
     }
   }
   __syncthreads();
+}
+
+struct LgNoInit {
+  __device__ void operator()(int, int, double&, double&) const {}
+  __device__ void operator()(int, int, double&) const {}
+};
+
+template <int TM, int TN, bool AC, bool BC, class LA, class LB, class ST>
+__device__ __forceinline__ void lg_gemm(int M, int Nc, int K, LA la, LB lb, ST st, double* lds) {
+  lg_gemm_impl<TM, TN, AC, BC, false>(M, Nc, K, la, lb, st, LgNoInit{}, lds);
+}
+
+// C -= A B in place: the accumulators start from -C and the store negates.
+template <int TM, int TN, bool AC, bool BC, class LA, class LB, class LC, class SC>
+__device__ __forceinline__ void lg_gemm_sub(int M, int Nc, int K, LA la, LB lb, LC lc, SC sc,
+                                            double* lds) {
+  lg_gemm_impl<TM, TN, AC, BC, true>(
+      M, Nc, K, la, lb,
+      [&](int i, int j, double cr, double ci) { sc(i, j, -cr, -ci); },
+      [&](int i, int j, double& cr, double& ci) {
+        lc(i, j, cr, ci);
+        cr = -cr;
+        ci = -ci;
+      }, lds);
 }
 
 // Reflector matrix V of the panel at j0 (pw columns): V(r, c) for rows r of
@@ -185,7 +238,7 @@ __device__ void lg_apply_panel(const LgPanel& pn, const double* tp, CMat Y, int 
   auto ycol = [&](int j) { return ymap ? ymap[ycol0 + j] : ycol0 + j; };
   const int j0 = pn.j0, pw = pn.pw;
   // F(0:pw, 0:Nc) = V^H Y
-  lg_gemm<16, 128, true, true>(
+  lg_gemm<16, 256, true, true>(
       pw, Nc, M,
       [&](int i, int k, double& ar, double& ai) {
         double vr, vi;
@@ -229,14 +282,19 @@ __device__ void lg_apply_panel(const LgPanel& pn, const double* tp, CMat Y, int 
   }
   __syncthreads();
   // Y -= V F
-  lg_gemm<128, 128, true, true>(
+  lg_gemm_sub<128, 128, true, true>(
       M, Nc, pw,
       [&](int i, int k, double& ar, double& ai) { pn.v(j0 + i, k, ar, ai); },
       [&](int k, int j, double& br, double& bi) { br = F.r(k, j); bi = F.m(k, j); },
+      [&](int i, int j, double& cr, double& ci) {
+        const int c = ycol(j);
+        cr = Y.r(j0 + i, c);
+        ci = Y.m(j0 + i, c);
+      },
       [&](int i, int j, double cr, double ci) {
         const int c = ycol(j);
-        Y.r(j0 + i, c) -= cr;
-        Y.m(j0 + i, c) -= ci;
+        Y.r(j0 + i, c) = cr;
+        Y.m(j0 + i, c) = ci;
       }, S.big);
 }
 
@@ -581,14 +639,12 @@ __device__ void lg_backsolve(CMat W, int N, CMat Y, SmemC<NC>& S) {
     }
     __syncthreads();
     if (i0 > 0) {
-      lg_gemm<128, 128, true, true>(
+      lg_gemm_sub<128, 128, true, true>(
           i0, N, bw,
           [&](int i, int k, double& ar, double& ai) { ar = W.r(i, i0 + k); ai = W.m(i, i0 + k); },
           [&](int k, int j, double& br, double& bi) { br = Y.r(i0 + k, j); bi = Y.m(i0 + k, j); },
-          [&](int i, int j, double cr, double ci) {
-            Y.r(i, j) -= cr;
-            Y.m(i, j) -= ci;
-          }, S.big);
+          [&](int i, int j, double& cr, double& ci) { cr = Y.r(i, j); ci = Y.m(i, j); },
+          [&](int i, int j, double cr, double ci) { Y.r(i, j) = cr; Y.m(i, j) = ci; }, S.big);
     }
   }
 }
