@@ -7,9 +7,14 @@ QR every s = 8 slices).  One step = one complete evaluation: slice
 exponential, stabilised slice chain, time-segment combines, close, log det and
 G, all on inputs already resident in HBM.
 
+The timed region replays a graph captured from a prepared call (the same
+launches as an eager call, exponential included, without the per-call
+descriptor upload); --no-graph times eager calls instead.
+
 Printed as one JSON line, with
-  roofline      the dominant kernel's model FLOP/s (HIP events around every
-                kernel phase inside the timed region) against FP64 MFMA peak,
+  roofline      the dominant kernel's algorithmic FLOP/s against FP64 MFMA peak,
+                its launch time from HIP events around every kernel phase on
+                the launch stream, in a pass of as many eager evaluations,
   cpu_baseline  the CPU oracle timed on a bounded sample on the host cores,
   force         HMC force evals/s (L = 8, N = 128, N_t = 256): checkpointed
                 adjoint (c = 16) against the plain per-slice inversion (c = 1),
@@ -115,6 +120,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the force, batched and HMC legs")
     ap.add_argument("--no-hmc", action="store_true", help="skip the 32-field L=16 HMC step")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager calls instead of the captured evaluation")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -172,18 +179,49 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.no_graph:
+        timed = step
+    else:
+        # the same launches (exponential, chain, combine levels, close) captured
+        # once from a prepared call and replayed: no descriptor upload and no
+        # host launch path per evaluation
+        plan = fd.Plan("greens", [(Kd, pd, w.dk)], s=s, segments=nseg)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plan.launch()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.launch()
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        timed = graph.replay
     print(f"[bench] warmup done; timing {args.steps} steps", file=sys.stderr, flush=True)
-    fd.profile_start()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        timed()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    if not args.no_graph:
+        st_g = int(plan.status.item())
+        if st_g < 0:
+            raise SystemExit(f"status {st_g}: {fd.strerror(st_g)}")
+        ld_g = torch.view_as_complex(plan.ld)[0]
+    # per-phase launch times (HIP events around every phase) from eager calls
+    fd.profile_start()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
     phases = fd.profile_stop()
     st = int(status.item())
     if st < 0:
         raise SystemExit(f"status {st}: {fd.strerror(st)}")
+    if not args.no_graph and not torch.equal(ld_g, torch.view_as_complex(ld)):
+        raise SystemExit("graph replay and eager call disagree")
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     evals_per_s = args.steps / (t1 - t0)
 
@@ -241,6 +279,7 @@ def main():
                         "phi~N(0, delta*U) seed 2, s=8; log det M and G per step",
             "segments": nseg,
             "segments_autotuned": tuned is not None,
+            "timed": "eager calls" if args.no_graph else "graph replay of the prepared call",
             "parallelism": "single GPU",
         },
         "fp64_mfma_pct_peak": 100.0 * alg_flops / (ms_per_step * 1e-3) / PEAK_FP64_MFMA,
