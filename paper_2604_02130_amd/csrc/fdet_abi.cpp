@@ -317,13 +317,31 @@ ScanPlan scan_schedule(int n, int g, bool later_left) {
   return sp;
 }
 
-// Group size of the checkpoint scans: plain Hillis-Steele while the scans of
-// the whole plan leave the compute units idle, groups of 4 once two rounds
-// of work items fill them.
+// Group size of the checkpoint scans: the candidate (1, 2, 4, 8, 16) whose
+// levels take the fewest rounds of one workgroup per compute unit over the
+// whole plan (both scan directions of every problem), the smallest on ties.
+// A lone problem gets the log-depth scan; a batch that fills the GPU many
+// times over gets larger groups and about 2n products per scan.
 int scan_group(const fd_problem* p, int nprob, const Opts& o) {
-  long long items = 0;
-  for (int i = 0; i < nprob; ++i) items += 2LL * ((p[i].Nt + o.c - 1) / o.c);
-  return items >= 2LL * device_cu_count() ? 4 : 1;
+  const int ncu = device_cu_count();
+  int best_g = 1;
+  long long best_rounds = -1;
+  for (int g : {1, 2, 4, 8, 16}) {
+    std::vector<long long> per_level;
+    for (int i = 0; i < nprob; ++i) {
+      const int nc = (p[i].Nt + o.c - 1) / o.c;
+      const ScanPlan sp = scan_schedule(nc, g, true);
+      if ((int)per_level.size() < sp.levels) per_level.resize(sp.levels, 0);
+      for (const ScanOp& op : sp.ops) per_level[op.level] += 2;   // both directions
+    }
+    long long rounds = 0;
+    for (long long n : per_level) rounds += (n + ncu - 1) / ncu;
+    if (best_rounds < 0 || rounds < best_rounds) {
+      best_rounds = rounds;
+      best_g = g;
+    }
+  }
+  return best_g;
 }
 
 // Build the layout and the work items.  `what` = FD_WHAT_*.

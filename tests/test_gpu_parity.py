@@ -375,10 +375,11 @@ def test_hmc_step_L16_sampled(fd):
     assert np.abs(F.imag - 0.5).max() < 1e-9
 
 
-@pytest.mark.parametrize("Nt,c", [(300, 1), (301, 1)])
+@pytest.mark.parametrize("Nt,c", [(300, 1), (301, 1), (256, 1)])
 def test_force_grouped_scan(fd, Nt, c):
     """Enough checkpoint intervals that the prefix / suffix scans run in
-    groups (sequential in a group, log-depth over the group totals)."""
+    groups (sequential in a group, log-depth over the group totals): groups
+    of 4 for 300 and 301 intervals, 2 for 256, on a 256-CU device."""
     K = honeycomb_hopping(2)
     dk = 0.1
     phi = sample_phi(900 + Nt, Nt, 8, dk, 3.0)
@@ -387,3 +388,55 @@ def test_force_grouped_scan(fd, Nt, c):
     assert np.abs(F.cpu().numpy() - Fo).max() <= TOL_F
     lo, _ = O.stabilised_logdet_greens(K, dk, phi)
     check_ld(complex(ld.item()), lo)
+
+
+def test_udv_large_class(fd):
+    """The stabilised factorisation from the blocked path (N = 162)."""
+    L, Nt, beta = 9, 16, 2.0
+    K = honeycomb_hopping(L)
+    N = K.shape[0]
+    dk = beta / Nt
+    phi = sample_phi(41, Nt, N, dk, 3.0)
+    X, D, T = fd.udv(to_dev(K), to_dev(phi), dk, s=4)
+    X, D, T = X.cpu().numpy(), D.cpu().numpy(), T.cpu().numpy()
+    assert np.abs(X.conj().T @ X - np.eye(N)).max() < 1e-12
+    assert abs(abs(np.linalg.det(T)) - 1.0) < 1e-9
+    B = O.slice_matrices(K, dk, phi)
+    P = np.eye(N, dtype=complex)
+    for b in B:
+        P = b @ P
+    assert np.abs(X @ np.diag(D) @ T - P).max() <= 1e-12 * np.abs(P).max()
+
+
+def test_batched_mixed_small_and_large(fd):
+    """One batch whose largest problem selects the blocked class: the small
+    problems then run through the blocked path as well."""
+    specs = [(2, 24, 0.125), (9, 16, 0.125), (3, 20, 0.125)]
+    probs, refs, frefs = [], [], []
+    for i, (L, Nt, dk) in enumerate(specs):
+        K = honeycomb_hopping(L)
+        phi = sample_phi(600 + i, Nt, K.shape[0], dk, 3.0)
+        probs.append((to_dev(K), to_dev(phi), dk))
+        refs.append(O.stabilised_logdet_greens(K, dk, phi))
+        frefs.append(O.stabilised_force(K, dk, phi))
+    ld, Gs = fd.greens_batched(probs, s=4, segments=2)
+    ld = ld.cpu().numpy()
+    for i, (lo, Go) in enumerate(refs):
+        check_ld(ld[i], lo)
+        check_G(Gs[i].cpu().numpy(), Go)
+    Fs, _ = fd.force_batched(probs, s=4, checkpoint=8)
+    for F, Fo in zip(Fs, frefs):
+        assert np.abs(F.cpu().numpy() - Fo).max() <= TOL_F
+
+
+def test_force_batched_grouped_by_8(fd):
+    """Six problems of 100 one-slice intervals: the scans run in groups of 8."""
+    probs, refs = [], []
+    K = honeycomb_hopping(2)
+    for i in range(6):
+        phi = sample_phi(1300 + i, 100, 8, 0.1, 3.0)
+        probs.append((to_dev(K), to_dev(phi), 0.1))
+        refs.append(O.stabilised_force(K, 0.1, phi))
+    Fs, _ = fd.force_batched(probs, s=4, checkpoint=1)
+    for F, Fo in zip(Fs, refs):
+        assert np.abs(F.cpu().numpy() - Fo).max() <= TOL_F
