@@ -85,6 +85,17 @@ def alg_force_flops(N, Nt, s, c):
     return alg_det_flops(N, Nt, s) + N ** 3 * Nt * (12.0 + (16 / 3 + 16 / 3 + 4.0) / s + 64.0 / c)
 
 
+def phase_split(call):
+    """Launch times of one eager call by phase: [(phase, work items, ms)],
+    from HIP events around every launch on the launch stream."""
+    import torch
+    import paper_2604_02130_amd as fd
+    fd.profile_start()
+    call()
+    torch.cuda.synchronize()
+    return [(name, n, round(ms, 4)) for name, n, ms in fd.profile_stop()]
+
+
 def src_digest():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2604_02130_amd", "csrc")
@@ -328,7 +339,9 @@ def main():
             torch.cuda.synchronize()
             dt = (time.perf_counter() - a) / reps
             out[label] = {"force_evals_per_s": 1.0 / dt, "ms": dt * 1e3,
-                          "alg_tflop_s": alg_force_flops(wf.N, wf.Nt, wf.s, 16) / dt / 1e12}
+                          "alg_tflop_s": alg_force_flops(wf.N, wf.Nt, wf.s, 16) / dt / 1e12,
+                          "phases_ms": phase_split(lambda: fd.force(
+                              Kf, pf, wf.dk, s=wf.s, checkpoint=c, check=False, ws=wsf))}
             print(f"[bench] force {label}: {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
         out["workload"] = "force_L8: honeycomb L=8 (N=128), Nt=256, beta=32, U=3, s=8"
         out["adjoint_vs_plain"] = out["adjoint_c16"]["force_evals_per_s"] / out["plain_c1"]["force_evals_per_s"]
@@ -358,6 +371,8 @@ def main():
         torch.cuda.synchronize()
         dtp = time.perf_counter() - a
         bflops = sum(alg_det_flops(wb.N, wb.Nt, 8) for wb in mix)
+        bphases = phase_split(lambda: fd.greens_batched(probs, s=8, segments=seg_b, check=False,
+                                                        ws=wsb))
         result["batched"] = {
             "workload": "256 configs, L in {3,5,6,7,8}, Nt in {32..512}, delta=0.125, U=3, s=8",
             "batched_evals_per_s": len(mix) / dtb,
@@ -365,6 +380,7 @@ def main():
             "batched_vs_plain": dtp / dtb,
             "batched_ms": dtb * 1e3,
             "fp64_mfma_pct_peak": 100.0 * bflops / dtb / PEAK_FP64_MFMA,
+            "phases_ms": bphases,
         }
         print(f"[bench] batched {dtb * 1e3:.1f} ms vs plain {dtp * 1e3:.1f} ms",
               file=sys.stderr, flush=True)

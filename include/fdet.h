@@ -64,6 +64,9 @@ enum { FD_WHAT_LOGDET = 0, FD_WHAT_GREENS = 1, FD_WHAT_FORCE = 2, FD_WHAT_UDV = 
 /* option flags */
 #define FD_REUSE_E 0x1   /* exp(+-dk K) already in this workspace from an earlier
                             call on the same problems: skip recomputing it     */
+#define FD_FORCE_SCANS 0x2 /* force: build the checkpoint products by prefix /
+                            suffix scans even where cyclic windows would take
+                            fewer rounds (fd_force)                           */
 
 typedef struct {
   int32_t N;            /* sites V, 1 <= N <= FD_MAX_N                        */
@@ -87,7 +90,7 @@ typedef struct {
                            batch, per problem in proportion to its chain work
                            max(N,32)^2 Nt, so that the batch's chains fill the
                            compute units about once (at most min(32, Nt/4))  */
-  int32_t flags;        /* FD_REUSE_E                                          */
+  int32_t flags;        /* FD_REUSE_E | FD_FORCE_SCANS                         */
 } fd_options;
 
 /* Bytes of workspace needed for `nprob` problems and the given entry point
@@ -116,9 +119,14 @@ int fd_greens(const fd_problem *p, const fd_options *o, double *logdet, double *
  * exact).  The G~_t come from UDV checkpoints every c slices of the prefix and
  * suffix products (Sec. 5, stabilised dense pre- and suffix) and are carried
  * between checkpoints by G~_{t+1} = B_t G~_t B_t^{-1}.  The checkpoint
- * intervals are multiplied out in parallel and the prefix and suffix UDVs at
- * every checkpoint follow from log2(ceil(N_t/c)) rounds of stabilised
- * products (eq. prod_2_mat_stab is associative up to rounding).
+ * intervals (nc = ceil(N_t/c)) are multiplied out in parallel; the two
+ * factors of each checkpoint's cyclic product then follow from rounds of
+ * stabilised products (eq. prod_2_mat_stab is associative up to rounding):
+ * either cyclic windows of P and nc - P consecutive intervals (P the smallest
+ * power of two with 2P >= nc; log2(P) rounds of nc products) or prefix and
+ * suffix scans (grouped, about 2 nc products per direction), whichever takes
+ * fewer rounds of one workgroup per compute unit for the whole call
+ * (FD_FORCE_SCANS: scans).  Checkpoint 0 gives log det M and G.
  * force: device, Nt*N doubles, Re F (row t-1 = slice t).
  * force_im: NULL or Nt*N doubles, Im F.  logdet: NULL or 2 doubles.          */
 int fd_force(const fd_problem *p, const fd_options *o, double *logdet, double *force,

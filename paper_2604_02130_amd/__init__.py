@@ -28,6 +28,7 @@ FD_ERR_UNSUPPORTED = -6
 
 FD_WHAT_LOGDET, FD_WHAT_GREENS, FD_WHAT_FORCE, FD_WHAT_UDV = 0, 1, 2, 3
 FD_REUSE_E = 0x1
+FD_FORCE_SCANS = 0x2
 MAX_N = 512
 
 # exported names (each declared in include/fdet.h)
@@ -237,7 +238,7 @@ def logdet(K, phi, dk, s=0, segments=0, flags=0, check=True, ws: Workspace | Non
     o = _opts(s=s, segments=segments, flags=flags)
     out = torch.empty(2, dtype=torch.float64, device=K.device)
     status = torch.empty(1, dtype=torch.int32, device=K.device)
-    need = workspace_bytes([p], FD_WHAT_LOGDET, s=s, segments=segments)
+    need = workspace_bytes([p], FD_WHAT_LOGDET, s=s, segments=segments, flags=flags)
     wsp, wsn = (ws or _default_ws).get(need, K.device)
     _check(lib.fd_logdet(ctypes.byref(p), ctypes.byref(o), out.data_ptr(), wsp, wsn,
                          status.data_ptr(), _stream()))
@@ -257,7 +258,7 @@ def greens(K, phi, dk, s=0, segments=0, flags=0, check=True, ws: Workspace | Non
     G = torch.empty((N, N, 2), dtype=torch.float64, device=K.device) if out is None else out[1]
     if status is None:
         status = torch.empty(1, dtype=torch.int32, device=K.device)
-    need = workspace_bytes([p], FD_WHAT_GREENS, s=s, segments=segments)
+    need = workspace_bytes([p], FD_WHAT_GREENS, s=s, segments=segments, flags=flags)
     wsp, wsn = (ws or _default_ws).get(need, K.device)
     _check(lib.fd_greens(ctypes.byref(p), ctypes.byref(o), ld.data_ptr(), G.data_ptr(), wsp, wsn,
                          status.data_ptr(), _stream()))
@@ -276,7 +277,7 @@ def force(K, phi, dk, s=0, checkpoint=0, flags=0, check=True, ws: Workspace | No
     Fi = torch.empty((p.Nt, p.N), dtype=torch.float64, device=K.device)
     ld = torch.empty(2, dtype=torch.float64, device=K.device)
     status = torch.empty(1, dtype=torch.int32, device=K.device)
-    need = workspace_bytes([p], FD_WHAT_FORCE, s=s, checkpoint=checkpoint)
+    need = workspace_bytes([p], FD_WHAT_FORCE, s=s, checkpoint=checkpoint, flags=flags)
     wsp, wsn = (ws or _default_ws).get(need, K.device)
     _check(lib.fd_force(ctypes.byref(p), ctypes.byref(o), ld.data_ptr(), Fr.data_ptr(),
                         Fi.data_ptr(), wsp, wsn, status.data_ptr(), _stream()))
@@ -324,12 +325,12 @@ def greens_batched(problems, s=0, segments=0, flags=0, check=True, ws: Workspace
     if want_g:
         total = sum(2 * p.N * p.N for p in probs)
         G = torch.empty(total, dtype=torch.float64, device=dev)
-        need = workspace_bytes(probs, FD_WHAT_GREENS, s=s, segments=segments)
+        need = workspace_bytes(probs, FD_WHAT_GREENS, s=s, segments=segments, flags=flags)
         wsp, wsn = (ws or _default_ws).get(need, dev)
         _check(lib.fd_greens_batched(arr, n, ctypes.byref(o), ld.data_ptr(), G.data_ptr(), wsp,
                                      wsn, status.data_ptr(), _stream()))
     else:
-        need = workspace_bytes(probs, FD_WHAT_LOGDET, s=s, segments=segments)
+        need = workspace_bytes(probs, FD_WHAT_LOGDET, s=s, segments=segments, flags=flags)
         wsp, wsn = (ws or _default_ws).get(need, dev)
         _check(lib.fd_logdet_batched(arr, n, ctypes.byref(o), ld.data_ptr(), wsp, wsn,
                                      status.data_ptr(), _stream()))
@@ -358,7 +359,7 @@ def force_batched(problems, s=0, checkpoint=0, flags=0, check=True, ws: Workspac
     Fi = torch.empty(total, dtype=torch.float64, device=dev)
     ld = torch.empty((n, 2), dtype=torch.float64, device=dev)
     status = torch.empty(n, dtype=torch.int32, device=dev)
-    need = workspace_bytes(probs, FD_WHAT_FORCE, s=s, checkpoint=checkpoint)
+    need = workspace_bytes(probs, FD_WHAT_FORCE, s=s, checkpoint=checkpoint, flags=flags)
     wsp, wsn = (ws or _default_ws).get(need, dev)
     _check(lib.fd_force_batched(arr, n, ctypes.byref(o), ld.data_ptr(), Fr.data_ptr(),
                                 Fi.data_ptr(), wsp, wsn, status.data_ptr(), _stream()))

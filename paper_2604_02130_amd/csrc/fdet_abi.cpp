@@ -317,15 +317,74 @@ ScanPlan scan_schedule(int n, int g, bool later_left) {
   return sp;
 }
 
-// Group size of the checkpoint scans: the candidate (1, 2, 4, 8, 16) whose
-// levels take the fewest rounds of one workgroup per compute unit over the
-// whole plan (both scan directions of every problem), the smallest on ties.
-// A lone problem gets the log-depth scan; a batch that fills the GPU many
-// times over gets larger groups and about 2n products per scan.
-int scan_group(const fd_problem* p, int nprob, const Opts& o) {
+// ---- cyclic windows of interval products for the force checkpoints
+//
+// W(i, len) = L_{i+len-1} ... L_i, indices mod nc.  The cyclic product that
+// checkpoint k needs, L_{k-1} ... L_0 L_{nc-1} ... L_k, splits into a left
+// window W(k - P, P) and a right window W(k, nc - P) for any P; with P the
+// smallest power of two such that 2 P >= nc, all nc left windows come from
+// log2(P) doubling levels W(i, 2p) = W(i + p, p) W(i, p), nc products each,
+// and the right windows (length nc - P <= P) are built from the same powers
+// within those levels: a window of length p + r (p a power of two, r < p)
+// is W(i + r, p) W(i, r).  Against the prefix / suffix scans this takes
+// log2(P) launches instead of about 2 log2(nc), which matters while a plan
+// leaves compute units idle.
+struct WinBuild {
+  int len, level, left, right;   // W(i, len) = W(i + right, left) W(i, right)
+};
+
+struct WinPlan {
+  int P = 1, w2 = 0, levels = 0;
+  std::vector<WinBuild> builds;   // in level order
+};
+
+WinPlan window_plan(int nc) {
+  WinPlan wp;
+  while (2 * wp.P < nc) wp.P *= 2;
+  wp.w2 = nc - wp.P;
+  std::vector<int> avail(nc + 1, -1);   // launches before W(., len) exists
+  avail[1] = 0;
+  for (int p = 2; p <= wp.P; p *= 2) {
+    wp.builds.push_back({p, avail[p / 2], p / 2, p / 2});
+    avail[p] = avail[p / 2] + 1;
+  }
+  // the right windows: lengths w2, then its remainders, built bottom-up
+  std::vector<int> chain;
+  for (int len = wp.w2; len > 1 && avail[len] < 0; len -= pow2_floor(len)) chain.push_back(len);
+  for (int c = (int)chain.size() - 1; c >= 0; --c) {
+    const int len = chain[c], p = pow2_floor(len), r = len - p;
+    const int lv = std::max(avail[p], avail[r]);
+    wp.builds.push_back({len, lv, p, r});
+    avail[len] = lv + 1;
+  }
+  for (const WinBuild& b : wp.builds) wp.levels = std::max(wp.levels, b.level + 1);
+  std::stable_sort(wp.builds.begin(), wp.builds.end(),
+                   [](const WinBuild& x, const WinBuild& y) { return x.level < y.level; });
+  return wp;
+}
+
+// Schedule of the checkpoint products: windows (g == 0) or scans with group
+// size g.  The candidate whose combine levels take the fewest rounds of one
+// workgroup per compute unit over the whole plan wins; on ties the windows,
+// then the smallest group.  A lone problem gets the windows; a batch that
+// fills the GPU many times over gets grouped scans (about 2 nc products per
+// direction instead of nc log2(nc) / 2 per window level).
+int force_schedule(const fd_problem* p, int nprob, const Opts& o) {
   const int ncu = device_cu_count();
-  int best_g = 1;
-  long long best_rounds = -1;
+  auto rounds_of = [&](const std::vector<long long>& per_level) {
+    long long r = 0;
+    for (long long n : per_level) r += (n + ncu - 1) / ncu;
+    return r;
+  };
+  std::vector<long long> win;
+  for (int i = 0; i < nprob; ++i) {
+    const int nc = (p[i].Nt + o.c - 1) / o.c;
+    const WinPlan wp = window_plan(nc);
+    if ((int)win.size() < wp.levels) win.resize(wp.levels, 0);
+    for (const WinBuild& b : wp.builds) win[b.level] += nc;
+  }
+  int best_g = 0;
+  long long best_rounds = (o.flags & FD_FORCE_SCANS) ? -1 : rounds_of(win);
   for (int g : {1, 2, 4, 8, 16}) {
     std::vector<long long> per_level;
     for (int i = 0; i < nprob; ++i) {
@@ -334,8 +393,7 @@ int scan_group(const fd_problem* p, int nprob, const Opts& o) {
       if ((int)per_level.size() < sp.levels) per_level.resize(sp.levels, 0);
       for (const ScanOp& op : sp.ops) per_level[op.level] += 2;   // both directions
     }
-    long long rounds = 0;
-    for (long long n : per_level) rounds += (n + ncu - 1) / ncu;
+    const long long rounds = rounds_of(per_level);
     if (best_rounds < 0 || rounds < best_rounds) {
       best_rounds = rounds;
       best_g = g;
@@ -352,19 +410,28 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   // count items to size the descriptor region
   const bool force = what == FD_WHAT_FORCE;
   std::vector<int> nseg = plan_segments(p, nprob, o), nck(nprob);
-  const int sgroup = force ? scan_group(p, nprob, o) : 1;
+  const int sgroup = force ? force_schedule(p, nprob, o) : 1;
   int maxlev = 0;
+  size_t nforce = 0;
   for (int i = 0; i < nprob; ++i) {
     pl.maxN = std::max(pl.maxN, p[i].N);
     if (force) {
       const int nc = (p[i].Nt + o.c - 1) / o.c;
       nck[i] = nc;
-      const ScanPlan sp = scan_schedule(nc, sgroup, true);
-      const size_t scan = 2 * sp.ops.size();
-      maxlev = std::max(maxlev, sp.levels);
-      // 2 exponentials, nc interval chains + the identity, the scans, the
-      // log-det close, nc force items
-      nitems += 2 + (size_t)nc + 1 + scan + 1 + nc;
+      size_t prods = 0;
+      if (sgroup == 0) {
+        const WinPlan wp = window_plan(nc);
+        prods = wp.builds.size() * (size_t)nc;
+        maxlev = std::max(maxlev, wp.levels);
+      } else {
+        const ScanPlan sp = scan_schedule(nc, sgroup, true);
+        prods = 2 * sp.ops.size();
+        maxlev = std::max(maxlev, sp.levels);
+      }
+      // 2 exponentials, nc interval chains + the identity, the checkpoint
+      // products, and 2 nc force items at most (forward / backward halves)
+      nitems += 2 + (size_t)nc + 1 + prods + 2 * (size_t)nc;
+      nforce += nc;
     } else {
       int lev = 0;
       while ((1 << lev) < nseg[i]) ++lev;
@@ -431,29 +498,17 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
       close.push_back(z);
     } else {
       // Checkpoint intervals [k c, (k+1) c): local products L_k in parallel,
-      // then two inclusive scans of stabilised products over them
-      // (log2(nc) levels each, Hillis-Steele, later factors on the left):
-      //   prefix  Q_k = L_k ... L_0,        suffix  S_k = L_{nc-1} ... L_k.
-      // Every scan entry lives in the interval buffer or one of two scan
-      // buffers (read one, write the other per level).  Checkpoint k uses
-      // Q_{k-1} (the identity for k = 0) and S_k, both in the X D T form
-      // with the unitary factor on the left.
+      // then the two factors of every checkpoint's cyclic product
+      // C_k = L_{k-1} ... L_0 L_{nc-1} ... L_k, both in the X D T form with
+      // the unitary factor on the left, from either
+      //   windows (sgroup == 0): C_k = W(k - P, P) W(k, nc - P), or
+      //   scans: the prefix Q_{k-1} = L_{k-1} ... L_0 (the identity for
+      //   k = 0) and the suffix S_k = L_{nc-1} ... L_k.
+      // C_0 is the whole product: checkpoint 0 also gives log det M and G.
       const int nc = nck[i];
       const size_t ub = udv_bytes(Np);
-      const ScanPlan spf = scan_schedule(nc, sgroup, true);
-      const ScanPlan spb = scan_schedule(nc, sgroup, false);
-      const int G = (nc + sgroup - 1) / sgroup;
-      // slots of the two scans (see scan_schedule); inputs are shared
-      std::vector<Udv> base(nc), slf(2 * nc + 2 * G), slb(2 * nc + 2 * G);
+      std::vector<Udv> base(nc);
       for (int k = 0; k < nc; ++k) base[k] = make_udv(cur.take(ub), Np);
-      for (int dir = 0; dir < 2; ++dir) {
-        std::vector<Udv>& sl = dir == 0 ? slf : slb;
-        // prefix sequence index i is interval i; suffix index i is nc-1-i
-        for (int i2 = 0; i2 < nc; ++i2) sl[i2] = base[dir == 0 ? i2 : nc - 1 - i2];
-        if (spf.uses_entries)
-          for (int i2 = 0; i2 < nc; ++i2) sl[nc + i2] = make_udv(cur.take(ub), Np);
-        for (int b = 0; b < 2 * G; ++b) sl[2 * nc + b] = make_udv(cur.take(ub), Np);
-      }
       const Udv ident = make_udv(cur.take(ub), Np);
       std::vector<double*> sf(nc), sb(nc);
       for (int k = 0; k < nc; ++k) {
@@ -487,33 +542,70 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
         c.scr = sb[0];
         chain.push_back(c);
       }
-      for (int dir = 0; dir < 2; ++dir) {
-        const ScanPlan& sp = dir == 0 ? spf : spb;
-        const std::vector<Udv>& sl = dir == 0 ? slf : slb;
-        const std::vector<double*>& sc = dir == 0 ? sf : sb;
-        for (const ScanOp& op : sp.ops) {
-          Item c = blank_item(fdet::IK_COMBINE, i);
-          c.b = sl[op.left];
-          c.a = sl[op.right];
-          c.o = sl[op.out];
-          c.scr = sc[op.scr];
-          comb[op.level].push_back(c);
+      std::vector<Udv> left(nc), right(nc);
+      if (sgroup == 0) {
+        // windows: slots per length, length 1 being the intervals
+        const WinPlan wp = window_plan(nc);
+        std::vector<std::vector<Udv>> win(nc + 1);
+        win[1] = base;
+        std::vector<int> used(wp.levels, 0);   // builds placed per level
+        for (const WinBuild& bd : wp.builds) {
+          win[bd.len].resize(nc);
+          for (int k = 0; k < nc; ++k) win[bd.len][k] = make_udv(cur.take(ub), Np);
+          const std::vector<double*>& sc = used[bd.level]++ == 0 ? sf : sb;
+          for (int k = 0; k < nc; ++k) {
+            Item c = blank_item(fdet::IK_COMBINE, i);
+            c.b = win[bd.left][(k + bd.right) % nc];
+            c.a = win[bd.right][k];
+            c.o = win[bd.len][k];
+            c.scr = sc[k];
+            comb[bd.level].push_back(c);
+          }
         }
-      }
-      // Q_k: prefix entry k; S_k: suffix entry nc-1-k
-      auto at_f = [&](int k) { return slf[spf.final_slot[k]]; };
-      auto at_b = [&](int k) { return slb[spb.final_slot[nc - 1 - k]]; };
-      // log det of the whole product from Q_{nc-1}
-      {
-        Item z = blank_item(fdet::IK_CLOSE, i);
-        z.a = at_f(nc - 1);
-        z.scr = sf[0];
-        close.push_back(z);
+        for (int k = 0; k < nc; ++k) {
+          left[k] = win[wp.P][((k - wp.P) % nc + nc) % nc];
+          right[k] = wp.w2 > 0 ? win[wp.w2][k] : ident;
+        }
+      } else {
+        // scans (see scan_schedule); the inputs are shared by both
+        const ScanPlan spf = scan_schedule(nc, sgroup, true);
+        const ScanPlan spb = scan_schedule(nc, sgroup, false);
+        const int G = (nc + sgroup - 1) / sgroup;
+        std::vector<Udv> slf(2 * nc + 2 * G), slb(2 * nc + 2 * G);
+        for (int dir = 0; dir < 2; ++dir) {
+          std::vector<Udv>& sl = dir == 0 ? slf : slb;
+          // prefix sequence index i is interval i; suffix index i is nc-1-i
+          for (int i2 = 0; i2 < nc; ++i2) sl[i2] = base[dir == 0 ? i2 : nc - 1 - i2];
+          if (spf.uses_entries)
+            for (int i2 = 0; i2 < nc; ++i2) sl[nc + i2] = make_udv(cur.take(ub), Np);
+          for (int b = 0; b < 2 * G; ++b) sl[2 * nc + b] = make_udv(cur.take(ub), Np);
+        }
+        for (int dir = 0; dir < 2; ++dir) {
+          const ScanPlan& sp = dir == 0 ? spf : spb;
+          const std::vector<Udv>& sl = dir == 0 ? slf : slb;
+          const std::vector<double*>& sc = dir == 0 ? sf : sb;
+          for (const ScanOp& op : sp.ops) {
+            Item c = blank_item(fdet::IK_COMBINE, i);
+            c.b = sl[op.left];
+            c.a = sl[op.right];
+            c.o = sl[op.out];
+            c.scr = sc[op.scr];
+            comb[op.level].push_back(c);
+          }
+        }
+        // Q_{k-1}: prefix entry k-1; S_k: suffix entry nc-1-k
+        for (int k = 0; k < nc; ++k) {
+          left[k] = k == 0 ? ident : slf[spf.final_slot[k - 1]];
+          right[k] = slb[spb.final_slot[nc - 1 - k]];
+        }
       }
       // checkpoint k (row k*c) carries G~ forward over the first half of the
       // gap to the next checkpoint and backward over the second half of the
       // gap from the previous one (cyclically for k = 0), so no G~ is carried
-      // across more than about c/2 slices
+      // across more than about c/2 slices.  While the plan leaves compute
+      // units idle, the two directions are separate items (the checkpoint's
+      // G~ is then formed twice, the carries run side by side).
+      const bool split = 2 * nforce <= (size_t)device_cu_count();
       const int last_gap = q.Nt - (nc - 1) * o.c;
       for (int k = 0; k < nc; ++k) {
         Item f = blank_item(fdet::IK_FORCE, i);
@@ -522,9 +614,18 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
         f.t0 = k * o.c;
         f.t1 = f.t0 + (gap_fwd + 1) / 2;
         f.nb = (nc == 1) ? q.Nt - (q.Nt + 1) / 2 : gap_bwd / 2;
-        f.a = k == 0 ? ident : at_f(k - 1);
-        f.b = at_b(k);
+        f.a = left[k];
+        f.b = right[k];
         f.scr = sf[k];
+        if (k == 0) f.flags = fdet::IF_OUT_LOGDET | fdet::IF_OUT_G;
+        if (split && f.nb > 0) {
+          Item g = f;
+          g.flags = 0;
+          g.t1 = g.t0;   // no forward rows
+          g.scr = sb[k];
+          f.nb = 0;
+          forcei.push_back(g);
+        }
         forcei.push_back(f);
       }
     }

@@ -10,9 +10,10 @@
 //   IK_COMBINE  stabilised product of two UDV triples
 //               (eqs. prod_2_mat_stab .. res_2_mat_stab).
 //   IK_CLOSE    log det(1 + X D T) and (1 + X D T)^{-1} (Sec. 7 steps 4-6).
-//   IK_FORCE    G~ at a checkpoint from prefix and suffix UDVs (Sec. 5,
-//               stabilised pre- and suffix), then G~_{t+1} = B_t G~_t B_t^{-1}
-//               across the checkpoint interval; F_{t,x} = i (1 - G~_t)_{xx}.
+//   IK_FORCE    G~ at a checkpoint from the two stabilised factors of its
+//               cyclic product (Sec. 5, stabilised pre- and suffix
+//               products), then G~_{t+1} = B_t G~_t B_t^{-1} across the
+//               checkpoint interval; F_{t,x} = i (1 - G~_t)_{xx}.
 //   IK_EXPORT   copy a UDV triple out in the caller's layout.
 #include "fdet_device.hpp"
 #include "fdet_plan.h"
@@ -211,7 +212,7 @@ __device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC
 
 template <int NC>
 __device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
-                         bool user_out, double* tst, SmemC<NC>& S);
+                         bool user_out, bool ld_out, double* tst, SmemC<NC>& S);
 
 template <int NC>
 __device__ void chain_chunk(const Prob& P, const Item& it, CMat X, CMat& Tc, CMat& Tt, double* D,
@@ -353,7 +354,7 @@ __device__ __forceinline__ void do_combine(const Prob& P, const Item& it, SmemC<
 // ---------------------------------------------------------------------------
 template <int NC>
 __device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
-                         bool user_out, double* tst, SmemC<NC>& S) {
+                         bool user_out, bool ld_out, double* tst, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
   CMat X = cmat_at(U.X, Np), T = cmat_at(U.T, Np);
   bool bad = false;
@@ -412,7 +413,7 @@ __device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, 
     double im = li + kPi * (double)((S.nref + par) & 1);
     im = remainder(im, 2.0 * kPi);
     if (im <= -kPi) im += 2.0 * kPi;
-    if (user_out && P.logdet) { P.logdet[0] = lr; P.logdet[1] = im; }
+    if (ld_out && P.logdet) { P.logdet[0] = lr; P.logdet[1] = im; }
     int32_t code = 0;
     if (nbad > 0.0) code = -4;
     else if (!(amin > 0.0)) code = -3;
@@ -468,13 +469,14 @@ __device__ __forceinline__ void do_force(const Prob& P, const Item& it, SmemC<NC
   CMat Xc = cmat_at(it.scr + 2 * cd, Np), Tc = cmat_at(it.scr + 3 * cd, Np);
   double* Dc = it.scr + 4 * cd;
   if (threadIdx.x == 0) S.flag = 0;
-  // G~ at the checkpoint row: (1 + Q_{k-1} S_k)^{-1}, prefix a, suffix b
+  // G~ at the checkpoint row: (1 + C)^{-1} for its cyclic product C = a b
   combine_core<NC>(P, it.a, it.b, W, Qb, Xc, Tc, Dc, tstore(it.scr, Np), S);
   Udv U;
   U.X = Xc.re; U.T = Tc.re; U.D = Dc;
-  do_close<NC>(P, U, W, Qb, W, true, false, tstore(it.scr, Np), S);
-  // the checkpoint at row 0 holds G~_1 = G = M^{-1} itself
-  if (it.t0 == 0 && P.G) {
+  do_close<NC>(P, U, W, Qb, W, true, false, (it.flags & IF_OUT_LOGDET) != 0, tstore(it.scr, Np), S);
+  // the checkpoint at row 0 holds G~_1 = G = M^{-1} itself (and C_0 = M - 1:
+  // the close above gave log det M)
+  if ((it.flags & IF_OUT_G) && P.G) {
     for (int idx = threadIdx.x; idx < N * N; idx += WG) {
       const int i = idx / N, j = idx % N;
       P.G[2 * (size_t)idx] = W.r(i, j);
@@ -482,7 +484,7 @@ __device__ __forceinline__ void do_force(const Prob& P, const Item& it, SmemC<NC
     }
   }
   // keep G~ of the checkpoint for the backward direction
-  copy_cmat(Tc, W, N);
+  if (it.nb > 0) copy_cmat(Tc, W, N);
   const double* E = P.E;
   const double* Ei = P.Einv;
   auto write_row = [&](CMat G, int t) {
@@ -719,7 +721,7 @@ FDET_KERNEL(k_chain, do_chain<C>(P, it, S))
 FDET_KERNEL(k_combine, do_combine<C>(P, it, S))
 FDET_KERNEL(k_close, do_close<C>(P, it.a, cmat_at(it.scr, P.Np),
                                    cmat_at(it.scr + cmat_doubles(P.Np), P.Np),
-                                   cmat_at(it.scr, P.Np), (it.flags & IF_WANT_G) != 0, true,
+                                   cmat_at(it.scr, P.Np), (it.flags & IF_WANT_G) != 0, true, true,
                                    tstore(it.scr, P.Np), S))
 FDET_KERNEL(k_force, do_force<C>(P, it, S))
 FDET_KERNEL(k_export, do_export<C>(P, it, S))

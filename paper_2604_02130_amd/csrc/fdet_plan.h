@@ -29,14 +29,17 @@ enum ItemKind : int32_t {
   IK_CHAIN = 1,     // stabilised product of a range of slices
   IK_COMBINE = 2,   // UDV(o or a) <- UDV(b) x UDV(a): stabilised product of two
   IK_CLOSE = 3,     // log det (+ G) from a UDV
-  IK_FORCE = 4,     // G~ at a checkpoint from its prefix (a) and suffix (b),
-                    // then carried forward and backward
+  IK_FORCE = 4,     // G~ at a checkpoint from the two factors a (left) and b
+                    // (right) of its cyclic product, then carried forward
+                    // and backward
   IK_EXPORT = 5,    // copy a UDV out in user layout
 };
 
 enum ItemFlags : int32_t {
   IF_IDENTITY = 2,     // chain: start from the identity
   IF_WANT_G = 8,       // close: also form G
+  IF_OUT_LOGDET = 16,  // force: write log det M (checkpoint 0 only)
+  IF_OUT_G = 32,       // force: write G = G~ of row 0 (checkpoint 0 only)
 };
 
 // A UDV triple X diag(D) T in workspace layout.
@@ -52,7 +55,7 @@ struct Item {
   int32_t s, pad0;      // stabilisation interval
   int32_t nb, pad1;     // force: rows t0-1, ..., t0-nb (mod N_t) carried backward
   Udv a;                // state / right operand / result
-  Udv b;                // left operand (combine), suffix product (force)
+  Udv b;                // left operand (combine), right factor (force)
   Udv o;                // combine: result (X == nullptr: into a)
   double* scr;          // scratch: 4 cmats + 2*Np doubles
 };

@@ -379,15 +379,37 @@ def test_hmc_step_L16_sampled(fd):
 def test_force_grouped_scan(fd, Nt, c):
     """Enough checkpoint intervals that the prefix / suffix scans run in
     groups (sequential in a group, log-depth over the group totals): groups
-    of 4 for 300 and 301 intervals, 2 for 256, on a 256-CU device."""
+    of 4 for 300 and 301 intervals, 2 for 256, on a 256-CU device (scans
+    forced: 256 intervals would otherwise take the cyclic windows)."""
     K = honeycomb_hopping(2)
     dk = 0.1
     phi = sample_phi(900 + Nt, Nt, 8, dk, 3.0)
-    F, ld = fd.force(to_dev(K), to_dev(phi), dk, s=4, checkpoint=c, with_logdet=True)
+    F, ld = fd.force(to_dev(K), to_dev(phi), dk, s=4, checkpoint=c, with_logdet=True,
+                     flags=fd.FD_FORCE_SCANS)
     Fo = O.stabilised_force(K, dk, phi)
     assert np.abs(F.cpu().numpy() - Fo).max() <= TOL_F
     lo, _ = O.stabilised_logdet_greens(K, dk, phi)
     check_ld(complex(ld.item()), lo)
+
+
+@pytest.mark.parametrize("Nt,c", [(5, 1), (7, 1), (12, 1), (17, 1), (33, 1), (40, 3), (256, 1)])
+def test_force_cyclic_windows(fd, Nt, c):
+    """Checkpoint products from cyclic windows of P and nc - P intervals
+    (nc = ceil(Nt / c)): powers of two, odd counts and a right window that
+    needs two extra lengths (33 = 32 + 1, 17 = 16 + 1, 7 = 4 + 3); against
+    the oracle force and log det, and against the scan schedule."""
+    K = honeycomb_hopping(2)
+    dk = 0.1
+    phi = sample_phi(1700 + Nt, Nt, 8, dk, 3.0)
+    F, ld = fd.force(to_dev(K), to_dev(phi), dk, s=4, checkpoint=c, with_logdet=True)
+    Fs, lds = fd.force(to_dev(K), to_dev(phi), dk, s=4, checkpoint=c, with_logdet=True,
+                       flags=fd.FD_FORCE_SCANS)
+    Fo = O.stabilised_force(K, dk, phi)
+    assert np.abs(F.cpu().numpy() - Fo).max() <= TOL_F
+    assert np.abs(F.cpu().numpy() - Fs.cpu().numpy()).max() <= TOL_F
+    lo, _ = O.stabilised_logdet_greens(K, dk, phi)
+    check_ld(complex(ld.item()), lo)
+    check_ld(complex(lds.item()), lo)
 
 
 def test_udv_large_class(fd):
