@@ -535,29 +535,38 @@ __device__ void rq_solve(CMat W, int N, CMat Yg, SmemC<NC>& S) {
 //
 // K is walked in panels of KP = kpanel<NC>() columns: the whole workgroup
 // fetches the next A(:, k0:k0+KP) and B(k0:k0+KP, :) into registers while it
-// multiplies the
-// current panels from LDS, so device-memory latency is paid once.  Each wave
-// keeps the accumulators of its output tiles (16 x 16, round-robin) across all
-// panels.  AC / BC: operand is complex.  Loaders: la(i,k,re,im) or la(i,k),
-// lb(k,j,re,im) or lb(k,j); store st(i,j,re,im) or st(i,j,v).
+// multiplies the current panels from LDS, so device-memory latency is paid
+// once.  Each wave keeps the accumulators of its output tiles (16 x 16,
+// round-robin) across all panels.  AC / BC: operand is complex.  Loaders:
+// la(i,k,re,im) or la(i,k), lb(k,j,re,im) or lb(k,j), called for indices up
+// to NC and returning zero outside N x N; store st(i,j,re,im) or st(i,j,v),
+// called for i, j < Np.
 // ---------------------------------------------------------------------------
 template <int NC, bool AC, bool BC, class LA, class LB, class ST>
 __device__ void gemm_lds(int Np, LA la, LB lb, ST st, double* lds) {
   constexpr bool CC = AC || BC;   // complex result
   constexpr int KP = kpanel<NC>();
-  // tiles per wave; at most 4 accumulator tiles are live per pass over K
+  // tiles per wave: the 128 class keeps all 8 accumulator tiles of a wave
+  // live (one pass over K); smaller classes at most 4 per pass
   constexpr int MAXT = ((NC / 16) * (NC / 16) + NWAVE - 1) / NWAVE;
-  constexpr int TP = MAXT < 4 ? MAXT : 4;
+  constexpr int TCAP = NC >= 128 ? 8 : 4;
+  constexpr int TP = MAXT < TCAP ? MAXT : TCAP;
+  // the k-steps of a panel fully unrolled except in the 128 class, whose
+  // hoisted operands would spill
+  constexpr int UNR = NC >= 128 ? 1 : KP / 4;
   constexpr int PER = (NC * KP + WG - 1) / WG;   // panel elements per thread
+  // Panels are staged with the class size NC as their extent and stride, so
+  // all index arithmetic of the staging is compile-time; elements outside
+  // Np are fetched as zeros by the (masking) loaders and never multiplied.
+  constexpr int SD = panel_stride(NC);
+  constexpr int NEL = NC * KP;
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   const int li = lane & 15, lk = lane >> 4;
-  const int SD = panel_stride(Np);
   double* Ar = lds;
   double* Ai = Ar + KP * SD;
   double* Br = Ar + (AC ? 2 : 1) * KP * SD;
   double* Bi = Br + KP * SD;
   const int nt = Np >> 4, ntiles = nt * nt;
-  const int nel = Np * KP;
   const int npass = (ntiles + NWAVE * TP - 1) / (NWAVE * TP);
 
   double fa_r[PER], fa_i[PER], fb_r[PER], fb_i[PER];
@@ -566,8 +575,8 @@ __device__ void gemm_lds(int Np, LA la, LB lb, ST st, double* lds) {
     for (int x = 0; x < PER; ++x) {
       const int e = tid + WG * x;
       fa_r[x] = 0.0; fa_i[x] = 0.0; fb_r[x] = 0.0; fb_i[x] = 0.0;
-      if (e < nel) {
-        const int i = e % Np, kk = e / Np;            // A: rows fastest
+      if (e < NEL) {
+        const int i = e % NC, kk = e / NC;            // A: rows fastest
         if constexpr (AC) la(i, k0 + kk, fa_r[x], fa_i[x]);
         else fa_r[x] = la(i, k0 + kk);
         const int kb = e % KP, j = e / KP;            // B: k fastest
@@ -580,8 +589,8 @@ __device__ void gemm_lds(int Np, LA la, LB lb, ST st, double* lds) {
 #pragma unroll
     for (int x = 0; x < PER; ++x) {
       const int e = tid + WG * x;
-      if (e < nel) {
-        const int i = e % Np, kk = e / Np;
+      if (e < NEL) {
+        const int i = e % NC, kk = e / NC;
         Ar[kk * SD + i] = fa_r[x];
         if constexpr (AC) Ai[kk * SD + i] = fa_i[x];
         const int kb = e % KP, j = e / KP;
@@ -603,7 +612,7 @@ __device__ void gemm_lds(int Np, LA la, LB lb, ST st, double* lds) {
       stash();
       __syncthreads();
       if (k0 + KP < Np) fetch(k0 + KP);
-#pragma unroll
+#pragma unroll UNR
       for (int sk = 0; sk < KP / 4; ++sk) {
         const int kk = 4 * sk + lk;
 #pragma unroll
