@@ -70,12 +70,15 @@ __device__ __forceinline__ int tri_lo(int r, int j) { return j * NC - (j * (j - 
 // index of (row r, column i) in the upper (R) triangle, r <= i
 __device__ __forceinline__ int tri_up(int r, int i) { return (i * (i + 1)) / 2 + r; }
 
-// 32-bit DPP move applied to both halves of a double (every lane writes).
+// 32-bit DPP move applied to both halves of a double.  Every control used
+// here permutes lanes inside a row with all rows and banks enabled, so every
+// lane reads a valid source and no previous destination value is needed
+// (one instruction per half, no zeroing move).
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
@@ -113,17 +116,25 @@ __device__ __forceinline__ void static_for(F&& f) {
 // The same reflector on the column slots q >= QLO of a lane, rows in blocks
 // m >= MLO (the reflector is zero on rows < 16 MLO), reductions interleaved.
 // Both bounds are template constants: the skipped work is not emitted.
+// Written as explicit fused multiply-add chains, four per complex element for
+// u^H y and four for the update: the compiler does not contract
+// s += a b + c d by itself, and these loops are bound by VALU issue.
 template <int CPL, int RPL, int MLO, int QLO>
 __device__ __forceinline__ void rq_reflect_all(double beta, const double* ur, const double* ui,
                                                double (*yr)[RPL], double (*yi)[RPL]) {
   double wr[CPL], wi[CPL];
 #pragma unroll
   for (int q = QLO; q < CPL; ++q) {
-    double sr = 0.0, si = 0.0;
+    double sr = ur[MLO] * yr[q][MLO];
+    double si = ur[MLO] * yi[q][MLO];
+    sr = fma(ui[MLO], yi[q][MLO], sr);
+    si = fma(-ui[MLO], yr[q][MLO], si);
 #pragma unroll
-    for (int m = MLO; m < RPL; ++m) {
-      sr += ur[m] * yr[q][m] + ui[m] * yi[q][m];
-      si += ur[m] * yi[q][m] - ui[m] * yr[q][m];
+    for (int m = MLO + 1; m < RPL; ++m) {
+      sr = fma(ur[m], yr[q][m], sr);
+      si = fma(ur[m], yi[q][m], si);
+      sr = fma(ui[m], yi[q][m], sr);
+      si = fma(-ui[m], yr[q][m], si);
     }
     wr[q] = sr;
     wi[q] = si;
@@ -137,9 +148,68 @@ __device__ __forceinline__ void rq_reflect_all(double beta, const double* ur, co
   for (int q = QLO; q < CPL; ++q) {
 #pragma unroll
     for (int m = MLO; m < RPL; ++m) {
-      yr[q][m] -= ur[m] * wr[q] - ui[m] * wi[q];
-      yi[q][m] -= ur[m] * wi[q] + ui[m] * wr[q];
+      yr[q][m] = fma(-ur[m], wr[q], yr[q][m]);
+      yi[q][m] = fma(-ur[m], wi[q], yi[q][m]);
+      yr[q][m] = fma(ui[m], wi[q], yr[q][m]);
+      yi[q][m] = fma(-ui[m], wr[q], yi[q][m]);
     }
+  }
+}
+
+// 1 / sqrt(x) and 1 / x for normal x well inside the exponent range: the
+// hardware estimates refined by two Newton steps each (each step doubles the
+// number of correct bits of the estimate).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+  }
+  return y;
+}
+
+// Householder coefficients of a column with squared norm s2 (rows >= j) and
+// leading element a0: alpha = sqrt(s2), e = a0 / |a0| (1 for a0 = 0) and
+// beta = 1 / (alpha (alpha + |a0|)), so that H = I - beta u u^H with
+// u = x + e alpha e_j maps x to -e alpha e_j.  The arguments are uniform over
+// the wave, so the choice between the refined estimates (the formation of a
+// reflector is on the critical path of every column) and the library
+// functions (tiny or huge norms) is a scalar branch.
+__device__ __forceinline__ void hh_coeffs(double s2, double a0r, double a0i, double& alpha,
+                                          double& beta, double& er, double& ei) {
+  const double q0 = a0r * a0r + a0i * a0i;
+  constexpr double lo = 0x1p-700, hi = 0x1p+700;
+  er = 1.0;
+  ei = 0.0;
+  if (s2 > lo && s2 < hi && (q0 == 0.0 || q0 > lo)) {
+    alpha = s2 * rsqrt_nr(s2);
+    double aa0 = 0.0;
+    if (q0 > 0.0) {
+      const double y0 = rsqrt_nr(q0);
+      aa0 = q0 * y0;
+      er = a0r * y0;
+      ei = a0i * y0;
+    }
+    beta = rcp_nr(alpha * (alpha + aa0));
+  } else {
+    alpha = sqrt(s2);
+    const double aa0 = sqrt(q0);
+    if (aa0 > 0.0) {
+      const double inv = 1.0 / aa0;
+      er = a0r * inv;
+      ei = a0i * inv;
+    }
+    beta = alpha > 0.0 ? 1.0 / (alpha * (alpha + aa0)) : 0.0;
   }
 }
 
@@ -161,7 +231,10 @@ __device__ __forceinline__ void rq_repivot(CMat W, int N,
     const int k = grp + 32 * q;
     double s = 0.0;
 #pragma unroll
-    for (int m = JB; m < RPL; ++m) s += ar[q][m] * ar[q][m] + ai[q][m] * ai[q][m];
+    for (int m = JB; m < RPL; ++m) {
+      s = fma(ar[q][m], ar[q][m], s);
+      s = fma(ai[q][m], ai[q][m], s);
+    }
     s = red16(s);
     if (k >= j && k < N) {
       if (l16 == 0) S.v3[k] = sqrt(s) * S.csp[k];
@@ -314,21 +387,21 @@ __device__ void rq_qrp(CMat W, int N, const double* keys, SmemC<NC>& S) {
 #pragma unroll
           for (int m = JB; m < RPL; ++m) {
             const int r = l16 + 16 * m;
-            const double keep = (r >= j) ? 1.0 : 0.0;
-            s += keep * (ar[q][m] * ar[q][m] + ai[q][m] * ai[q][m]);
+            const double vr = (r >= j) ? ar[q][m] : 0.0;
+            const double vi = (r >= j) ? ai[q][m] : 0.0;
+            s = fma(vr, vr, s);
+            s = fma(vi, vi, s);
           }
         }
         // every group of the wave reduced its own slot qp; take the owner's
-        const double alpha = readlane_d(sqrt(red16(s)), 16 * (og & 3));
+        const double s2 = readlane_d(red16(s), 16 * (og & 3));
         const int src = 16 * (og & 3) + (j & 15);
         const double a0r = readlane_d(xr, src);
         const double a0i = readlane_d(xi, src);
-        const double aa0 = sqrt(a0r * a0r + a0i * a0i);
-        double er = 1.0, ei = 0.0;
-        if (aa0 > 0.0) { const double inv = 1.0 / aa0; er = a0r * inv; ei = a0i * inv; }
+        double alpha, beta, er, ei;
+        hh_coeffs(s2, a0r, a0i, alpha, beta, er, ei);
         const bool refl = alpha > 0.0;
-        const double beta = refl ? 1.0 / (alpha * (alpha + aa0)) : 0.0;
-        const double u0r = a0r + er * alpha, u0i = a0i + ei * alpha;
+        const double u0r = fma(er, alpha, a0r), u0i = fma(ei, alpha, a0i);
         if (grp == og) {
 #pragma unroll
           for (int q = QLO; q < CPL; ++q) {
@@ -492,7 +565,8 @@ __device__ void rq_solve(CMat W, int N, CMat Yg, SmemC<NC>& S) {
     constexpr int IB = RPL - 1 - decltype(kc)::value;   // rows i in block IB
     for (int i = min(16 * IB + 15, N - 1); i >= 16 * IB; --i) {
       const double dr = S.rdr[i], di = S.rdi[i];
-      const double den = dr * dr + di * di;
+      const double rden = 1.0 / (dr * dr + di * di);
+      const double ir = dr * rden, ii = -di * rden;   // 1 / R_ii
       const int li = i & 15;
       double cr[IB + 1], ci[IB + 1];
 #pragma unroll
@@ -506,14 +580,16 @@ __device__ void rq_solve(CMat W, int N, CMat Yg, SmemC<NC>& S) {
       for (int q = 0; q < CPL; ++q) {
         const double vr = __shfl(yr[q][IB], gbase + li, 64);
         const double vi = __shfl(yi[q][IB], gbase + li, 64);
-        const double zr = (vr * dr + vi * di) / den;
-        const double zi = (vi * dr - vr * di) / den;
+        const double zr = fma(vr, ir, -vi * ii);
+        const double zi = fma(vr, ii, vi * ir);
 #pragma unroll
         for (int m = 0; m <= IB; ++m) {
           const int r = l16 + 16 * m;
           if (r == i) { yr[q][m] = zr; yi[q][m] = zi; }
-          yr[q][m] -= cr[m] * zr - ci[m] * zi;
-          yi[q][m] -= cr[m] * zi + ci[m] * zr;
+          yr[q][m] = fma(-cr[m], zr, yr[q][m]);
+          yi[q][m] = fma(-cr[m], zi, yi[q][m]);
+          yr[q][m] = fma(ci[m], zi, yr[q][m]);
+          yi[q][m] = fma(-ci[m], zr, yi[q][m]);
         }
       }
     }
