@@ -28,4 +28,5 @@ from .closed_form import (  # noqa: F401
     uniform_field_logdet,
     uniform_field_greens,
     uniform_field_force,
+    two_site,
 )

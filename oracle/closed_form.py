@@ -103,3 +103,53 @@ def uniform_field_force(L: int, bk: float, theta: float) -> complex:
         a = bk * abs(f)
         acc += math.sin(theta) / (math.cos(theta) + math.cosh(a))
     return complex(-acc / N, 0.5)
+
+
+# ---------------------------------------------------------------------------
+# Two sites with one bond: K = [[0, 1], [1, 0]], so K^2 = 1 and
+# exp(dk K) = cosh(dk) 1 + sinh(dk) K.  The slice matrices, their product and
+# 1 + P are 2 x 2; their determinant and inverse are written out, with no
+# linear-algebra library: M = 1 + B_{N_t} ... B_1 (Sec. 2), G = M^{-1}, and
+# F_{t,x} = i (1 - G~_t)_{xx} with G~_t = (1 + B_{t-1} ... B_1 B_{N_t} ... B_t)^{-1}
+# (Sec. 4 response formula, phi_{t,x} entering B_t = E diag(e^{i phi_t})).
+# ---------------------------------------------------------------------------
+
+def _mul2(a, b):
+    return [[a[0][0] * b[0][0] + a[0][1] * b[1][0], a[0][0] * b[0][1] + a[0][1] * b[1][1]],
+            [a[1][0] * b[0][0] + a[1][1] * b[1][0], a[1][0] * b[0][1] + a[1][1] * b[1][1]]]
+
+
+def _inv_one_plus2(p):
+    """(1 + p)^{-1} and det(1 + p) of a 2 x 2 complex matrix."""
+    a, b, c, d = 1.0 + p[0][0], p[0][1], p[1][0], 1.0 + p[1][1]
+    det = a * d - b * c
+    return [[d / det, -b / det], [-c / det, a / det]], det
+
+
+def two_site(dk: float, phi) -> tuple:
+    """(log det M, G, F) of the two-site system; phi is (N_t, 2), row t-1 = slice t.
+    log det has its imaginary part in (-pi, pi]; G is 2 x 2, F is (N_t, 2)."""
+    ch, sh = math.cosh(dk), math.sinh(dk)
+    nt = len(phi)
+    slices = []
+    for t in range(nt):
+        e0, e1 = cmath.exp(1j * phi[t][0]), cmath.exp(1j * phi[t][1])
+        slices.append([[ch * e0, sh * e1], [sh * e0, ch * e1]])
+    one = [[1.0 + 0j, 0j], [0j, 1.0 + 0j]]
+
+    def prod(ts):
+        # B_{ts[-1]} ... B_{ts[0]}: later slices on the left
+        m = one
+        for t in ts:
+            m = _mul2(slices[t], m)
+        return m
+
+    g, det = _inv_one_plus2(prod(range(nt)))
+    logdet = _wrap(cmath.log(det))
+    force = []
+    for t in range(nt):
+        # cyclic product starting at slice t+1 (0-based t): B_t ... B_1 B_{N_t} ... B_{t+1}
+        c = prod(list(range(t, nt)) + list(range(0, t)))
+        gt, _ = _inv_one_plus2(c)
+        force.append([1j * (1.0 - gt[0][0]), 1j * (1.0 - gt[1][1])])
+    return logdet, np.array(g, dtype=complex), np.array(force, dtype=complex)

@@ -324,6 +324,37 @@ def test_batched_force(fd):
 
 
 # ---------------------------------------------------------------------------
+# worked example: two sites (tests/golden/two_site.json, 2 x 2 closed form)
+# ---------------------------------------------------------------------------
+
+def _golden_two_site():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "two_site.json")
+    with open(path) as f:
+        doc = json.load(f)
+    for c in doc["cases"]:
+        ld = complex(*c["logdet"])
+        G = np.array([[complex(*z) for z in row] for row in c["G"]])
+        F = np.array([[complex(*z) for z in row] for row in c["F"]])
+        yield c["dk"], np.array(c["phi"], dtype=float), ld, G, F
+
+
+@pytest.mark.parametrize("s,c", [(1, 1), (2, 2), (4, 3), (8, 4)])
+def test_golden_two_site(fd, s, c):
+    """log det, G and the force of the two-site system against the stored
+    closed-form values, for QR intervals and checkpoint spacings from every
+    slice to none."""
+    K = np.array([[0.0, 1.0], [1.0, 0.0]])
+    for dk, phi, ld, G, F in _golden_two_site():
+        l2, G2 = gpu_greens(fd, K, phi, dk, s=s)
+        check_ld(l2, ld)
+        check_G(G2, G)
+        F2 = fd.force(to_dev(K), to_dev(phi), dk, s=s, checkpoint=c).cpu().numpy()
+        assert np.abs(F2 - F).max() <= TOL_F
+
+
+# ---------------------------------------------------------------------------
 # N > 128: the large size class
 # ---------------------------------------------------------------------------
 

@@ -296,3 +296,46 @@ def test_pins_catch_planted_mistakes(monkeypatch):
     monkeypatch.setattr(fo, "udv_identity", lambda N: (orig(N)[0], -orig(N)[1], orig(N)[2]))
     l3, G3 = fo.stabilised_logdet_greens(K, dk, phi)
     assert np.abs(G3 - G1).max() > 1e-3
+
+
+# --- worked example: two sites, fixture in tests/golden --------------------
+
+def _golden_two_site():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "two_site.json")
+    with open(path) as f:
+        doc = json.load(f)
+    for c in doc["cases"]:
+        ld = complex(*c["logdet"])
+        G = np.array([[complex(*z) for z in row] for row in c["G"]])
+        F = np.array([[complex(*z) for z in row] for row in c["F"]])
+        yield c["dk"], np.array(c["phi"], dtype=float), ld, G, F
+
+
+def test_golden_two_site_fixture_matches_closed_form():
+    """The stored values are those of the 2 x 2 closed form (regenerate with
+    tests/golden/make_two_site.py)."""
+    for dk, phi, ld, G, F in _golden_two_site():
+        ld2, G2, F2 = O.two_site(dk, phi.tolist())
+        assert abs(wrapped_diff(ld2, ld)) <= 1e-15 * abs(ld)
+        assert np.abs(G2 - G).max() <= 1e-15
+        assert np.abs(F2 - F).max() <= 1e-15
+
+
+def test_golden_two_site_brute_force_and_stabilised():
+    """Block fermion matrix (Sec. 2), stabilised UDV (Sec. 7), sporadic QR
+    (Sec. 9) and the force (Sec. 4/5) against the two-site closed form."""
+    K = np.array([[0.0, 1.0], [1.0, 0.0]])
+    for dk, phi, ld, G, F in _golden_two_site():
+        lb, Gb = O.bruteforce_logdet_greens(K, dk, phi)
+        ls, Gs = O.stabilised_logdet_greens(K, dk, phi)
+        lp, Gp = O.sporadic_logdet_greens(K, dk, phi, 4)
+        for l2, G2 in ((lb, Gb), (ls, Gs), (lp, Gp)):
+            assert rel_err(l2, ld) <= 1e-12
+            assert np.abs(G2 - G).max() <= 1e-12
+        assert np.abs(O.bruteforce_force(K, dk, phi) - F).max() <= 1e-12
+        assert np.abs(O.stabilised_force(K, dk, phi) - F).max() <= 1e-12
+        # Im log det = (1/2) sum phi (mod pi) on the bipartite two-site graph
+        d = math.remainder(ld.imag - 0.5 * phi.sum(), math.pi)
+        assert abs(d) <= 1e-12
