@@ -69,6 +69,14 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// f(i, j) over 0 <= i, j < N: columns by wave, rows by lane (coalesced on
+// column-major data, no integer division).
+template <class F>
+__device__ __forceinline__ void for_each_ij(int N, F&& f) {
+  for (int j = threadIdx.x >> 6; j < N; j += NWAVE)
+    for (int i = threadIdx.x & 63; i < N; i += 64) f(i, j);
+}
+
 __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }

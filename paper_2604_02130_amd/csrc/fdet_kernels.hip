@@ -100,19 +100,17 @@ __device__ void load_phases(const Prob& P, int t, SmemC<NC>& S) {
 }
 
 __device__ void set_identity(CMat A, int N) {
-  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
-    const int i = idx % N, j = idx / N;
+  for_each_ij(N, [&](int i, int j) {
     A.r(i, j) = (i == j) ? 1.0 : 0.0;
     A.m(i, j) = 0.0;
-  }
+  });
 }
 
 __device__ void copy_cmat(CMat dst, CMat src, int N) {
-  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
-    const int i = idx % N, j = idx / N;
+  for_each_ij(N, [&](int i, int j) {
     dst.r(i, j) = src.r(i, j);
     dst.m(i, j) = src.m(i, j);
-  }
+  });
 }
 
 __device__ double block_sum(double v, double* red) {
@@ -330,15 +328,22 @@ __device__ __forceinline__ void do_combine(const Prob& P, const Item& it, SmemC<
   const int N = P.N, Np = P.Np;
   const size_t cd = cmat_doubles(Np);
   CMat W = cmat_at(it.scr, Np), Qb = cmat_at(it.scr + cd, Np);
-  CMat Xo = cmat_at(it.scr + 2 * cd, Np), To = cmat_at(it.scr + 3 * cd, Np);
-  double* Do = it.scr + 4 * cd;
+  CMat Xs = cmat_at(it.scr + 2 * cd, Np), Ts = cmat_at(it.scr + 3 * cd, Np);
+  double* Ds = it.scr + 4 * cd;
   if (threadIdx.x == 0) S.flag = 0;
-  // left factor b (the later slices), right factor a; result into o, or a
-  combine_core<NC>(P, it.b, it.a, W, Qb, Xo, To, Do, tstore(it.scr, Np), S);
+  // Left factor b (the later slices), right factor a; result into o, or a.
+  // combine_core reads X_b until the last-but-one product, T_a in the last,
+  // and X_a, T_b and the scales only before its QR: a result slot that is
+  // neither operand is written directly, one that is an operand takes the
+  // parts that operand no longer needs, and the rest goes through scratch.
   const Udv& R = it.o.X ? it.o : it.a;
-  copy_cmat(cmat_at(R.X, Np), Xo, N);
-  copy_cmat(cmat_at(R.T, Np), To, N);
-  for (int i = threadIdx.x; i < N; i += WG) R.D[i] = Do[i];
+  const bool is_a = R.X == it.a.X, is_b = R.X == it.b.X;
+  CMat Xo = is_b ? Xs : cmat_at(R.X, Np);
+  CMat To = is_a ? Ts : cmat_at(R.T, Np);
+  double* Do = R.D;
+  combine_core<NC>(P, it.b, it.a, W, Qb, Xo, To, Do, tstore(it.scr, Np), S);
+  if (is_b) copy_cmat(cmat_at(R.X, Np), Xs, N);
+  if (is_a) copy_cmat(cmat_at(R.T, Np), Ts, N);
   if (threadIdx.x == 0 && S.flag) status_merge(P.status, -4);
   __syncthreads();
 }
@@ -423,12 +428,11 @@ __device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, 
   __syncthreads();
   if (!want_g) return;
   // Yb = D_b^{-1} X^H
-  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
-    const int i = idx % N, j = idx / N;
+  for_each_ij(N, [&](int i, int j) {
     const double sc = 1.0 / S.v1[i];
     Yb.r(i, j) = X.r(j, i) * sc;
     Yb.m(i, j) = -X.m(j, i) * sc;
-  }
+  });
   for (int r = threadIdx.x; r < N; r += WG) S.pinv[S.piv[r]] = r;
   __syncthreads();
   qr_solve<NC>(W, N, Yb, T, tst, S);
@@ -605,10 +609,7 @@ __device__ __forceinline__ void do_expm(const Prob& P, const Item& it, SmemC<NC>
   double* A4 = Ab + 3 * n2;
   double* R0 = Ab + 4 * n2;
   double* R1 = Ab + 5 * n2;
-  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
-    const int i = idx % N, j = idx / N;
-    Ab[(size_t)j * Np + i] = a * K[(size_t)i * N + j];
-  }
+  for_each_ij(N, [&](int i, int j) { Ab[(size_t)j * Np + i] = a * K[(size_t)i * N + j]; });
   __syncthreads();
   auto ld = [&](const double* M) {
     return [=](int i, int k) { return (i < N && k < N) ? M[(size_t)k * Np + i] : 0.0; };
@@ -630,10 +631,9 @@ __device__ __forceinline__ void do_expm(const Prob& P, const Item& it, SmemC<NC>
     return ((i == jj) ? kInvFact[4 * jb] : 0.0) + Ab[o] * kInvFact[4 * jb + 1] +
            A2[o] * kInvFact[4 * jb + 2] + A3[o] * kInvFact[4 * jb + 3];
   };
-  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
-    const int i = idx % N, j = idx / N;
+  for_each_ij(N, [&](int i, int j) {
     R0[(size_t)j * Np + i] = A4[(size_t)j * Np + i] * kInvFact[16] + cj(3, i, j);
-  }
+  });
   __syncthreads();
   double* cur = R0;
   double* nxt = R1;
@@ -657,13 +657,12 @@ __device__ __forceinline__ void do_expm(const Prob& P, const Item& it, SmemC<NC>
     double* t = cur; cur = nxt; nxt = t;
   }
   bool bad = false;
-  for (int idx = threadIdx.x; idx < N * N; idx += WG) {
-    const int i = idx % N, j = idx / N;
+  for_each_ij(N, [&](int i, int j) {
     const double v = cur[(size_t)j * Np + i];
     if (!isfinite(v)) bad = true;
     out[(size_t)j * Np + i] = v;
     if (it.sign > 0 && P.outE) P.outE[(size_t)i * N + j] = v;
-  }
+  });
   if (bad) status_merge(P.status, -4);
 }
 

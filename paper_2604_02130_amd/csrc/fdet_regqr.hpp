@@ -556,10 +556,9 @@ __device__ void rq_solve(CMat W, int N, CMat Yg, SmemC<NC>& S) {
   // R into the LDS triangle (column i, rows 0..i)
   double* tr = S.big;
   double* ti = S.big + BigLds<NC>::TRI;
-  for (int idx = tid; idx < N * N; idx += WG) {
-    const int r = idx % N, i = idx / N;
+  for_each_ij(N, [&](int r, int i) {
     if (r <= i) { tr[tri_up(r, i)] = W.r(r, i); ti[tri_up(r, i)] = W.m(r, i); }
-  }
+  });
   __syncthreads();
   static_for<0, RPL>([&](auto kc) {
     constexpr int IB = RPL - 1 - decltype(kc)::value;   // rows i in block IB
