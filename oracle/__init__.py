@@ -22,6 +22,7 @@ from .fdet_oracle import (  # noqa: F401
     udv_close,
     wrap_phase,
     logdet_close,
+    response_trace,
 )
 from .closed_form import (  # noqa: F401
     honeycomb_dispersion,

@@ -344,3 +344,25 @@ def stabilised_force_rows(K, dk, phi, rows):
 def stabilised_force(K, dk, phi):
     """Complex force F (N_t, N) for every slice (see stabilised_force_rows)."""
     return stabilised_force_rows(K, dk, phi, range(1, phi.shape[0] + 1))
+
+
+# ---------------------------------------------------------------------------
+# observables
+# ---------------------------------------------------------------------------
+
+def response_trace(G, A=None):
+    """Equal-time response tr((1 - G) A) of one Green's function G = M^{-1}.
+
+    Sec. 4, shortcut for simple operators: the expectation value of an
+    operator A is the trace of A against prod_{t'' > t} B M^{-1} prod_{t' <= t} B;
+    at the slice where the left product is empty that matrix is
+    M^{-1} P = 1 - G (P = M - 1).  A = None stands for A = 1 / V, which gives
+    the fermion number n = 1 - tr G / V (eq. fermion_number).  G and A are
+    (N, N) arrays; the result is complex.
+    """
+    G = np.asarray(G, dtype=np.complex128)
+    N = G.shape[0]
+    if A is None:
+        return complex(1.0 - np.trace(G) / N)
+    A = np.asarray(A, dtype=np.complex128)
+    return complex(np.trace((np.eye(N) - G) @ A))

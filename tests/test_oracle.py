@@ -279,6 +279,49 @@ def test_force_uniform_closed_form():
     assert np.abs(F - ref).max() < 1e-12
 
 
+# --- observables (Sec. 4 shortcut) ------------------------------------------
+
+def test_response_kinetic_is_kappa_derivative_uniform_field():
+    """Uniform field: phi_{t,x} = c_t commutes with K, so P = e^{i theta}
+    exp(beta kappa K) and d log det M / d(beta kappa) = tr(G P K) =
+    tr((1 - G) K) exactly; the derivative is taken by central differences of
+    the momentum-space closed form."""
+    L, beta, Nt = 3, 4.0, 16
+    K = honeycomb_hopping(L)
+    c = np.random.default_rng(8).normal(0, 0.4, Nt)
+    phi = uniform_phi(c, K.shape[0])
+    _, G = O.bruteforce_logdet_greens(K, beta / Nt, phi)
+    got = O.response_trace(G, K)
+    h = 1e-4
+    up = O.uniform_field_logdet(L, beta + h, c.sum())
+    dn = O.uniform_field_logdet(L, beta - h, c.sum())
+    want = (up - dn) / (2 * h)
+    assert abs(got - want) <= 1e-7 * abs(want), (got, want)
+    assert abs(got.imag) <= 1e-12 * abs(got)
+
+
+def test_response_fermion_number_half_filling():
+    """Bipartite K with zero diagonal: Re G_xx = 1/2 at any field, so
+    Re n = 1/2; A = None is A = 1 / V."""
+    K, dk, phi = case(2, 12, 3.0)
+    _, G = O.bruteforce_logdet_greens(K, dk, phi)
+    n = O.response_trace(G)
+    assert abs(n.real - 0.5) <= 1e-13
+    assert abs(n - O.response_trace(G, np.eye(K.shape[0]) / K.shape[0])) <= 1e-15
+    assert abs(n.imag + np.trace(G).imag / K.shape[0]) <= 1e-15
+
+
+def test_response_rank_one_operator_picks_one_element():
+    """tr((1 - G) e_a e_b^T) = delta_ab - G_ba: the trace of a rank-one
+    product is a matrix element (catches a transposed operand)."""
+    rng = np.random.default_rng(3)
+    G = rng.normal(size=(7, 7)) + 1j * rng.normal(size=(7, 7))
+    for a, b in ((0, 0), (2, 5), (6, 1)):
+        A = np.zeros((7, 7))
+        A[a, b] = 1.0
+        assert O.response_trace(G, A) == pytest.approx((a == b) - G[b, a], abs=1e-15)
+
+
 # --- planted mistakes: each must be caught by a pin above --------------------------
 
 def test_pins_catch_planted_mistakes(monkeypatch):
@@ -339,3 +382,17 @@ def test_golden_two_site_brute_force_and_stabilised():
         # Im log det = (1/2) sum phi (mod pi) on the bipartite two-site graph
         d = math.remainder(ld.imag - 0.5 * phi.sum(), math.pi)
         assert abs(d) <= 1e-12
+
+
+def test_response_pins_catch_planted_mistakes():
+    """A transposed operand and a dropped identity must fail the pins above."""
+    rng = np.random.default_rng(3)
+    G = rng.normal(size=(7, 7)) + 1j * rng.normal(size=(7, 7))
+    A = np.zeros((7, 7))
+    A[2, 5] = 1.0
+    transposed = complex(np.trace((np.eye(7) - G) @ A.T))
+    assert abs(transposed - ((2 == 5) - G[5, 2])) > 1e-3
+    K, dk, phi = case(2, 12, 3.0)
+    _, Gk = O.bruteforce_logdet_greens(K, dk, phi)
+    no_identity = complex(-np.trace(Gk) / K.shape[0])
+    assert abs(no_identity.real - 0.5) > 1e-3
