@@ -385,6 +385,30 @@ def main():
         print(f"[bench] batched {dtb * 1e3:.1f} ms vs plain {dtp * 1e3:.1f} ms",
               file=sys.stderr, flush=True)
 
+        # ---------------- observables: tr((1 - G) A) and n = 1 - tr G / N from G
+        obs = {"workload": "tr((1 - G) A) of one random complex G and A (k_trace_tiles + "
+                           "k_trace_final); algorithmic bytes 2 N^2 x 16 B read"}
+        rng = np.random.default_rng(5)
+        for No in (72, 512):
+            Go = torch.from_numpy(rng.normal(size=(No, No)) + 1j * rng.normal(size=(No, No))).to(dev)
+            Ao = torch.from_numpy(rng.normal(size=(No, No)) + 1j * rng.normal(size=(No, No))).to(dev)
+            wso = fd.Workspace()
+            for _ in range(10):
+                fd.response_trace(Go, Ao, ws=wso)
+            reps = 200
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for _ in range(reps):
+                fd.response_trace(Go, Ao, ws=wso)
+            ev1.record()
+            torch.cuda.synchronize()
+            us = ev0.elapsed_time(ev1) * 1e3 / reps
+            nbytes = 2 * No * No * 16
+            obs[f"N{No}"] = {"us_per_call": us, "hbm_gb_s": nbytes / (us * 1e-6) / 1e9,
+                             "frac_hbm_peak": nbytes / (us * 1e-6) / PEAK_HBM}
+            print(f"[bench] response trace N={No}: {us:.1f} us", file=sys.stderr, flush=True)
+        result["observables"] = obs
+
         # ---------------- largest configuration: one HMC step of 32 fields
         if not args.no_hmc:
             hb = hmc_batch(32)

@@ -197,6 +197,26 @@ int fd_tune_save(const char *path);
 int fd_tune_load(const char *path);
 int fd_tune_clear(void);
 
+/* Equal-time response trace (Sec. 4, shortcut for simple operators): the
+ * expectation value of an operator A from one Green's function G = M^{-1},
+ *     out = tr((1 - G) A) = tr A - sum_ij G_ij A_ji,
+ * the trace of A against M^{-1} P at the slice where the partial products of
+ * the response formula are empty.  A == NULL stands for A = 1 / N, giving the
+ * fermion number n = 1 - tr G / N (eq. fermion_number).
+ *   G    device, N*N complex (interleaved, row-major, as fd_greens writes it)
+ *   A    device, N*N complex in the same layout, or NULL
+ *   out  device, 2 doubles {Re, Im}
+ *   ws   device workspace of fd_response_trace_workspace_bytes(N) bytes,
+ *        256-byte aligned (per-tile partial sums)
+ * 1 <= N <= FD_MAX_N.  Asynchronous on `stream`; the result does not depend
+ * on scheduling (partials are added in a fixed order).  Returns
+ * FD_ERR_INVALID_ARG for a bad N or a NULL G / out, FD_ERR_WORKSPACE for a
+ * missing, misaligned or short workspace, FD_ERR_HIP for a launch error.
+ * fd_response_trace_workspace_bytes returns 0 for a bad N.                   */
+size_t fd_response_trace_workspace_bytes(int32_t N);
+int fd_response_trace(int32_t N, const double *G, const double *A, double *out, void *ws,
+                      size_t ws_bytes, void *stream);
+
 /* Text for a return/status code; the last error message of this thread.      */
 const char *fd_strerror(int code);
 const char *fd_last_error(void);

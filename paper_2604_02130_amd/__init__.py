@@ -37,7 +37,7 @@ SYMBOLS = (
     "fd_udv", "fd_logdet_batched", "fd_greens_batched", "fd_force_batched",
     "fd_strerror", "fd_last_error", "fd_version", "fd_profile_start", "fd_profile_stop",
     "fd_plan_create", "fd_plan_launch", "fd_plan_destroy", "fd_autotune", "fd_tune_save",
-    "fd_tune_load", "fd_tune_clear",
+    "fd_tune_load", "fd_tune_clear", "fd_response_trace_workspace_bytes", "fd_response_trace",
 )
 
 PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export"}
@@ -112,6 +112,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fd_tune_load.restype = ctypes.c_int
     lib.fd_tune_clear.argtypes = []
     lib.fd_tune_clear.restype = ctypes.c_int
+    lib.fd_response_trace_workspace_bytes.argtypes = [i32]
+    lib.fd_response_trace_workspace_bytes.restype = sz
+    lib.fd_response_trace.argtypes = [i32, vp, vp, vp, vp, sz, vp]
+    lib.fd_response_trace.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -303,6 +307,36 @@ def udv(K, phi, dk, s=0, segments=0, check=True, ws: Workspace | None = None):
                       wsp, wsn, status.data_ptr(), _stream()))
     _status_check(status, check)
     return torch.view_as_complex(X), D, torch.view_as_complex(T)
+
+
+def _c128_matrix(name, t, N=None):
+    """Device complex128 (N, N) tensor as a contiguous interleaved buffer."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise FdError(FD_ERR_INVALID_ARG, f"{name} must be a CUDA tensor")
+    if t.dim() != 2 or t.shape[0] != t.shape[1] or (N is not None and t.shape[0] != N):
+        raise FdError(FD_ERR_INVALID_ARG, f"{name} must be square" +
+                      (f" with {N} rows" if N is not None else ""))
+    return t.to(torch.complex128).contiguous()
+
+
+def response_trace(G, A=None, ws: Workspace | None = None):
+    """tr((1 - G) A) for one Green's function G (Sec. 4 shortcut) as a
+    complex128 scalar tensor on the device; A = None gives the fermion number
+    n = 1 - tr G / N (eq. fermion_number).  G and A are (N, N) device tensors
+    (A may be real)."""
+    torch = _torch()
+    lib = load_library()
+    Gc = _c128_matrix("G", G)
+    N = int(Gc.shape[0])
+    Ac = _c128_matrix("A", A, N) if A is not None else None
+    out = torch.empty(2, dtype=torch.float64, device=Gc.device)
+    need = lib.fd_response_trace_workspace_bytes(N)
+    if need == 0:
+        raise FdError(FD_ERR_INVALID_ARG, lib.fd_last_error().decode())
+    wsp, wsn = (ws or _default_ws).get(need, Gc.device)
+    _check(lib.fd_response_trace(N, Gc.data_ptr(), _ptr(Ac), out.data_ptr(), wsp, wsn, _stream()))
+    return torch.view_as_complex(out)
 
 
 def _batch(problems):

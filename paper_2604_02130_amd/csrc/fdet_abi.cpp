@@ -19,6 +19,8 @@
 extern "C" hipError_t fdet_launch_items(int maxn, int kind, const fdet::Prob* probs,
                                         const fdet::Item* items, int nitems, hipStream_t st);
 extern "C" hipError_t fdet_launch_init_status(const fdet::Prob* probs, int nprob, hipStream_t st);
+extern "C" hipError_t fdet_launch_trace(int N, const double* G, const double* A, double* part,
+                                        double* out, hipStream_t st);
 
 namespace {
 
@@ -1103,6 +1105,28 @@ const char* fd_strerror(int code) {
 }
 
 const char* fd_last_error(void) { return g_last_error.c_str(); }
+
+size_t fd_response_trace_workspace_bytes(int32_t N) {
+  if (N < 1 || N > FD_MAX_N) {
+    fail(FD_ERR_INVALID_ARG, "N must be in [1, FD_MAX_N]");
+    return 0;
+  }
+  const size_t nb = (size_t)(N + 31) / 32;   // 32 x 32 tiles, 4 partial sums each
+  return align_up(4 * nb * nb * sizeof(double));
+}
+
+int fd_response_trace(int32_t N, const double* G, const double* A, double* out, void* ws,
+                      size_t ws_bytes, void* stream) {
+  const size_t need = fd_response_trace_workspace_bytes(N);
+  if (need == 0) return FD_ERR_INVALID_ARG;
+  if (!G || !out) return fail(FD_ERR_INVALID_ARG, "G and out must be device pointers");
+  const int rc = check_ws(ws, ws_bytes, need);
+  if (rc != FD_OK) return rc;
+  const hipError_t e = fdet_launch_trace(N, G, A, static_cast<double*>(ws), out,
+                                         static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(FD_ERR_HIP, hipGetErrorString(e));
+  return FD_OK;
+}
 
 const char* fd_version(void) { return "fdet 0.1.0 (gfx950)"; }
 

@@ -165,3 +165,20 @@ def test_force_plan_layout(lib, Nt, c):
     n = fd.workspace_bytes([prob(18, Nt)], fd.FD_WHAT_FORCE, checkpoint=c)
     m = fd.workspace_bytes([prob(18, Nt), prob(50, Nt + 3)], fd.FD_WHAT_FORCE, checkpoint=c)
     assert 0 < n < m and n % 256 == 0
+
+
+def test_response_trace_workspace_and_argument_checks(lib):
+    """Observables entry point: workspace size per 32 x 32 tile, and every bad
+    argument rejected on the host before a launch."""
+    assert lib.fd_response_trace_workspace_bytes(0) == 0
+    assert lib.fd_response_trace_workspace_bytes(fd.MAX_N + 1) == 0
+    assert lib.fd_response_trace_workspace_bytes(1) == 256
+    assert lib.fd_response_trace_workspace_bytes(72) == 512          # 9 tiles x 32 B, rounded up
+    assert lib.fd_response_trace_workspace_bytes(512) == 256 * 32    # 256 tiles x 32 B
+    ws = 0x10000
+    assert lib.fd_response_trace(0, 0x1000, 0, 0x2000, ws, 4096, None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_response_trace(8, 0, 0, 0x2000, ws, 4096, None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_response_trace(8, 0x1000, 0, 0, ws, 4096, None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_response_trace(8, 0x1000, 0, 0x2000, 0, 4096, None) == fd.FD_ERR_WORKSPACE
+    assert lib.fd_response_trace(8, 0x1000, 0, 0x2000, ws + 8, 4096, None) == fd.FD_ERR_WORKSPACE
+    assert lib.fd_response_trace(72, 0x1000, 0, 0x2000, ws, 255, None) == fd.FD_ERR_WORKSPACE

@@ -493,3 +493,45 @@ def test_force_batched_grouped_by_8(fd):
     Fs, _ = fd.force_batched(probs, s=4, checkpoint=1)
     for F, Fo in zip(Fs, refs):
         assert np.abs(F.cpu().numpy() - Fo).max() <= TOL_F
+
+
+# ---------------------------------------------------------------------------
+# f: observables (Sec. 4, shortcut for simple operators)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [1, 8, 31, 32, 33, 72, 200, 512])
+def test_response_trace_random(fd, N):
+    """tr((1 - G) A) and n = 1 - tr G / N on random complex matrices: sizes
+    below, at and across the 32 x 32 tile, a ragged tail, the largest N."""
+    rng = np.random.default_rng(2000 + N)
+    G = rng.normal(size=(N, N)) + 1j * rng.normal(size=(N, N))
+    A = rng.normal(size=(N, N)) + 1j * rng.normal(size=(N, N))
+    Gd, Ad = to_dev(G), to_dev(A)
+    got = complex(fd.response_trace(Gd, Ad).item())
+    want = O.response_trace(G, A)
+    scale = np.abs(G * A.T).sum() + np.abs(np.diag(A)).sum()
+    assert abs(got - want) <= 1e-13 * scale, (got, want)
+    n = complex(fd.response_trace(Gd).item())
+    assert abs(n - O.response_trace(G)) <= 1e-14 * (1.0 + np.abs(np.diag(G)).sum() / N)
+    # partial sums are added in a fixed order: the same bits on every call
+    assert complex(fd.response_trace(Gd, Ad).item()) == got
+    # a real operator is taken as complex
+    Ar = rng.normal(size=(N, N))
+    got_r = complex(fd.response_trace(Gd, to_dev(Ar)).item())
+    assert abs(got_r - O.response_trace(G, Ar)) <= 1e-13 * (np.abs(G * Ar.T).sum() + N)
+
+
+def test_response_trace_low_temperature_workload(fd):
+    """Fermion number and the kinetic trace tr((1 - G) K) of the L = 6,
+    N_t = 256, beta = 32 workload: GPU trace of the GPU G against the oracle
+    trace of the oracle's G; Re n = 1/2 for the bipartite K."""
+    w = WORKLOADS["lowT_L6"]
+    K, phi = w.K(), w.phi()
+    _, G = fd.greens(to_dev(K), to_dev(phi), w.dk, s=w.s)
+    _, Go = low_temperature_reference()
+    n = complex(fd.response_trace(G).item())
+    assert abs(n - O.response_trace(Go)) <= TOL_G
+    assert abs(n.real - 0.5) <= TOL_G
+    kin = complex(fd.response_trace(G, to_dev(K)).item())
+    # |d tr((1 - G) K)| <= sum |dG_ij| |K_ji| = 3 N max |dG| (three bonds per site)
+    assert abs(kin - O.response_trace(Go, K)) <= 3 * K.shape[0] * TOL_G
