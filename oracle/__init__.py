@@ -23,6 +23,8 @@ from .fdet_oracle import (  # noqa: F401
     wrap_phase,
     logdet_close,
     response_trace,
+    hmc_hamiltonian,
+    hmc_leapfrog,
 )
 from .closed_form import (  # noqa: F401
     honeycomb_dispersion,

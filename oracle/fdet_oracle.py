@@ -366,3 +366,35 @@ def response_trace(G, A=None):
         return complex(1.0 - np.trace(G) / N)
     A = np.asarray(A, dtype=np.complex128)
     return complex(np.trace((np.eye(N) - G) @ A))
+
+
+# ---------------------------------------------------------------------------
+# molecular dynamics (HMC)
+# ---------------------------------------------------------------------------
+
+def hmc_hamiltonian(K, dk, phi, pi, dU):
+    """H = 1/2 sum pi^2 + sum phi^2 / (2 dU) - 2 Re log det M(phi): unit-mass
+    momenta, the Gaussian weight of the auxiliary field and two fermion
+    flavours with complex-conjugate determinants (Sec. 3.1 and
+    eq. hamiltonian_alg, whose further terms the paper leaves open)."""
+    ld = stabilised_logdet_greens(K, dk, phi)[0]
+    return 0.5 * float(np.sum(pi * pi)) + float(np.sum(phi * phi)) / (2.0 * dU) - 2.0 * ld.real
+
+
+def hmc_leapfrog(K, dk, phi, pi, dU, eps, nsteps):
+    """Leapfrog integration of the equations of motion of hmc_hamiltonian:
+    half kick, nsteps x (drift, kick) with the last kick halved, where the
+    kick uses dH/dphi = phi / dU - 2 Re F (F = d log det M / d phi, the
+    stabilised force).  Returns (phi, pi, H_end - H_start)."""
+    phi = np.array(phi, dtype=float)
+    pi = np.array(pi, dtype=float)
+    h0 = hmc_hamiltonian(K, dk, phi, pi, dU)
+
+    def grad(f):
+        return f / dU - 2.0 * stabilised_force(K, dk, f).real
+
+    pi = pi - 0.5 * eps * grad(phi)
+    for n in range(nsteps):
+        phi = phi + eps * pi
+        pi = pi - (eps if n + 1 < nsteps else 0.5 * eps) * grad(phi)
+    return phi, pi, hmc_hamiltonian(K, dk, phi, pi, dU) - h0

@@ -322,6 +322,36 @@ def test_response_rank_one_operator_picks_one_element():
         assert O.response_trace(G, A) == pytest.approx((a == b) - G[b, a], abs=1e-15)
 
 
+# --- molecular dynamics (Sec. 3.1) -----------------------------------------
+
+def _md_case():
+    K, dk, phi = case(2, 12, 3.0, seed=21)
+    pi = np.random.default_rng(22).standard_normal(phi.shape)
+    return K, dk, phi, pi, dk * 3.0
+
+
+def test_leapfrog_is_reversible():
+    """Leapfrog is time-reversible: run, flip the momenta, run again, and the
+    start comes back."""
+    K, dk, phi, pi, dU = _md_case()
+    p1, q1, d1 = O.hmc_leapfrog(K, dk, phi, pi, dU, 0.05, 4)
+    p2, q2, d2 = O.hmc_leapfrog(K, dk, p1, -q1, dU, 0.05, 4)
+    assert np.abs(p2 - phi).max() <= 1e-11
+    assert np.abs(q2 + pi).max() <= 1e-11
+    assert abs(d1 + d2) <= 1e-9
+
+
+def test_leapfrog_energy_error_is_second_order():
+    """At a fixed trajectory length the energy error of leapfrog falls as
+    eps^2: halving eps divides dH by about 4.  A wrong sign or factor in the
+    force would leave dH of order eps or larger."""
+    K, dk, phi, pi, dU = _md_case()
+    d1 = O.hmc_leapfrog(K, dk, phi, pi, dU, 0.04, 5)[2]
+    d2 = O.hmc_leapfrog(K, dk, phi, pi, dU, 0.02, 10)[2]
+    assert abs(d1) < 0.05
+    assert 0.18 <= abs(d2 / d1) <= 0.32, (d1, d2)
+
+
 # --- planted mistakes: each must be caught by a pin above --------------------------
 
 def test_pins_catch_planted_mistakes(monkeypatch):
@@ -396,3 +426,17 @@ def test_response_pins_catch_planted_mistakes():
     _, Gk = O.bruteforce_logdet_greens(K, dk, phi)
     no_identity = complex(-np.trace(Gk) / K.shape[0])
     assert abs(no_identity.real - 0.5) > 1e-3
+
+
+def test_md_pins_catch_planted_mistakes(monkeypatch):
+    """A force with the wrong sign, or the fermion term counted once, breaks
+    the eps^2 law above."""
+    import oracle.fdet_oracle as fo
+    K, dk, phi, pi, dU = _md_case()
+    orig = fo.stabilised_force
+    for bad in (lambda K_, dk_, f: -orig(K_, dk_, f), lambda K_, dk_, f: 0.5 * orig(K_, dk_, f)):
+        monkeypatch.setattr(fo, "stabilised_force", bad)
+        d1 = fo.hmc_leapfrog(K, dk, phi, pi, dU, 0.04, 5)[2]
+        d2 = fo.hmc_leapfrog(K, dk, phi, pi, dU, 0.02, 10)[2]
+        assert not (abs(d1) < 0.05 and 0.18 <= abs(d2 / d1) <= 0.32), (d1, d2)
+    monkeypatch.undo()
