@@ -409,6 +409,33 @@ def main():
             print(f"[bench] response trace N={No}: {us:.1f} us", file=sys.stderr, flush=True)
         result["observables"] = obs
 
+        # ---------------- HMC molecular dynamics: one leapfrog trajectory
+        wm = WORKLOADS["force_L8"]
+        Km = torch.from_numpy(wm.K()).to(dev)
+        pm = torch.from_numpy(wm.phi()).to(dev)
+        rng = np.random.default_rng(6)
+        pim = torch.from_numpy(rng.standard_normal(wm.phi().shape).reshape(-1)).to(dev)
+        wsm = fd.Workspace()
+        nmd, epsm, dUm = 4, 0.02, wm.dk * 3.0
+        fd.hmc_leapfrog([(Km, pm, wm.dk)], pim, dUm, epsm, nmd, s=wm.s, checkpoint=wm.c, ws=wsm)
+        torch.cuda.synchronize()
+        reps = 3
+        a = time.perf_counter()
+        for _ in range(reps):
+            dHm = fd.hmc_leapfrog([(Km, pm, wm.dk)], pim, dUm, epsm, nmd, s=wm.s,
+                                  checkpoint=wm.c, ws=wsm)
+        torch.cuda.synchronize()
+        dtm = (time.perf_counter() - a) / reps
+        result["hmc_trajectory"] = {
+            "workload": "force_L8 field (N=128, Nt=256, s=8, c=16), leapfrog of 4 steps "
+                        "(5 force evaluations), eps=0.02, dU=delta*U",
+            "ms": dtm * 1e3,
+            "ms_per_force_eval": dtm * 1e3 / (nmd + 1),
+            "last_dH": float(dHm[0]),
+        }
+        print(f"[bench] HMC trajectory (4 steps, N=128): {dtm * 1e3:.1f} ms", file=sys.stderr,
+              flush=True)
+
         # ---------------- largest configuration: one HMC step of 32 fields
         if not args.no_hmc:
             hb = hmc_batch(32)

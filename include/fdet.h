@@ -59,7 +59,8 @@ enum {
 };
 
 /* what a workspace is sized for */
-enum { FD_WHAT_LOGDET = 0, FD_WHAT_GREENS = 1, FD_WHAT_FORCE = 2, FD_WHAT_UDV = 3 };
+enum { FD_WHAT_LOGDET = 0, FD_WHAT_GREENS = 1, FD_WHAT_FORCE = 2, FD_WHAT_UDV = 3,
+       FD_WHAT_HMC = 4 };
 
 /* option flags */
 #define FD_REUSE_E 0x1   /* exp(+-dk K) already in this workspace from an earlier
@@ -196,6 +197,32 @@ int fd_autotune(int32_t what, const fd_problem *p, int32_t nprob, const fd_optio
 int fd_tune_save(const char *path);
 int fd_tune_load(const char *path);
 int fd_tune_clear(void);
+
+/* Molecular dynamics of HMC (Sec. 3.1): one leapfrog trajectory of `nsteps`
+ * steps of size `eps` for each of `nprob` fields, with unit-mass momenta,
+ * two fermion flavours whose determinants are complex conjugates and the
+ * Gaussian weight of the auxiliary field:
+ *     H = 1/2 sum pi^2 + sum phi^2 / (2 dU) - 2 Re log det M(phi),
+ *     dH/dphi_{t,x} = phi_{t,x} / dU - 2 Re F_{t,x}   (F as for fd_force).
+ * Half kick, then nsteps x (drift, force, kick), the last kick a half one:
+ * nsteps + 1 force evaluations, each a prepared fd_force call.
+ *   p[i].phi  device, N_t*N: advanced IN PLACE to the end of the trajectory
+ *   pi        device, momenta of every field, concatenated in the layout of
+ *             fd_force_batched's force (the caller draws them); advanced in place
+ *   dH        device, nprob doubles: H at the end minus H at the start (the
+ *             caller accepts with probability min(1, exp(-dH)) and otherwise
+ *             restores its copy of phi)
+ *   dU        delta * U > 0, the variance of the auxiliary field's weight
+ *   ws        fd_workspace_bytes(p, nprob, o, FD_WHAT_HMC) bytes, 256-aligned
+ *   status    device, nprob int32: the worst status of all force evaluations
+ * o as for fd_force (FD_REUSE_E is ignored: the first evaluation computes
+ * exp(+-dk K), the rest reuse it).  Prepares plans (a synchronous descriptor
+ * upload), so it is not for stream capture; FD_ERR_INVALID_ARG for bad
+ * arguments, FD_ERR_WORKSPACE for a short workspace, FD_ERR_HIP on launch
+ * errors.                                                                   */
+int fd_hmc_leapfrog(const fd_problem *p, int32_t nprob, const fd_options *o, double dU, double eps,
+                    int32_t nsteps, double *pi, double *dH, void *ws, size_t ws_bytes,
+                    int32_t *status, void *stream);
 
 /* Equal-time response trace (Sec. 4, shortcut for simple operators): the
  * expectation value of an operator A from one Green's function G = M^{-1},

@@ -26,7 +26,7 @@ FD_ERR_NONFINITE = -4
 FD_ERR_HIP = -5
 FD_ERR_UNSUPPORTED = -6
 
-FD_WHAT_LOGDET, FD_WHAT_GREENS, FD_WHAT_FORCE, FD_WHAT_UDV = 0, 1, 2, 3
+FD_WHAT_LOGDET, FD_WHAT_GREENS, FD_WHAT_FORCE, FD_WHAT_UDV, FD_WHAT_HMC = 0, 1, 2, 3, 4
 FD_REUSE_E = 0x1
 FD_FORCE_SCANS = 0x2
 MAX_N = 512
@@ -38,6 +38,7 @@ SYMBOLS = (
     "fd_strerror", "fd_last_error", "fd_version", "fd_profile_start", "fd_profile_stop",
     "fd_plan_create", "fd_plan_launch", "fd_plan_destroy", "fd_autotune", "fd_tune_save",
     "fd_tune_load", "fd_tune_clear", "fd_response_trace_workspace_bytes", "fd_response_trace",
+    "fd_hmc_leapfrog",
 )
 
 PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export"}
@@ -112,6 +113,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fd_tune_load.restype = ctypes.c_int
     lib.fd_tune_clear.argtypes = []
     lib.fd_tune_clear.restype = ctypes.c_int
+    lib.fd_hmc_leapfrog.argtypes = [P, i32, O, ctypes.c_double, ctypes.c_double, i32, vp, vp, vp,
+                                    sz, vp, vp]
+    lib.fd_hmc_leapfrog.restype = ctypes.c_int
     lib.fd_response_trace_workspace_bytes.argtypes = [i32]
     lib.fd_response_trace_workspace_bytes.restype = sz
     lib.fd_response_trace.argtypes = [i32, vp, vp, vp, vp, sz, vp]
@@ -307,6 +311,64 @@ def udv(K, phi, dk, s=0, segments=0, check=True, ws: Workspace | None = None):
                       wsp, wsn, status.data_ptr(), _stream()))
     _status_check(status, check)
     return torch.view_as_complex(X), D, torch.view_as_complex(T)
+
+
+def hmc_leapfrog(problems, pi, dU, eps, nsteps, s=0, checkpoint=0, flags=0, check=True,
+                 ws: Workspace | None = None):
+    """One leapfrog trajectory (Sec. 3.1) of `nsteps` steps of size `eps` for
+    every (K, phi, dk) in `problems`, with
+        H = 1/2 sum pi^2 + sum phi^2 / (2 dU) - 2 Re log det M(phi).
+    Each phi and the momenta are advanced in place: `pi` is one flat float64
+    device tensor in the layout of force_batched (the fields' (N_t, N) blocks
+    one after another) or a list of (N_t, N) tensors.  Returns dH = H_end -
+    H_start per problem (float64 device tensor)."""
+    torch = _torch()
+    lib = load_library()
+    probs = _batch(problems)
+    dev = problems[0][1].device
+    n = len(probs)
+    flat = pi if isinstance(pi, torch.Tensor) else torch.cat([t.reshape(-1) for t in pi])
+    total = sum(p.Nt * p.N for p in probs)
+    if (not flat.is_cuda or flat.dtype != torch.float64 or not flat.is_contiguous()
+            or flat.numel() != total):
+        raise FdError(FD_ERR_INVALID_ARG, f"pi must hold {total} contiguous float64 values on the GPU")
+    arr = (FdProblem * n)(*probs)
+    o = _opts(s=s, checkpoint=checkpoint, flags=flags)
+    need = lib.fd_workspace_bytes(arr, n, ctypes.byref(o), FD_WHAT_HMC)
+    if need == 0:
+        raise FdError(FD_ERR_INVALID_ARG, lib.fd_last_error().decode())
+    wsp, wsn = (ws or _default_ws).get(need, dev)
+    dH = torch.empty(n, dtype=torch.float64, device=dev)
+    status = torch.empty(n, dtype=torch.int32, device=dev)
+    _check(lib.fd_hmc_leapfrog(arr, n, ctypes.byref(o), float(dU), float(eps), int(nsteps),
+                               flat.data_ptr(), dH.data_ptr(), wsp, wsn, status.data_ptr(),
+                               _stream()))
+    _status_check(status, check)
+    if not isinstance(pi, torch.Tensor):
+        off = 0
+        for t in pi:
+            t.copy_(flat[off:off + t.numel()].view_as(t))
+            off += t.numel()
+    return dH
+
+
+def hmc_trajectory(problems, dU, eps, nsteps, rng, **kw):
+    """Momenta drawn from N(0, 1) with the numpy Generator `rng`, one leapfrog
+    trajectory, and the Metropolis step: field i keeps its new value with
+    probability min(1, exp(-dH_i)), else gets its old one back.  Returns
+    (dH as numpy array, accepted flags)."""
+    import numpy as np
+    torch = _torch()
+    old = [phi.clone() for _, phi, _ in problems]
+    pis = [torch.from_numpy(rng.standard_normal(tuple(phi.shape))).to(phi.device)
+           for _, phi, _ in problems]
+    dH = hmc_leapfrog(problems, pis, dU, eps, nsteps, **kw).cpu().numpy()
+    u = rng.random(len(problems))
+    acc = u < np.exp(-np.minimum(dH, 700.0))
+    for (_, phi, _), o, a in zip(problems, old, acc):
+        if not a:
+            phi.copy_(o)
+    return dH, acc
 
 
 def _c128_matrix(name, t, N=None):

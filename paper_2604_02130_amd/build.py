@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdet.so")
 
-SOURCES = ["fdet_kernels.hip", "fdet_obs.hip", "fdet_abi.cpp"]
+SOURCES = ["fdet_kernels.hip", "fdet_obs.hip", "fdet_hmc.hip", "fdet_abi.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

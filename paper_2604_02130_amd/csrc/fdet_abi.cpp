@@ -14,11 +14,17 @@
 #include <vector>
 
 #include "../../include/fdet.h"
+#include "fdet_hmc.h"
 #include "fdet_plan.h"
 
 extern "C" hipError_t fdet_launch_items(int maxn, int kind, const fdet::Prob* probs,
                                         const fdet::Item* items, int nitems, hipStream_t st);
 extern "C" hipError_t fdet_launch_init_status(const fdet::Prob* probs, int nprob, hipStream_t st);
+extern "C" hipError_t fdet_launch_hmc(int op, const fdet::HmcProb* hp, int nprob, int64_t maxn,
+                                      double* pi, const double* force, const double* logdet,
+                                      double dU, double h, double* H0, double* dH,
+                                      const int32_t* st_step, int32_t* st_acc, int mode,
+                                      hipStream_t st);
 extern "C" hipError_t fdet_launch_trace(int N, const double* G, const double* A, double* part,
                                         double* out, hipStream_t st);
 
@@ -794,7 +800,36 @@ struct fd_plan {
 
 extern "C" {
 
+// Workspace of fd_hmc_leapfrog: the force plan's, then the force (sum N_t N
+// doubles), log det (2 per field), H at the start (1 per field), the status
+// of one force evaluation (1 int32 per field) and the field descriptors.
+struct HmcLayout {
+  size_t force_ws, f, ld, h0, st, hp, total;
+  int64_t ntot, maxn;
+};
+
+static HmcLayout hmc_layout(const fd_problem* p, int nprob, size_t force_ws) {
+  HmcLayout L{};
+  L.force_ws = align_up(force_ws);
+  for (int i = 0; i < nprob; ++i) {
+    const int64_t n = (int64_t)p[i].Nt * p[i].N;
+    L.ntot += n;
+    L.maxn = std::max(L.maxn, n);
+  }
+  L.f = L.force_ws;
+  L.ld = L.f + align_up((size_t)L.ntot * sizeof(double));
+  L.h0 = L.ld + align_up((size_t)2 * nprob * sizeof(double));
+  L.st = L.h0 + align_up((size_t)nprob * sizeof(double));
+  L.hp = L.st + align_up((size_t)nprob * sizeof(int32_t));
+  L.total = L.hp + align_up((size_t)nprob * sizeof(fdet::HmcProb));
+  return L;
+}
+
 size_t fd_workspace_bytes(const fd_problem* p, int32_t nprob, const fd_options* o, int32_t what) {
+  if (what == FD_WHAT_HMC) {
+    const size_t fw = fd_workspace_bytes(p, nprob, o, FD_WHAT_FORCE);
+    return fw ? hmc_layout(p, nprob, fw).total : 0;
+  }
   if (what < FD_WHAT_LOGDET || what > FD_WHAT_UDV) {
     fail(FD_ERR_INVALID_ARG, "unknown workspace kind");
     return 0;
@@ -1105,6 +1140,73 @@ const char* fd_strerror(int code) {
 }
 
 const char* fd_last_error(void) { return g_last_error.c_str(); }
+
+int fd_hmc_leapfrog(const fd_problem* p, int32_t nprob, const fd_options* o, double dU, double eps,
+                    int32_t nsteps, double* pi, double* dH, void* ws, size_t ws_bytes,
+                    int32_t* status, void* stream) {
+  if (!pi || !dH || !status) return fail(FD_ERR_INVALID_ARG, "pi, dH and status must be device pointers");
+  if (!(dU > 0.0) || !std::isfinite(dU)) return fail(FD_ERR_INVALID_ARG, "dU must be positive and finite");
+  if (!std::isfinite(eps)) return fail(FD_ERR_INVALID_ARG, "eps must be finite");
+  if (nsteps < 1) return fail(FD_ERR_INVALID_ARG, "nsteps must be >= 1");
+  if (!p || nprob < 1) return fail(FD_ERR_INVALID_ARG, "no problems given");
+  if (nprob > 65535) return fail(FD_ERR_INVALID_ARG, "at most 65535 fields per call");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+    return fail(FD_ERR_INVALID_ARG, "fd_hmc_leapfrog prepares plans: call it outside stream capture");
+  fd_options o1{0, 0, 0, 0};
+  if (o) o1 = *o;
+  o1.flags &= ~FD_REUSE_E;
+  const size_t fw = fd_workspace_bytes(p, nprob, &o1, FD_WHAT_FORCE);
+  if (fw == 0) return FD_ERR_INVALID_ARG;
+  const HmcLayout L = hmc_layout(p, nprob, fw);
+  int rc = check_ws(ws, ws_bytes, L.total);
+  if (rc != FD_OK) return rc;
+  char* base = static_cast<char*>(ws);
+  double* F = reinterpret_cast<double*>(base + L.f);
+  double* ld = reinterpret_cast<double*>(base + L.ld);
+  double* H0 = reinterpret_cast<double*>(base + L.h0);
+  int32_t* sstep = reinterpret_cast<int32_t*>(base + L.st);
+  fdet::HmcProb* hp = reinterpret_cast<fdet::HmcProb*>(base + L.hp);
+  std::vector<fdet::HmcProb> hh(nprob);
+  int64_t off = 0;
+  for (int i = 0; i < nprob; ++i) {
+    hh[i].phi = const_cast<double*>(p[i].phi);
+    hh[i].off = off;
+    hh[i].n = (int64_t)p[i].Nt * p[i].N;
+    off += hh[i].n;
+  }
+  hipError_t e = hipMemcpyAsync(hp, hh.data(), sizeof(fdet::HmcProb) * nprob, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+  auto md = [&](int op, double h, int mode) -> int {
+    const hipError_t r = fdet_launch_hmc(op, hp, nprob, L.maxn, pi, F, ld, dU, h, H0, dH, sstep,
+                                         status, mode, st);
+    return r == hipSuccess ? FD_OK : fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(r));
+  };
+  // the first force evaluation also computes exp(+-dk K); later ones reuse it
+  fd_plan* plan = nullptr;
+  rc = fd_plan_create(FD_WHAT_FORCE, p, nprob, &o1, ld, nullptr, F, nullptr, ws, fw, sstep, stream, &plan);
+  if (rc != FD_OK) return rc;
+  rc = fd_plan_launch(plan, stream);
+  fd_plan_destroy(plan);
+  if (rc == FD_OK) rc = md(3, 0.0, 0);
+  if (rc == FD_OK) rc = md(2, 0.0, 0);          // H at the start
+  if (rc == FD_OK) rc = md(0, 0.5 * eps, 0);    // half kick
+  if (rc != FD_OK) return rc;
+  o1.flags |= FD_REUSE_E;
+  rc = fd_plan_create(FD_WHAT_FORCE, p, nprob, &o1, ld, nullptr, F, nullptr, ws, fw, sstep, stream, &plan);
+  if (rc != FD_OK) return rc;
+  for (int n = 0; n < nsteps && rc == FD_OK; ++n) {
+    rc = md(1, eps, 0);                          // drift
+    if (rc == FD_OK) rc = fd_plan_launch(plan, stream);
+    if (rc == FD_OK) rc = md(3, 0.0, 1);
+    if (rc == FD_OK) rc = md(0, n + 1 < nsteps ? eps : 0.5 * eps, 0);
+  }
+  fd_plan_destroy(plan);
+  if (rc == FD_OK) rc = md(2, 0.0, 1);          // dH = H at the end - H at the start
+  return rc;
+}
 
 size_t fd_response_trace_workspace_bytes(int32_t N) {
   if (N < 1 || N > FD_MAX_N) {

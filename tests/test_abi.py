@@ -182,3 +182,26 @@ def test_response_trace_workspace_and_argument_checks(lib):
     assert lib.fd_response_trace(8, 0x1000, 0, 0x2000, 0, 4096, None) == fd.FD_ERR_WORKSPACE
     assert lib.fd_response_trace(8, 0x1000, 0, 0x2000, ws + 8, 4096, None) == fd.FD_ERR_WORKSPACE
     assert lib.fd_response_trace(72, 0x1000, 0, 0x2000, ws, 255, None) == fd.FD_ERR_WORKSPACE
+
+
+def test_hmc_workspace_and_argument_checks(lib):
+    """Leapfrog entry point: its workspace holds the force's and more; bad
+    arguments are rejected on the host before a launch."""
+    P = prob(18, 16)
+    force = fd.workspace_bytes([P], fd.FD_WHAT_FORCE, checkpoint=8)
+    hmc = fd.workspace_bytes([P], fd.FD_WHAT_HMC, checkpoint=8)
+    assert hmc >= force + 18 * 16 * 8 and hmc % 256 == 0
+    arr = (fd.FdProblem * 1)(P)
+    o = fd.FdOptions(4, 8, 0, 0)
+    ws, pi, dH, st = 0x100000, 0x1000, 0x2000, 0x3000
+    call = lambda **kw: lib.fd_hmc_leapfrog(
+        arr, kw.get("n", 1), ctypes.byref(o), kw.get("dU", 0.75), kw.get("eps", 0.1),
+        kw.get("steps", 3), kw.get("pi", pi), kw.get("dH", dH), ws, hmc, kw.get("st", st), None)
+    assert call(dU=0.0) == fd.FD_ERR_INVALID_ARG
+    assert call(dU=float("inf")) == fd.FD_ERR_INVALID_ARG
+    assert call(eps=float("nan")) == fd.FD_ERR_INVALID_ARG
+    assert call(steps=0) == fd.FD_ERR_INVALID_ARG
+    assert call(pi=0) == fd.FD_ERR_INVALID_ARG
+    assert call(dH=0) == fd.FD_ERR_INVALID_ARG
+    assert call(st=0) == fd.FD_ERR_INVALID_ARG
+    assert call(n=0) == fd.FD_ERR_INVALID_ARG

@@ -535,3 +535,66 @@ def test_response_trace_low_temperature_workload(fd):
     kin = complex(fd.response_trace(G, to_dev(K)).item())
     # |d tr((1 - G) K)| <= sum |dG_ij| |K_ji| = 3 N max |dG| (three bonds per site)
     assert abs(kin - O.response_trace(Go, K)) <= 3 * K.shape[0] * TOL_G
+
+
+# ---------------------------------------------------------------------------
+# f: molecular dynamics of HMC (Sec. 3.1)
+# ---------------------------------------------------------------------------
+
+def _md_fields(specs, seed):
+    import torch
+    probs, host = [], []
+    rng = np.random.default_rng(seed)
+    for i, (L, Nt, beta) in enumerate(specs):
+        K = honeycomb_hopping(L)
+        dk = beta / Nt
+        phi = sample_phi(seed + i, Nt, K.shape[0], dk, 3.0)
+        pi = rng.standard_normal(phi.shape)
+        host.append((K, dk, phi, pi))
+        probs.append((to_dev(K), to_dev(phi), dk))
+    pis = [torch.from_numpy(pi).to(dev()) for *_, pi in host]
+    return probs, host, pis
+
+
+def test_hmc_leapfrog_vs_oracle(fd):
+    """Two fields of different sizes in one call: fields, momenta and dH after
+    4 leapfrog steps against the oracle's leapfrog (same start, same dU)."""
+    specs = [(2, 16, 4.0), (3, 24, 6.0)]
+    probs, host, pis = _md_fields(specs, 3100)
+    dU = 0.25 * 3.0
+    dH = fd.hmc_leapfrog(probs, pis, dU, 0.05, 4, s=4, checkpoint=8).cpu().numpy()
+    for i, (K, dk, phi, pi) in enumerate(host):
+        p1, q1, d1 = O.hmc_leapfrog(K, dk, phi, pi, dU, 0.05, 4)
+        assert np.abs(probs[i][1].cpu().numpy() - p1).max() <= 1e-9
+        assert np.abs(pis[i].cpu().numpy() - q1).max() <= 1e-9
+        assert abs(dH[i] - d1) <= 1e-8, (dH[i], d1)
+
+
+def test_hmc_leapfrog_reversible_on_gpu(fd):
+    """Forward, flip the momenta, forward again: the start comes back, and the
+    two energy changes cancel (same bar as the force)."""
+    specs = [(3, 32, 8.0)]
+    probs, host, pis = _md_fields(specs, 3200)
+    phi0 = probs[0][1].clone()
+    pi0 = pis[0].clone()
+    d1 = fd.hmc_leapfrog(probs, pis, 1.0, 0.04, 5, s=8, checkpoint=8).cpu().numpy()
+    pis[0].neg_()
+    d2 = fd.hmc_leapfrog(probs, pis, 1.0, 0.04, 5, s=8, checkpoint=8).cpu().numpy()
+    assert float((probs[0][1] - phi0).abs().max()) <= 1e-9
+    assert float((pis[0] + pi0).abs().max()) <= 1e-9
+    assert abs(d1[0] + d2[0]) <= 1e-8
+
+
+def test_hmc_trajectory_accept_step(fd):
+    """Momenta from the generator, one trajectory, Metropolis: a small step
+    size keeps |dH| small, and a rejected field gets its old value back."""
+    specs = [(2, 16, 4.0), (2, 16, 4.0)]
+    probs, host, _ = _md_fields(specs, 3300)
+    old = [phi.clone() for _, phi, _ in probs]
+    dH, acc = fd.hmc_trajectory(probs, 0.75, 0.02, 5, np.random.default_rng(7), s=4, checkpoint=8)
+    assert np.all(np.abs(dH) < 0.1)
+    for (_, phi, _), o, a in zip(probs, old, acc):
+        if not a:
+            assert bool((phi == o).all())
+        else:
+            assert not bool((phi == o).all())
