@@ -244,6 +244,21 @@ size_t fd_response_trace_workspace_bytes(int32_t N);
 int fd_response_trace(int32_t N, const double *G, const double *A, double *out, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* Average over all slices of the response to a diagonal operator diag(a)
+ * (the shortcut of Sec. 4 summed over every slice, which for a
+ * non-constant a differs from the single-slice trace above):
+ *     out = (1 / N_t) sum_t sum_x a_x (1 - G~_t)_xx,
+ * read off the force sweep's output, (1 - G~_t)_xx = Im F_{t,x} - i Re F_{t,x}.
+ *   force, force_im  device, N_t*N: Re F and Im F as fd_force writes them
+ *                    (force_im must have been requested)
+ *   a                device, N doubles, or NULL for a_x = 1 / N (the
+ *                    fermion number)
+ *   out              device, 2 doubles {Re, Im}
+ * One workgroup, fixed summation order; no workspace.  FD_ERR_INVALID_ARG
+ * for bad sizes or NULL pointers, FD_ERR_HIP on a launch error.            */
+int fd_diag_response(int32_t Nt, int32_t N, const double *force, const double *force_im,
+                     const double *a, double *out, void *stream);
+
 /* Text for a return/status code; the last error message of this thread.      */
 const char *fd_strerror(int code);
 const char *fd_last_error(void);

@@ -23,6 +23,7 @@ from .fdet_oracle import (  # noqa: F401
     wrap_phase,
     logdet_close,
     response_trace,
+    diag_response,
     hmc_hamiltonian,
     hmc_leapfrog,
 )

@@ -398,3 +398,15 @@ def hmc_leapfrog(K, dk, phi, pi, dU, eps, nsteps):
         phi = phi + eps * pi
         pi = pi - (eps if n + 1 < nsteps else 0.5 * eps) * grad(phi)
     return phi, pi, hmc_hamiltonian(K, dk, phi, pi, dU) - h0
+
+
+def diag_response(F, a=None):
+    """Average over the slices of the response to a diagonal operator
+    diag(a): (1 / N_t) sum_t sum_x a_x (1 - G~_t)_xx (Sec. 4 shortcut summed
+    over every slice), read off the complex force F_{t,x} = i (1 - G~_t)_xx
+    as (1 - G~_t)_xx = -i F_{t,x}.  a = None stands for a_x = 1 / N (the
+    fermion number)."""
+    F = np.asarray(F, dtype=np.complex128)
+    Nt, N = F.shape
+    w = np.full(N, 1.0 / N) if a is None else np.asarray(a, dtype=float)
+    return complex(np.sum((-1j * F) @ w) / Nt)

@@ -38,7 +38,7 @@ SYMBOLS = (
     "fd_strerror", "fd_last_error", "fd_version", "fd_profile_start", "fd_profile_stop",
     "fd_plan_create", "fd_plan_launch", "fd_plan_destroy", "fd_autotune", "fd_tune_save",
     "fd_tune_load", "fd_tune_clear", "fd_response_trace_workspace_bytes", "fd_response_trace",
-    "fd_hmc_leapfrog",
+    "fd_hmc_leapfrog", "fd_diag_response",
 )
 
 PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export"}
@@ -116,6 +116,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fd_hmc_leapfrog.argtypes = [P, i32, O, ctypes.c_double, ctypes.c_double, i32, vp, vp, vp,
                                     sz, vp, vp]
     lib.fd_hmc_leapfrog.restype = ctypes.c_int
+    lib.fd_diag_response.argtypes = [i32, i32, vp, vp, vp, vp, vp]
+    lib.fd_diag_response.restype = ctypes.c_int
     lib.fd_response_trace_workspace_bytes.argtypes = [i32]
     lib.fd_response_trace_workspace_bytes.restype = sz
     lib.fd_response_trace.argtypes = [i32, vp, vp, vp, vp, sz, vp]
@@ -369,6 +371,29 @@ def hmc_trajectory(problems, dU, eps, nsteps, rng, **kw):
         if not a:
             phi.copy_(o)
     return dH, acc
+
+
+def diag_response(F, a=None):
+    """(1 / N_t) sum_t sum_x a_x (1 - G~_t)_xx from the complex force F
+    ((N_t, N) device tensor as fd.force returns it), as a complex128 scalar
+    tensor on the device; a = None gives the fermion number averaged over the
+    slices."""
+    torch = _torch()
+    lib = load_library()
+    if not isinstance(F, torch.Tensor) or not F.is_cuda or F.dim() != 2:
+        raise FdError(FD_ERR_INVALID_ARG, "F must be an (N_t, N) CUDA tensor")
+    Nt, N = int(F.shape[0]), int(F.shape[1])
+    Fc = F.to(torch.complex128)
+    fre, fim = Fc.real.contiguous(), Fc.imag.contiguous()
+    ad = None
+    if a is not None:
+        ad = a.to(device=F.device, dtype=torch.float64).contiguous()
+        if ad.numel() != N:
+            raise FdError(FD_ERR_INVALID_ARG, f"a must hold {N} values")
+    out = torch.empty(2, dtype=torch.float64, device=F.device)
+    _check(lib.fd_diag_response(Nt, N, fre.data_ptr(), fim.data_ptr(), _ptr(ad), out.data_ptr(),
+                                _stream()))
+    return torch.view_as_complex(out)
 
 
 def _c128_matrix(name, t, N=None):

@@ -25,6 +25,8 @@ extern "C" hipError_t fdet_launch_hmc(int op, const fdet::HmcProb* hp, int nprob
                                       double dU, double h, double* H0, double* dH,
                                       const int32_t* st_step, int32_t* st_acc, int mode,
                                       hipStream_t st);
+extern "C" hipError_t fdet_launch_diag_response(int Nt, int N, const double* fre, const double* fim,
+                                                const double* a, double* out, hipStream_t st);
 extern "C" hipError_t fdet_launch_trace(int N, const double* G, const double* A, double* part,
                                         double* out, hipStream_t st);
 
@@ -1226,6 +1228,17 @@ int fd_response_trace(int32_t N, const double* G, const double* A, double* out, 
   if (rc != FD_OK) return rc;
   const hipError_t e = fdet_launch_trace(N, G, A, static_cast<double*>(ws), out,
                                          static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(FD_ERR_HIP, hipGetErrorString(e));
+  return FD_OK;
+}
+
+int fd_diag_response(int32_t Nt, int32_t N, const double* force, const double* force_im,
+                     const double* a, double* out, void* stream) {
+  if (Nt < 1 || N < 1 || N > FD_MAX_N) return fail(FD_ERR_INVALID_ARG, "need Nt >= 1 and 1 <= N <= FD_MAX_N");
+  if (!force || !force_im || !out)
+    return fail(FD_ERR_INVALID_ARG, "force, force_im and out must be device pointers");
+  const hipError_t e = fdet_launch_diag_response(Nt, N, force, force_im, a, out,
+                                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail(FD_ERR_HIP, hipGetErrorString(e));
   return FD_OK;
 }

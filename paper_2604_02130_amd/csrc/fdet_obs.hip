@@ -1,4 +1,4 @@
-// Equal-time observables from a Green's function G = M^{-1} on gfx950.
+// Observables from the Green's functions on gfx950.
 //
 // Sec. 4, shortcut for simple operators: the expectation value of an operator
 // A is a trace of A against the Green's function; at the slice where the
@@ -11,6 +11,9 @@
 // A along rows too (both coalesced), meeting through LDS; a second one-
 // workgroup kernel adds the per-tile partials in a fixed order, so the result
 // does not depend on scheduling.
+//
+// The same shortcut summed over every slice, for a diagonal operator, is read
+// off the force sweep's output instead (k_diag_response below).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -131,7 +134,40 @@ __global__ __launch_bounds__(TWG) void k_trace_final(int N, int ntile, int has_a
   }
 }
 
+// Average over the slices of the response to diag(a):
+//   out = (1 / N_t) sum_t sum_x a_x (1 - G~_t)_xx,  (1 - G~_t)_xx = Im F - i Re F,
+// from the force sweep's output (F_{t,x} = i (1 - G~_t)_xx); a == nullptr
+// stands for a_x = 1 / N.  One workgroup, rows of the force read along x
+// (coalesced), partial sums in a fixed order.
+__global__ __launch_bounds__(TWG) void k_diag_response(int Nt, int N,
+                                                       const double* __restrict__ fre,
+                                                       const double* __restrict__ fim,
+                                                       const double* __restrict__ a,
+                                                       double* __restrict__ out) {
+  __shared__ double red[4][TWAVE];
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  const double inv_n = 1.0 / N;
+  const int64_t total = (int64_t)Nt * N;
+  for (int64_t k = threadIdx.x; k < total; k += TWG) {
+    const int x = (int)(k % N);
+    const double w = a ? a[x] : inv_n;
+    v[0] = fma(w, fim[k], v[0]);
+    v[1] = fma(-w, fre[k], v[1]);
+  }
+  obs_block_sum4(v, red);
+  if (threadIdx.x == 0) {
+    out[0] = v[0] / Nt;
+    out[1] = v[1] / Nt;
+  }
+}
+
 }  // namespace
+
+extern "C" hipError_t fdet_launch_diag_response(int Nt, int N, const double* fre, const double* fim,
+                                                const double* a, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_diag_response, dim3(1), dim3(TWG), 0, st, Nt, N, fre, fim, a, out);
+  return hipGetLastError();
+}
 
 // part: 4 * nb * nb doubles, nb = ceil(N / 32); the host checks N and the sizes.
 extern "C" hipError_t fdet_launch_trace(int N, const double* G, const double* A, double* part,

@@ -205,3 +205,13 @@ def test_hmc_workspace_and_argument_checks(lib):
     assert call(dH=0) == fd.FD_ERR_INVALID_ARG
     assert call(st=0) == fd.FD_ERR_INVALID_ARG
     assert call(n=0) == fd.FD_ERR_INVALID_ARG
+
+
+def test_diag_response_argument_checks(lib):
+    f, fi, out = 0x1000, 0x2000, 0x3000
+    assert lib.fd_diag_response(0, 8, f, fi, 0, out, None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_diag_response(4, 0, f, fi, 0, out, None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_diag_response(4, fd.MAX_N + 1, f, fi, 0, out, None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_diag_response(4, 8, 0, fi, 0, out, None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_diag_response(4, 8, f, 0, 0, out, None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_diag_response(4, 8, f, fi, 0, 0, None) == fd.FD_ERR_INVALID_ARG

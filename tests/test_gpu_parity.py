@@ -537,6 +537,26 @@ def test_response_trace_low_temperature_workload(fd):
     assert abs(kin - O.response_trace(Go, K)) <= 3 * K.shape[0] * TOL_G
 
 
+@pytest.mark.parametrize("L,Nt,beta,c", [(2, 20, 4.0, 5), (3, 48, 6.0, 16)])
+def test_diag_response_from_force(fd, L, Nt, beta, c):
+    """Slice average of the response to diag(a) from the GPU force against
+    the oracle's average of the oracle force; a = None against the fermion
+    number of G (every G~_t is similar to G)."""
+    import torch
+    K = honeycomb_hopping(L)
+    dk = beta / Nt
+    phi = sample_phi(2400 + L, Nt, K.shape[0], dk, 3.0)
+    F = fd.force(to_dev(K), to_dev(phi), dk, s=4, checkpoint=c)
+    a = np.random.default_rng(9).normal(size=K.shape[0])
+    got = complex(fd.diag_response(F, torch.from_numpy(a)).item())
+    Fo = O.stabilised_force(K, dk, phi)
+    assert abs(got - O.diag_response(Fo, a)) <= TOL_F * np.abs(a).sum()
+    assert abs(got - O.diag_response(F.cpu().numpy(), a)) <= 1e-14 * np.abs(a).sum()
+    n = complex(fd.diag_response(F).item())
+    _, Go = O.stabilised_logdet_greens(K, dk, phi)
+    assert abs(n - O.response_trace(Go)) <= TOL_F
+
+
 # ---------------------------------------------------------------------------
 # f: molecular dynamics of HMC (Sec. 3.1)
 # ---------------------------------------------------------------------------

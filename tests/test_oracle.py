@@ -322,6 +322,23 @@ def test_response_rank_one_operator_picks_one_element():
         assert O.response_trace(G, A) == pytest.approx((a == b) - G[b, a], abs=1e-15)
 
 
+def test_diag_response_averages_the_shifted_greens_functions():
+    """The slice average from the force equals (1 / N_t) sum_t tr((1 - G~_t)
+    diag(a)) with every G~_t taken from the block-matrix inverse (the
+    diagonal blocks of M_block^{-1} are the G~_t), and, for a = 1 / N, the
+    fermion number of G itself (G~_t is similar to G)."""
+    K, dk, phi = case(2, 10, 2.5, seed=31)
+    Nt, N = phi.shape
+    F = O.bruteforce_force(K, dk, phi)
+    Minv = np.linalg.inv(O.block_fermion_matrix(K, dk, phi))
+    a = np.random.default_rng(4).normal(size=N)
+    want = np.mean([np.trace((np.eye(N) - Minv[t * N:(t + 1) * N, t * N:(t + 1) * N]) @ np.diag(a))
+                    for t in range(Nt)])
+    assert abs(O.diag_response(F, a) - want) <= 1e-12 * max(1.0, abs(want))
+    _, G = O.bruteforce_logdet_greens(K, dk, phi)
+    assert abs(O.diag_response(F) - O.response_trace(G)) <= 1e-12
+
+
 # --- molecular dynamics (Sec. 3.1) -----------------------------------------
 
 def _md_case():
