@@ -496,6 +496,26 @@ def test_force_batched_grouped_by_8(fd):
 
 
 # ---------------------------------------------------------------------------
+# edge case: one site (N = 1), every B_t a number
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("Nt,s,c", [(1, 1, 1), (2, 1, 1), (3, 2, 2), (7, 4, 3), (16, 8, 16)])
+def test_single_site(fd, Nt, s, c):
+    """N = 1: P = exp(N_t dk k0 + i sum phi), log det M = log(1 + P),
+    G = 1 / (1 + P) and F_t = i P / (1 + P) for every t, through the full
+    path (chain, QR, combine tree, close, checkpoint products, carries)."""
+    k0, dk = 0.7, 0.3
+    phi = np.random.default_rng(40 + Nt).normal(0, 0.8, (Nt, 1))
+    P = np.exp(Nt * dk * k0 + 1j * phi.sum())
+    K = np.array([[k0]])
+    ld, G = gpu_greens(fd, K, phi, dk, s=s, segments=min(Nt, 4))
+    check_ld(ld, np.log(1.0 + P))
+    assert abs(G[0, 0] - 1.0 / (1.0 + P)) <= TOL_G
+    F = fd.force(to_dev(K), to_dev(phi), dk, s=s, checkpoint=c).cpu().numpy()
+    assert np.abs(F - 1j * P / (1.0 + P)).max() <= TOL_F
+
+
+# ---------------------------------------------------------------------------
 # f: observables (Sec. 4, shortcut for simple operators)
 # ---------------------------------------------------------------------------
 

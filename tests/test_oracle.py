@@ -279,6 +279,30 @@ def test_force_uniform_closed_form():
     assert np.abs(F - ref).max() < 1e-12
 
 
+# --- one site: scalar closed form ------------------------------------------
+
+def scalar_site(k0, dk, phi):
+    """N = 1: every B_t is the number exp(dk k0 + i phi_t), so P is their
+    product, log det M = log(1 + P), G = 1 / (1 + P), and every G~_t = G
+    (numbers commute): F_t = i (1 - G) = i P / (1 + P)."""
+    P = np.exp(len(phi) * dk * k0 + 1j * np.sum(phi))
+    G = 1.0 / (1.0 + P)
+    return np.log(1.0 + P), G, np.full((len(phi), 1), 1j * P / (1.0 + P))
+
+
+@pytest.mark.parametrize("Nt", [1, 2, 5])
+def test_scalar_site_all_tiers(Nt):
+    K = np.array([[0.7]])
+    dk = 0.3
+    phi = np.random.default_rng(Nt).normal(0, 0.8, (Nt, 1))
+    ld, G, F = scalar_site(0.7, dk, phi[:, 0])
+    for lo, Go in (O.bruteforce_logdet_greens(K, dk, phi), O.stabilised_logdet_greens(K, dk, phi)):
+        assert abs(wrapped_diff(lo, ld)) <= 1e-14
+        assert abs(Go[0, 0] - G) <= 1e-14
+    assert np.abs(O.stabilised_force(K, dk, phi) - F).max() <= 1e-14
+    assert np.abs(O.bruteforce_force(K, dk, phi) - F).max() <= 1e-14
+
+
 # --- observables (Sec. 4 shortcut) ------------------------------------------
 
 def test_response_kinetic_is_kappa_derivative_uniform_field():
