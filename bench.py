@@ -426,15 +426,28 @@ def main():
                                   checkpoint=wm.c, ws=wsm)
         torch.cuda.synchronize()
         dtm = (time.perf_counter() - a) / reps
+        # the same trajectory prepared once and replayed from a captured graph
+        hplan = fd.HmcPlan([(Km, pm, wm.dk)], dUm, epsm, nmd, s=wm.s, checkpoint=wm.c)
+        hplan.pi.copy_(pim)
+        hplan.capture()
+        hplan.replay()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            hplan.replay()
+        torch.cuda.synchronize()
+        dtg = (time.perf_counter() - a) / reps
+        hplan.close()
         result["hmc_trajectory"] = {
             "workload": "force_L8 field (N=128, Nt=256, s=8, c=16), leapfrog of 4 steps "
                         "(5 force evaluations), eps=0.02, dU=delta*U",
             "ms": dtm * 1e3,
             "ms_per_force_eval": dtm * 1e3 / (nmd + 1),
+            "graph_ms": dtg * 1e3,
             "last_dH": float(dHm[0]),
         }
-        print(f"[bench] HMC trajectory (4 steps, N=128): {dtm * 1e3:.1f} ms", file=sys.stderr,
-              flush=True)
+        print(f"[bench] HMC trajectory (4 steps, N=128): {dtm * 1e3:.1f} ms, "
+              f"graph {dtg * 1e3:.1f} ms", file=sys.stderr, flush=True)
 
         # ---------------- largest configuration: one HMC step of 32 fields
         if not args.no_hmc:

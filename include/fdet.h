@@ -224,6 +224,22 @@ int fd_hmc_leapfrog(const fd_problem *p, int32_t nprob, const fd_options *o, dou
                     int32_t nsteps, double *pi, double *dH, void *ws, size_t ws_bytes,
                     int32_t *status, void *stream);
 
+/* A prepared trajectory: fd_hmc_leapfrog's arguments fixed once.  Creation
+ * (outside stream capture, synchronous) uploads the field descriptors and
+ * runs one full force call so that exp(+-dk K) sits in the workspace; K and
+ * dk must then stay fixed.  fd_hmc_plan_launch enqueues kernels only (every
+ * force evaluation of the trajectory reuses the exponential), so it may be
+ * captured into a HIP graph and replayed; it reads phi and pi at launch time
+ * and advances both in place, as fd_hmc_leapfrog does, with the same
+ * results.  The workspace (FD_WHAT_HMC size) belongs to the plan while it
+ * lives.  fd_hmc_plan_destroy frees host memory only.                      */
+typedef struct fd_hmc_plan fd_hmc_plan;
+int fd_hmc_plan_create(const fd_problem *p, int32_t nprob, const fd_options *o, double dU,
+                       double eps, int32_t nsteps, double *pi, double *dH, void *ws,
+                       size_t ws_bytes, int32_t *status, void *stream, fd_hmc_plan **plan);
+int fd_hmc_plan_launch(const fd_hmc_plan *plan, void *stream);
+void fd_hmc_plan_destroy(fd_hmc_plan *plan);
+
 /* Equal-time response trace (Sec. 4, shortcut for simple operators): the
  * expectation value of an operator A from one Green's function G = M^{-1},
  *     out = tr((1 - G) A) = tr A - sum_ij G_ij A_ji,

@@ -38,7 +38,8 @@ SYMBOLS = (
     "fd_strerror", "fd_last_error", "fd_version", "fd_profile_start", "fd_profile_stop",
     "fd_plan_create", "fd_plan_launch", "fd_plan_destroy", "fd_autotune", "fd_tune_save",
     "fd_tune_load", "fd_tune_clear", "fd_response_trace_workspace_bytes", "fd_response_trace",
-    "fd_hmc_leapfrog", "fd_diag_response",
+    "fd_hmc_leapfrog", "fd_diag_response", "fd_hmc_plan_create", "fd_hmc_plan_launch",
+    "fd_hmc_plan_destroy",
 )
 
 PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export"}
@@ -116,6 +117,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fd_hmc_leapfrog.argtypes = [P, i32, O, ctypes.c_double, ctypes.c_double, i32, vp, vp, vp,
                                     sz, vp, vp]
     lib.fd_hmc_leapfrog.restype = ctypes.c_int
+    lib.fd_hmc_plan_create.argtypes = [P, i32, O, ctypes.c_double, ctypes.c_double, i32, vp, vp,
+                                       vp, sz, vp, vp, ctypes.POINTER(vp)]
+    lib.fd_hmc_plan_create.restype = ctypes.c_int
+    lib.fd_hmc_plan_launch.argtypes = [vp, vp]
+    lib.fd_hmc_plan_launch.restype = ctypes.c_int
+    lib.fd_hmc_plan_destroy.argtypes = [vp]
+    lib.fd_hmc_plan_destroy.restype = None
     lib.fd_diag_response.argtypes = [i32, i32, vp, vp, vp, vp, vp]
     lib.fd_diag_response.restype = ctypes.c_int
     lib.fd_response_trace_workspace_bytes.argtypes = [i32]
@@ -394,6 +402,107 @@ def diag_response(F, a=None):
     _check(lib.fd_diag_response(Nt, N, fre.data_ptr(), fim.data_ptr(), _ptr(ad), out.data_ptr(),
                                 _stream()))
     return torch.view_as_complex(out)
+
+
+class HmcPlan:
+    """A prepared leapfrog trajectory (fd_hmc_plan_create) on fixed fields,
+    momenta and step parameters, with a workspace of its own.  launch() only
+    enqueues kernels, so capture() records it in a graph that replay()
+    reruns; the fields (the phi tensors of `problems`) and the momenta
+    (`self.pi`, flat, in the layout of force_batched) are read at launch time
+    and advanced in place.  exp(+-dk K) is computed once here.
+
+        plan = HmcPlan(problems, dU, eps, nsteps, s=8, checkpoint=16)
+        dH, acc = plan.trajectory(np.random.default_rng(1))   # draw, run, accept
+    """
+
+    def __init__(self, problems, dU, eps, nsteps, s=0, checkpoint=0, flags=0):
+        torch = _torch()
+        self.lib = load_library()
+        self.problems = list(problems)
+        self.probs = _batch(self.problems)
+        n = len(self.probs)
+        dev = self.problems[0][1].device
+        self.n = n
+        self.shapes = [(p.Nt, p.N) for p in self.probs]
+        self.arr = (FdProblem * n)(*self.probs)
+        self.pi = torch.zeros(sum(p.Nt * p.N for p in self.probs), dtype=torch.float64, device=dev)
+        self.dH = torch.empty(n, dtype=torch.float64, device=dev)
+        self.status = torch.empty(n, dtype=torch.int32, device=dev)
+        o = _opts(s=s, checkpoint=checkpoint, flags=flags)
+        need = self.lib.fd_workspace_bytes(self.arr, n, ctypes.byref(o), FD_WHAT_HMC)
+        if need == 0:
+            raise FdError(FD_ERR_INVALID_ARG, self.lib.fd_last_error().decode())
+        self.ws = Workspace()
+        self.wsp, self.wsn = self.ws.get(need, dev)
+        self.handle = ctypes.c_void_p(0)
+        _check(self.lib.fd_hmc_plan_create(self.arr, n, ctypes.byref(o), float(dU), float(eps),
+                                           int(nsteps), self.pi.data_ptr(), self.dH.data_ptr(),
+                                           self.wsp, self.wsn, self.status.data_ptr(), _stream(),
+                                           ctypes.byref(self.handle)))
+        self.graph = None
+
+    def launch(self):
+        """Enqueue one trajectory on the current stream."""
+        _check(self.lib.fd_hmc_plan_launch(self.handle, _stream()))
+
+    def capture(self):
+        """Record launch() in a CUDA/HIP graph (after one warm-up launch on
+        a side stream, which advances the fields and momenta once)."""
+        torch = _torch()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.launch()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.launch()
+        torch.cuda.synchronize()
+
+    def replay(self):
+        if self.graph is None:
+            self.launch()
+        else:
+            self.graph.replay()
+
+    def momenta(self):
+        """Views of self.pi per field, shaped (N_t, N)."""
+        out, off = [], 0
+        for Nt, N in self.shapes:
+            out.append(self.pi[off:off + Nt * N].view(Nt, N))
+            off += Nt * N
+        return out
+
+    def trajectory(self, rng, check=True):
+        """Momenta from N(0, 1) drawn with the numpy Generator `rng`, one
+        trajectory (the graph if captured), and the Metropolis step.  Returns
+        (dH as numpy array, accepted flags)."""
+        import numpy as np
+        torch = _torch()
+        old = [phi.clone() for _, phi, _ in self.problems]
+        self.pi.copy_(torch.from_numpy(rng.standard_normal(self.pi.numel())))
+        self.replay()
+        _status_check(self.status, check)
+        dH = self.dH.cpu().numpy()
+        u = rng.random(self.n)
+        acc = u < np.exp(-np.minimum(dH, 700.0))
+        for (_, phi, _), o, a in zip(self.problems, old, acc):
+            if not a:
+                phi.copy_(o)
+        return dH, acc
+
+    def close(self):
+        if self.handle:
+            self.lib.fd_hmc_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _c128_matrix(name, t, N=None):

@@ -1210,6 +1210,118 @@ int fd_hmc_leapfrog(const fd_problem* p, int32_t nprob, const fd_options* o, dou
   return rc;
 }
 
+struct fd_hmc_plan {
+  fd_plan* force = nullptr;   // prepared force call with exp(+-dk K) already in ws
+  fdet::HmcProb* hp = nullptr;
+  int nprob = 0;
+  int64_t maxn = 0;
+  double dU = 0.0, eps = 0.0;
+  int nsteps = 0;
+  double *pi = nullptr, *dH = nullptr, *F = nullptr, *ld = nullptr, *H0 = nullptr;
+  int32_t *sstep = nullptr, *status = nullptr;
+};
+
+int fd_hmc_plan_create(const fd_problem* p, int32_t nprob, const fd_options* o, double dU,
+                       double eps, int32_t nsteps, double* pi, double* dH, void* ws,
+                       size_t ws_bytes, int32_t* status, void* stream, fd_hmc_plan** plan) {
+  if (!plan) return fail(FD_ERR_INVALID_ARG, "plan must not be NULL");
+  *plan = nullptr;
+  if (!pi || !dH || !status) return fail(FD_ERR_INVALID_ARG, "pi, dH and status must be device pointers");
+  if (!(dU > 0.0) || !std::isfinite(dU)) return fail(FD_ERR_INVALID_ARG, "dU must be positive and finite");
+  if (!std::isfinite(eps)) return fail(FD_ERR_INVALID_ARG, "eps must be finite");
+  if (nsteps < 1) return fail(FD_ERR_INVALID_ARG, "nsteps must be >= 1");
+  if (!p || nprob < 1) return fail(FD_ERR_INVALID_ARG, "no problems given");
+  if (nprob > 65535) return fail(FD_ERR_INVALID_ARG, "at most 65535 fields per call");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+    return fail(FD_ERR_INVALID_ARG, "create plans outside stream capture");
+  fd_options o1{0, 0, 0, 0};
+  if (o) o1 = *o;
+  o1.flags &= ~FD_REUSE_E;
+  const size_t fw = fd_workspace_bytes(p, nprob, &o1, FD_WHAT_FORCE);
+  if (fw == 0) return FD_ERR_INVALID_ARG;
+  const HmcLayout L = hmc_layout(p, nprob, fw);
+  int rc = check_ws(ws, ws_bytes, L.total);
+  if (rc != FD_OK) return rc;
+  char* base = static_cast<char*>(ws);
+  fd_hmc_plan* h = new fd_hmc_plan;
+  h->F = reinterpret_cast<double*>(base + L.f);
+  h->ld = reinterpret_cast<double*>(base + L.ld);
+  h->H0 = reinterpret_cast<double*>(base + L.h0);
+  h->sstep = reinterpret_cast<int32_t*>(base + L.st);
+  h->hp = reinterpret_cast<fdet::HmcProb*>(base + L.hp);
+  h->nprob = nprob;
+  h->maxn = L.maxn;
+  h->dU = dU;
+  h->eps = eps;
+  h->nsteps = nsteps;
+  h->pi = pi;
+  h->dH = dH;
+  h->status = status;
+  std::vector<fdet::HmcProb> hh(nprob);
+  int64_t off = 0;
+  for (int i = 0; i < nprob; ++i) {
+    hh[i].phi = const_cast<double*>(p[i].phi);
+    hh[i].off = off;
+    hh[i].n = (int64_t)p[i].Nt * p[i].N;
+    off += hh[i].n;
+  }
+  hipError_t e = hipMemcpyAsync(h->hp, hh.data(), sizeof(fdet::HmcProb) * nprob,
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(FD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+  }
+  // one full force call now leaves exp(+-dk K) in the workspace; the plan
+  // kept for the launches reuses it (K and dk fixed for the plan's lifetime)
+  fd_plan* full = nullptr;
+  rc = fd_plan_create(FD_WHAT_FORCE, p, nprob, &o1, h->ld, nullptr, h->F, nullptr, ws, fw, h->sstep,
+                      stream, &full);
+  if (rc == FD_OK) rc = fd_plan_launch(full, stream);
+  fd_plan_destroy(full);
+  if (rc == FD_OK) {
+    o1.flags |= FD_REUSE_E;
+    rc = fd_plan_create(FD_WHAT_FORCE, p, nprob, &o1, h->ld, nullptr, h->F, nullptr, ws, fw,
+                        h->sstep, stream, &h->force);
+  }
+  if (rc != FD_OK) {
+    delete h;
+    return rc;
+  }
+  *plan = h;
+  return FD_OK;
+}
+
+int fd_hmc_plan_launch(const fd_hmc_plan* h, void* stream) {
+  if (!h) return fail(FD_ERR_INVALID_ARG, "plan must not be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  auto md = [&](int op, double step, int mode) -> int {
+    const hipError_t r = fdet_launch_hmc(op, h->hp, h->nprob, h->maxn, h->pi, h->F, h->ld, h->dU,
+                                         step, h->H0, h->dH, h->sstep, h->status, mode, st);
+    return r == hipSuccess ? FD_OK : fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(r));
+  };
+  int rc = fd_plan_launch(h->force, stream);
+  if (rc == FD_OK) rc = md(3, 0.0, 0);
+  if (rc == FD_OK) rc = md(2, 0.0, 0);
+  if (rc == FD_OK) rc = md(0, 0.5 * h->eps, 0);
+  for (int n = 0; n < h->nsteps && rc == FD_OK; ++n) {
+    rc = md(1, h->eps, 0);
+    if (rc == FD_OK) rc = fd_plan_launch(h->force, stream);
+    if (rc == FD_OK) rc = md(3, 0.0, 1);
+    if (rc == FD_OK) rc = md(0, n + 1 < h->nsteps ? h->eps : 0.5 * h->eps, 0);
+  }
+  if (rc == FD_OK) rc = md(2, 0.0, 1);
+  return rc;
+}
+
+void fd_hmc_plan_destroy(fd_hmc_plan* h) {
+  if (!h) return;
+  fd_plan_destroy(h->force);
+  delete h;
+}
+
 size_t fd_response_trace_workspace_bytes(int32_t N) {
   if (N < 1 || N > FD_MAX_N) {
     fail(FD_ERR_INVALID_ARG, "N must be in [1, FD_MAX_N]");

@@ -215,3 +215,23 @@ def test_diag_response_argument_checks(lib):
     assert lib.fd_diag_response(4, 8, 0, fi, 0, out, None) == fd.FD_ERR_INVALID_ARG
     assert lib.fd_diag_response(4, 8, f, 0, 0, out, None) == fd.FD_ERR_INVALID_ARG
     assert lib.fd_diag_response(4, 8, f, fi, 0, 0, None) == fd.FD_ERR_INVALID_ARG
+
+
+def test_hmc_plan_argument_checks(lib):
+    P = prob(18, 16)
+    arr = (fd.FdProblem * 1)(P)
+    o = fd.FdOptions(4, 8, 0, 0)
+    hmc = fd.workspace_bytes([P], fd.FD_WHAT_HMC, checkpoint=8)
+    h = ctypes.c_void_p(0)
+    ws, pi, dH, st = 0x100000, 0x1000, 0x2000, 0x3000
+    assert lib.fd_hmc_plan_create(arr, 1, ctypes.byref(o), 0.75, 0.1, 3, pi, dH, ws, hmc, st, None,
+                                  None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_hmc_plan_create(arr, 1, ctypes.byref(o), -1.0, 0.1, 3, pi, dH, ws, hmc, st, None,
+                                  ctypes.byref(h)) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_hmc_plan_create(arr, 1, ctypes.byref(o), 0.75, 0.1, 0, pi, dH, ws, hmc, st, None,
+                                  ctypes.byref(h)) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_hmc_plan_create(arr, 1, ctypes.byref(o), 0.75, 0.1, 3, 0, dH, ws, hmc, st, None,
+                                  ctypes.byref(h)) == fd.FD_ERR_INVALID_ARG
+    assert not h.value
+    assert lib.fd_hmc_plan_launch(None, None) == fd.FD_ERR_INVALID_ARG
+    lib.fd_hmc_plan_destroy(None)

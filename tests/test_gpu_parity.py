@@ -638,3 +638,59 @@ def test_hmc_trajectory_accept_step(fd):
             assert bool((phi == o).all())
         else:
             assert not bool((phi == o).all())
+
+
+def test_hmc_plan_and_graph_replays_match_leapfrog(fd):
+    """The prepared trajectory, launched eagerly and replayed from a captured
+    graph three times (fields and momenta reset in between, eager work
+    between the replays), gives the bits of fd_hmc_leapfrog."""
+    import torch
+    specs = [(2, 16, 4.0), (3, 24, 6.0)]
+    probs, host, pis = _md_fields(specs, 3400)
+    phi0 = [phi.clone() for _, phi, _ in probs]
+    pi0 = torch.cat([p.reshape(-1) for p in pis])
+    ref_pi = pi0.clone()
+    ref_phi = [p.clone() for p in phi0]
+    ref_probs = [(K, ph, dk) for (K, _, dk), ph in zip(probs, ref_phi)]
+    ref_dH = fd.hmc_leapfrog(ref_probs, ref_pi, 0.75, 0.05, 3, s=4, checkpoint=8)
+    plan = fd.HmcPlan(probs, 0.75, 0.05, 3, s=4, checkpoint=8)
+
+    def reset():
+        for (_, phi, _), p0 in zip(probs, phi0):
+            phi.copy_(p0)
+        plan.pi.copy_(pi0)
+
+    def check():
+        torch.cuda.synchronize()
+        assert torch.equal(plan.dH, ref_dH)
+        assert torch.equal(plan.pi, ref_pi)
+        for (_, phi, _), r in zip(probs, ref_phi):
+            assert torch.equal(phi, r)
+
+    reset()
+    plan.launch()
+    check()
+    plan.capture()
+    for k in range(3):
+        reset()
+        torch.cuda.synchronize()
+        junk = torch.randn(256, 256, device=dev(), dtype=torch.float64) @ torch.randn(
+            256, 256, device=dev(), dtype=torch.float64)
+        plan.replay()
+        check()
+        del junk
+    # the step as a whole: draw, run, accept; dH against the oracle's
+    # leapfrog from the same momenta (a large dH is physics: the trajectory of
+    # field 0 passes close to a zero of det M)
+    reset()
+    dH, acc = plan.trajectory(np.random.default_rng(11))
+    draw = np.random.default_rng(11).standard_normal(int(pi0.numel()))
+    off = 0
+    for i, (K, dk, phi, _) in enumerate(host):
+        p = draw[off:off + phi.size].reshape(phi.shape)
+        off += phi.size
+        d = O.hmc_leapfrog(K, dk, phi, p, 0.75, 0.05, 3)[2]
+        assert abs(dH[i] - d) <= 1e-8 * max(1.0, abs(d)), (dH[i], d)
+        if not acc[i]:
+            assert torch.equal(probs[i][1], phi0[i])
+    plan.close()
