@@ -367,18 +367,24 @@ def hmc_trajectory(problems, dU, eps, nsteps, rng, **kw):
     trajectory, and the Metropolis step: field i keeps its new value with
     probability min(1, exp(-dH_i)), else gets its old one back.  Returns
     (dH as numpy array, accepted flags)."""
-    import numpy as np
     torch = _torch()
     old = [phi.clone() for _, phi, _ in problems]
     pis = [torch.from_numpy(rng.standard_normal(tuple(phi.shape))).to(phi.device)
            for _, phi, _ in problems]
     dH = hmc_leapfrog(problems, pis, dU, eps, nsteps, **kw).cpu().numpy()
+    return dH, _metropolis(problems, old, dH, rng)
+
+
+def _metropolis(problems, old, dH, rng):
+    """Accept field i with probability min(1, exp(-dH_i)) (one uniform draw
+    per field from `rng`); a rejected field gets its old value back."""
+    import numpy as np
     u = rng.random(len(problems))
     acc = u < np.exp(-np.minimum(dH, 700.0))
     for (_, phi, _), o, a in zip(problems, old, acc):
         if not a:
             phi.copy_(o)
-    return dH, acc
+    return acc
 
 
 def diag_response(F, a=None):
@@ -479,19 +485,13 @@ class HmcPlan:
         """Momenta from N(0, 1) drawn with the numpy Generator `rng`, one
         trajectory (the graph if captured), and the Metropolis step.  Returns
         (dH as numpy array, accepted flags)."""
-        import numpy as np
         torch = _torch()
         old = [phi.clone() for _, phi, _ in self.problems]
         self.pi.copy_(torch.from_numpy(rng.standard_normal(self.pi.numel())))
         self.replay()
         _status_check(self.status, check)
         dH = self.dH.cpu().numpy()
-        u = rng.random(self.n)
-        acc = u < np.exp(-np.minimum(dH, 700.0))
-        for (_, phi, _), o, a in zip(self.problems, old, acc):
-            if not a:
-                phi.copy_(o)
-        return dH, acc
+        return dH, _metropolis(self.problems, old, dH, rng)
 
     def close(self):
         if self.handle:

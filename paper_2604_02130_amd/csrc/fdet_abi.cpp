@@ -800,7 +800,7 @@ struct fd_plan {
   char* ws = nullptr;
 };
 
-extern "C" {
+namespace {
 
 // Workspace of fd_hmc_leapfrog: the force plan's, then the force (sum N_t N
 // doubles), log det (2 per field), H at the start (1 per field), the status
@@ -810,7 +810,7 @@ struct HmcLayout {
   int64_t ntot, maxn;
 };
 
-static HmcLayout hmc_layout(const fd_problem* p, int nprob, size_t force_ws) {
+HmcLayout hmc_layout(const fd_problem* p, int nprob, size_t force_ws) {
   HmcLayout L{};
   L.force_ws = align_up(force_ws);
   for (int i = 0; i < nprob; ++i) {
@@ -826,6 +826,100 @@ static HmcLayout hmc_layout(const fd_problem* p, int nprob, size_t force_ws) {
   L.total = L.hp + align_up((size_t)nprob * sizeof(fdet::HmcProb));
   return L;
 }
+
+// A leapfrog trajectory's fixed arguments and its part of the workspace.
+struct HmcState {
+  fdet::HmcProb* hp = nullptr;
+  int nprob = 0;
+  int64_t maxn = 0;
+  double dU = 0.0, eps = 0.0;
+  int nsteps = 0;
+  double *pi = nullptr, *dH = nullptr, *F = nullptr, *ld = nullptr, *H0 = nullptr;
+  int32_t *sstep = nullptr, *status = nullptr;
+  size_t force_ws = 0;   // bytes at the head of the workspace for the force plan
+};
+
+// Checks the arguments of fd_hmc_leapfrog / fd_hmc_plan_create, carves the
+// workspace (hmc_layout) and uploads the field descriptors (synchronously).
+// o1: the force options with FD_REUSE_E cleared.
+int hmc_setup(const fd_problem* p, int32_t nprob, const fd_options* o, double dU, double eps,
+              int32_t nsteps, double* pi, double* dH, void* ws, size_t ws_bytes, int32_t* status,
+              void* stream, fd_options& o1, HmcState& S) {
+  if (!pi || !dH || !status) return fail(FD_ERR_INVALID_ARG, "pi, dH and status must be device pointers");
+  if (!(dU > 0.0) || !std::isfinite(dU)) return fail(FD_ERR_INVALID_ARG, "dU must be positive and finite");
+  if (!std::isfinite(eps)) return fail(FD_ERR_INVALID_ARG, "eps must be finite");
+  if (nsteps < 1) return fail(FD_ERR_INVALID_ARG, "nsteps must be >= 1");
+  if (!p || nprob < 1) return fail(FD_ERR_INVALID_ARG, "no problems given");
+  if (nprob > 65535) return fail(FD_ERR_INVALID_ARG, "at most 65535 fields per call");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+    return fail(FD_ERR_INVALID_ARG, "trajectories prepare plans: call outside stream capture");
+  o1 = fd_options{0, 0, 0, 0};
+  if (o) o1 = *o;
+  o1.flags &= ~FD_REUSE_E;
+  const size_t fw = fd_workspace_bytes(p, nprob, &o1, FD_WHAT_FORCE);
+  if (fw == 0) return FD_ERR_INVALID_ARG;
+  const HmcLayout L = hmc_layout(p, nprob, fw);
+  int rc = check_ws(ws, ws_bytes, L.total);
+  if (rc != FD_OK) return rc;
+  char* base = static_cast<char*>(ws);
+  S.force_ws = fw;
+  S.F = reinterpret_cast<double*>(base + L.f);
+  S.ld = reinterpret_cast<double*>(base + L.ld);
+  S.H0 = reinterpret_cast<double*>(base + L.h0);
+  S.sstep = reinterpret_cast<int32_t*>(base + L.st);
+  S.hp = reinterpret_cast<fdet::HmcProb*>(base + L.hp);
+  S.nprob = nprob;
+  S.maxn = L.maxn;
+  S.dU = dU;
+  S.eps = eps;
+  S.nsteps = nsteps;
+  S.pi = pi;
+  S.dH = dH;
+  S.status = status;
+  std::vector<fdet::HmcProb> hh(nprob);
+  int64_t off = 0;
+  for (int i = 0; i < nprob; ++i) {
+    hh[i].phi = const_cast<double*>(p[i].phi);
+    hh[i].off = off;
+    hh[i].n = (int64_t)p[i].Nt * p[i].N;
+    off += hh[i].n;
+  }
+  hipError_t e = hipMemcpyAsync(S.hp, hh.data(), sizeof(fdet::HmcProb) * nprob,
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+  return FD_OK;
+}
+
+// Enqueues one trajectory: half kick, nsteps x (drift, force, kick), the
+// last kick a half one, with H before and after.  force(n) enqueues force
+// evaluation n (0 at the start field) into S.F, S.ld and S.sstep.
+template <class Force>
+int hmc_enqueue(const HmcState& S, hipStream_t st, Force&& force) {
+  auto md = [&](int op, double step, int mode) -> int {
+    const hipError_t r = fdet_launch_hmc(op, S.hp, S.nprob, S.maxn, S.pi, S.F, S.ld, S.dU, step,
+                                         S.H0, S.dH, S.sstep, S.status, mode, st);
+    return r == hipSuccess ? FD_OK : fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(r));
+  };
+  int rc = force(0);
+  if (rc == FD_OK) rc = md(3, 0.0, 0);           // status of this force evaluation
+  if (rc == FD_OK) rc = md(2, 0.0, 0);           // H at the start
+  if (rc == FD_OK) rc = md(0, 0.5 * S.eps, 0);   // half kick
+  for (int n = 0; n < S.nsteps && rc == FD_OK; ++n) {
+    rc = md(1, S.eps, 0);                         // drift
+    if (rc == FD_OK) rc = force(n + 1);
+    if (rc == FD_OK) rc = md(3, 0.0, 1);
+    if (rc == FD_OK) rc = md(0, n + 1 < S.nsteps ? S.eps : 0.5 * S.eps, 0);
+  }
+  if (rc == FD_OK) rc = md(2, 0.0, 1);           // dH = H at the end - H at the start
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
 
 size_t fd_workspace_bytes(const fd_problem* p, int32_t nprob, const fd_options* o, int32_t what) {
   if (what == FD_WHAT_HMC) {
@@ -1146,79 +1240,33 @@ const char* fd_last_error(void) { return g_last_error.c_str(); }
 int fd_hmc_leapfrog(const fd_problem* p, int32_t nprob, const fd_options* o, double dU, double eps,
                     int32_t nsteps, double* pi, double* dH, void* ws, size_t ws_bytes,
                     int32_t* status, void* stream) {
-  if (!pi || !dH || !status) return fail(FD_ERR_INVALID_ARG, "pi, dH and status must be device pointers");
-  if (!(dU > 0.0) || !std::isfinite(dU)) return fail(FD_ERR_INVALID_ARG, "dU must be positive and finite");
-  if (!std::isfinite(eps)) return fail(FD_ERR_INVALID_ARG, "eps must be finite");
-  if (nsteps < 1) return fail(FD_ERR_INVALID_ARG, "nsteps must be >= 1");
-  if (!p || nprob < 1) return fail(FD_ERR_INVALID_ARG, "no problems given");
-  if (nprob > 65535) return fail(FD_ERR_INVALID_ARG, "at most 65535 fields per call");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
-    return fail(FD_ERR_INVALID_ARG, "fd_hmc_leapfrog prepares plans: call it outside stream capture");
-  fd_options o1{0, 0, 0, 0};
-  if (o) o1 = *o;
-  o1.flags &= ~FD_REUSE_E;
-  const size_t fw = fd_workspace_bytes(p, nprob, &o1, FD_WHAT_FORCE);
-  if (fw == 0) return FD_ERR_INVALID_ARG;
-  const HmcLayout L = hmc_layout(p, nprob, fw);
-  int rc = check_ws(ws, ws_bytes, L.total);
+  HmcState S;
+  fd_options o1;
+  int rc = hmc_setup(p, nprob, o, dU, eps, nsteps, pi, dH, ws, ws_bytes, status, stream, o1, S);
   if (rc != FD_OK) return rc;
-  char* base = static_cast<char*>(ws);
-  double* F = reinterpret_cast<double*>(base + L.f);
-  double* ld = reinterpret_cast<double*>(base + L.ld);
-  double* H0 = reinterpret_cast<double*>(base + L.h0);
-  int32_t* sstep = reinterpret_cast<int32_t*>(base + L.st);
-  fdet::HmcProb* hp = reinterpret_cast<fdet::HmcProb*>(base + L.hp);
-  std::vector<fdet::HmcProb> hh(nprob);
-  int64_t off = 0;
-  for (int i = 0; i < nprob; ++i) {
-    hh[i].phi = const_cast<double*>(p[i].phi);
-    hh[i].off = off;
-    hh[i].n = (int64_t)p[i].Nt * p[i].N;
-    off += hh[i].n;
-  }
-  hipError_t e = hipMemcpyAsync(hp, hh.data(), sizeof(fdet::HmcProb) * nprob, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
-  auto md = [&](int op, double h, int mode) -> int {
-    const hipError_t r = fdet_launch_hmc(op, hp, nprob, L.maxn, pi, F, ld, dU, h, H0, dH, sstep,
-                                         status, mode, st);
-    return r == hipSuccess ? FD_OK : fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(r));
-  };
-  // the first force evaluation also computes exp(+-dk K); later ones reuse it
+  // the first force evaluation also computes exp(+-dk K); the plan for the
+  // later ones, created after it (same layout), reuses it
   fd_plan* plan = nullptr;
-  rc = fd_plan_create(FD_WHAT_FORCE, p, nprob, &o1, ld, nullptr, F, nullptr, ws, fw, sstep, stream, &plan);
-  if (rc != FD_OK) return rc;
-  rc = fd_plan_launch(plan, stream);
+  rc = hmc_enqueue(S, static_cast<hipStream_t>(stream), [&](int n) -> int {
+    if (n > 0) return fd_plan_launch(plan, stream);
+    int r = fd_plan_create(FD_WHAT_FORCE, p, nprob, &o1, S.ld, nullptr, S.F, nullptr, ws,
+                           S.force_ws, S.sstep, stream, &plan);
+    if (r == FD_OK) r = fd_plan_launch(plan, stream);
+    fd_plan_destroy(plan);
+    plan = nullptr;
+    if (r != FD_OK) return r;
+    fd_options o2 = o1;
+    o2.flags |= FD_REUSE_E;
+    return fd_plan_create(FD_WHAT_FORCE, p, nprob, &o2, S.ld, nullptr, S.F, nullptr, ws,
+                          S.force_ws, S.sstep, stream, &plan);
+  });
   fd_plan_destroy(plan);
-  if (rc == FD_OK) rc = md(3, 0.0, 0);
-  if (rc == FD_OK) rc = md(2, 0.0, 0);          // H at the start
-  if (rc == FD_OK) rc = md(0, 0.5 * eps, 0);    // half kick
-  if (rc != FD_OK) return rc;
-  o1.flags |= FD_REUSE_E;
-  rc = fd_plan_create(FD_WHAT_FORCE, p, nprob, &o1, ld, nullptr, F, nullptr, ws, fw, sstep, stream, &plan);
-  if (rc != FD_OK) return rc;
-  for (int n = 0; n < nsteps && rc == FD_OK; ++n) {
-    rc = md(1, eps, 0);                          // drift
-    if (rc == FD_OK) rc = fd_plan_launch(plan, stream);
-    if (rc == FD_OK) rc = md(3, 0.0, 1);
-    if (rc == FD_OK) rc = md(0, n + 1 < nsteps ? eps : 0.5 * eps, 0);
-  }
-  fd_plan_destroy(plan);
-  if (rc == FD_OK) rc = md(2, 0.0, 1);          // dH = H at the end - H at the start
   return rc;
 }
 
 struct fd_hmc_plan {
+  HmcState S;
   fd_plan* force = nullptr;   // prepared force call with exp(+-dk K) already in ws
-  fdet::HmcProb* hp = nullptr;
-  int nprob = 0;
-  int64_t maxn = 0;
-  double dU = 0.0, eps = 0.0;
-  int nsteps = 0;
-  double *pi = nullptr, *dH = nullptr, *F = nullptr, *ld = nullptr, *H0 = nullptr;
-  int32_t *sstep = nullptr, *status = nullptr;
 };
 
 int fd_hmc_plan_create(const fd_problem* p, int32_t nprob, const fd_options* o, double dU,
@@ -1226,65 +1274,21 @@ int fd_hmc_plan_create(const fd_problem* p, int32_t nprob, const fd_options* o, 
                        size_t ws_bytes, int32_t* status, void* stream, fd_hmc_plan** plan) {
   if (!plan) return fail(FD_ERR_INVALID_ARG, "plan must not be NULL");
   *plan = nullptr;
-  if (!pi || !dH || !status) return fail(FD_ERR_INVALID_ARG, "pi, dH and status must be device pointers");
-  if (!(dU > 0.0) || !std::isfinite(dU)) return fail(FD_ERR_INVALID_ARG, "dU must be positive and finite");
-  if (!std::isfinite(eps)) return fail(FD_ERR_INVALID_ARG, "eps must be finite");
-  if (nsteps < 1) return fail(FD_ERR_INVALID_ARG, "nsteps must be >= 1");
-  if (!p || nprob < 1) return fail(FD_ERR_INVALID_ARG, "no problems given");
-  if (nprob > 65535) return fail(FD_ERR_INVALID_ARG, "at most 65535 fields per call");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(st, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
-    return fail(FD_ERR_INVALID_ARG, "create plans outside stream capture");
-  fd_options o1{0, 0, 0, 0};
-  if (o) o1 = *o;
-  o1.flags &= ~FD_REUSE_E;
-  const size_t fw = fd_workspace_bytes(p, nprob, &o1, FD_WHAT_FORCE);
-  if (fw == 0) return FD_ERR_INVALID_ARG;
-  const HmcLayout L = hmc_layout(p, nprob, fw);
-  int rc = check_ws(ws, ws_bytes, L.total);
-  if (rc != FD_OK) return rc;
-  char* base = static_cast<char*>(ws);
   fd_hmc_plan* h = new fd_hmc_plan;
-  h->F = reinterpret_cast<double*>(base + L.f);
-  h->ld = reinterpret_cast<double*>(base + L.ld);
-  h->H0 = reinterpret_cast<double*>(base + L.h0);
-  h->sstep = reinterpret_cast<int32_t*>(base + L.st);
-  h->hp = reinterpret_cast<fdet::HmcProb*>(base + L.hp);
-  h->nprob = nprob;
-  h->maxn = L.maxn;
-  h->dU = dU;
-  h->eps = eps;
-  h->nsteps = nsteps;
-  h->pi = pi;
-  h->dH = dH;
-  h->status = status;
-  std::vector<fdet::HmcProb> hh(nprob);
-  int64_t off = 0;
-  for (int i = 0; i < nprob; ++i) {
-    hh[i].phi = const_cast<double*>(p[i].phi);
-    hh[i].off = off;
-    hh[i].n = (int64_t)p[i].Nt * p[i].N;
-    off += hh[i].n;
-  }
-  hipError_t e = hipMemcpyAsync(h->hp, hh.data(), sizeof(fdet::HmcProb) * nprob,
-                                hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) {
-    delete h;
-    return fail(FD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
-  }
+  fd_options o1;
+  int rc = hmc_setup(p, nprob, o, dU, eps, nsteps, pi, dH, ws, ws_bytes, status, stream, o1, h->S);
   // one full force call now leaves exp(+-dk K) in the workspace; the plan
   // kept for the launches reuses it (K and dk fixed for the plan's lifetime)
   fd_plan* full = nullptr;
-  rc = fd_plan_create(FD_WHAT_FORCE, p, nprob, &o1, h->ld, nullptr, h->F, nullptr, ws, fw, h->sstep,
-                      stream, &full);
+  if (rc == FD_OK)
+    rc = fd_plan_create(FD_WHAT_FORCE, p, nprob, &o1, h->S.ld, nullptr, h->S.F, nullptr, ws,
+                        h->S.force_ws, h->S.sstep, stream, &full);
   if (rc == FD_OK) rc = fd_plan_launch(full, stream);
   fd_plan_destroy(full);
   if (rc == FD_OK) {
     o1.flags |= FD_REUSE_E;
-    rc = fd_plan_create(FD_WHAT_FORCE, p, nprob, &o1, h->ld, nullptr, h->F, nullptr, ws, fw,
-                        h->sstep, stream, &h->force);
+    rc = fd_plan_create(FD_WHAT_FORCE, p, nprob, &o1, h->S.ld, nullptr, h->S.F, nullptr, ws,
+                        h->S.force_ws, h->S.sstep, stream, &h->force);
   }
   if (rc != FD_OK) {
     delete h;
@@ -1296,24 +1300,8 @@ int fd_hmc_plan_create(const fd_problem* p, int32_t nprob, const fd_options* o, 
 
 int fd_hmc_plan_launch(const fd_hmc_plan* h, void* stream) {
   if (!h) return fail(FD_ERR_INVALID_ARG, "plan must not be NULL");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  auto md = [&](int op, double step, int mode) -> int {
-    const hipError_t r = fdet_launch_hmc(op, h->hp, h->nprob, h->maxn, h->pi, h->F, h->ld, h->dU,
-                                         step, h->H0, h->dH, h->sstep, h->status, mode, st);
-    return r == hipSuccess ? FD_OK : fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(r));
-  };
-  int rc = fd_plan_launch(h->force, stream);
-  if (rc == FD_OK) rc = md(3, 0.0, 0);
-  if (rc == FD_OK) rc = md(2, 0.0, 0);
-  if (rc == FD_OK) rc = md(0, 0.5 * h->eps, 0);
-  for (int n = 0; n < h->nsteps && rc == FD_OK; ++n) {
-    rc = md(1, h->eps, 0);
-    if (rc == FD_OK) rc = fd_plan_launch(h->force, stream);
-    if (rc == FD_OK) rc = md(3, 0.0, 1);
-    if (rc == FD_OK) rc = md(0, n + 1 < h->nsteps ? h->eps : 0.5 * h->eps, 0);
-  }
-  if (rc == FD_OK) rc = md(2, 0.0, 1);
-  return rc;
+  return hmc_enqueue(h->S, static_cast<hipStream_t>(stream),
+                     [&](int) -> int { return fd_plan_launch(h->force, stream); });
 }
 
 void fd_hmc_plan_destroy(fd_hmc_plan* h) {
