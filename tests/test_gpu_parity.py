@@ -496,6 +496,34 @@ def test_force_batched_grouped_by_8(fd):
 
 
 # ---------------------------------------------------------------------------
+# every size class and its edges
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [32, 33, 64, 65, 80, 81, 90, 96, 97, 128, 129])
+def test_size_class_boundaries(fd, N):
+    """The kernels are instantiated per size class (the smallest of 32, 64,
+    80, 96, 128 and 512 that holds N): log det, G and force at each class's
+    edges for a generic symmetric hopping matrix (random, spectral radius 3),
+    against the oracle; the G and force bars scale with max |G| as for the
+    largest test."""
+    rng = np.random.default_rng(500 + N)
+    A = rng.normal(size=(N, N))
+    K = (A + A.T) / 2
+    K *= 3.0 / np.abs(np.linalg.eigvalsh(K)).max()
+    Nt, beta = 16, 4.0
+    dk = beta / Nt            # s dk rho = 3 at s = 4, c dk rho = 6 at c = 8
+    phi = sample_phi(600 + N, Nt, N, dk, 3.0)
+    ld, G = gpu_greens(fd, K, phi, dk, s=4, segments=2)
+    lo, Go = O.stabilised_logdet_greens(K, dk, phi)
+    scale = max(1.0, np.abs(Go).max())
+    check_ld(ld, lo)
+    check_G(G, Go, tol=TOL_G * scale)
+    F = fd.force(to_dev(K), to_dev(phi), dk, s=4, checkpoint=8).cpu().numpy()
+    Fo = O.stabilised_force(K, dk, phi)
+    assert np.abs(F - Fo).max() <= TOL_F * scale
+
+
+# ---------------------------------------------------------------------------
 # edge case: one site (N = 1), every B_t a number
 # ---------------------------------------------------------------------------
 
