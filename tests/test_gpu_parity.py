@@ -523,6 +523,23 @@ def test_size_class_boundaries(fd, N):
     assert np.abs(F - Fo).max() <= TOL_F * scale
 
 
+@pytest.mark.parametrize("N", [257, 511])
+def test_large_class_ragged(fd, N):
+    """The blocked (N > 128) class past its first panel boundaries and one
+    row short of the largest size: log det and G of a generic hopping
+    matrix against the oracle (bar scaled by max |G|)."""
+    rng = np.random.default_rng(500 + N)
+    A = rng.normal(size=(N, N))
+    K = (A + A.T) / 2
+    K *= 3.0 / np.abs(np.linalg.eigvalsh(K)).max()
+    Nt, dk = 16, 0.25
+    phi = sample_phi(600 + N, Nt, N, dk, 3.0)
+    ld, G = gpu_greens(fd, K, phi, dk, s=4, segments=2)
+    lo, Go = O.stabilised_logdet_greens(K, dk, phi)
+    check_ld(ld, lo)
+    check_G(G, Go, tol=TOL_G * max(1.0, np.abs(Go).max()))
+
+
 # ---------------------------------------------------------------------------
 # edge case: one site (N = 1), every B_t a number
 # ---------------------------------------------------------------------------
