@@ -343,6 +343,16 @@ def main():
                           "phases_ms": phase_split(lambda: fd.force(
                               Kf, pf, wf.dk, s=wf.s, checkpoint=c, check=False, ws=wsf))}
             print(f"[bench] force {label}: {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
+        # the adjoint force as a prepared call replayed from a graph (E computed once)
+        trf = fd.Trajectory(Kf, pf, wf.dk, s=wf.s, checkpoint=wf.c)
+        trf.replay()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(10):
+            trf.replay()
+        torch.cuda.synchronize()
+        out["adjoint_c16"]["graph_ms"] = (time.perf_counter() - a) / 10 * 1e3
+        del trf
         out["workload"] = "force_L8: honeycomb L=8 (N=128), Nt=256, beta=32, U=3, s=8"
         out["adjoint_vs_plain"] = out["adjoint_c16"]["force_evals_per_s"] / out["plain_c1"]["force_evals_per_s"]
         result["force"] = out
