@@ -1,0 +1,138 @@
+// Host-only check of the work-item planner (no GPU): the host side of the
+// library is compiled with the kernel launchers stubbed out, plans are built
+// against a fake workspace base for named shapes and for random batches of
+// every kind, and every launch is checked: items of one launch share no
+// scratch and never write a slot another item of it reads; every workspace
+// pointer an item carries (E, E^-1, UDV slots, scratch) lies inside the
+// workspace that fd_workspace_bytes sizes; slice ranges stay inside [0, N_t].
+// Prints one line per plan and "bad <count>" last; exits nonzero on a finding.
+#include "../paper_2604_02130_amd/csrc/fdet_abi.cpp"
+#include <set>
+#include <random>
+#include <map>
+extern "C" hipError_t fdet_launch_items(int, int, const fdet::Prob*, const fdet::Item*, int, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_init_status(const fdet::Prob*, int, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_trace(int, const double*, const double*, double*, double*, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_diag_response(int, int, const double*, const double*, const double*, double*, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_hmc(int, const fdet::HmcProb*, int, int64_t, double*, const double*, const double*, double, double, double*, double*, const int32_t*, int32_t*, int, hipStream_t) { return hipSuccess; }
+
+static int check(const char* name, std::vector<fd_problem> p, fd_options oo, int what, bool verbose) {
+  Opts o = resolve(&oo, p.data(), (int)p.size(), what);
+  Plan pl;
+  build_plan(p.data(), (int)p.size(), o, what, (char*)0x10000000, pl);
+  int bad = 0;
+  // every workspace pointer of every item stays inside [base + desc, base + total)
+  {
+    const char* lo = (const char*)0x10000000 + align_up(pl.desc_bytes);
+    const char* hi = (const char*)0x10000000 + pl.total;
+    auto in = [&](const void* p, size_t bytes) { return (const char*)p >= lo && (const char*)p + bytes <= hi; };
+    for (auto& P : pl.probs) {
+      const size_t eb = (size_t)P.Np * P.Np * sizeof(double);
+      if (!in(P.E, eb)) { printf(" [E out]"); bad++; }
+      if (P.Einv && !in(P.Einv, eb)) { printf(" [Einv out]"); bad++; }
+    }
+    for (auto& ph : pl.phases) for (auto& it : ph) {
+      const Prob& P = pl.probs[it.prob];
+      const size_t ub = (size_t)4 * P.Np * P.Np * sizeof(double) + (size_t)P.Np * sizeof(double);
+      for (const Udv* u : {&it.a, &it.b, &it.o}) {
+        if (!u->X) continue;
+        if (!in(u->X, ub) || u->T != u->X + (size_t)2 * P.Np * P.Np || u->D != u->X + (size_t)4 * P.Np * P.Np) { printf(" [udv out]"); bad++; }
+      }
+      if (it.scr && !in(it.scr, scratch_bytes(P.Np))) { printf(" [scr out]"); bad++; }
+      if (it.t0 < 0 || it.t1 < it.t0 || it.t1 > P.Nt || it.nb < 0 || it.nb > P.Nt) { printf(" [rows out]"); bad++; }
+      if (it.kind != fdet::IK_EXPM && it.kind != fdet::IK_EXPORT && it.kind != fdet::IK_CLOSE && !it.scr) { printf(" [no scr]"); bad++; }
+    }
+    if (pl.total > fd_workspace_bytes(p.data(), (int)p.size(), &oo, what)) { printf(" [total > sized]"); bad++; }
+  }
+  if (what == FD_WHAT_FORCE) printf("%s: schedule g=%d ", name, force_schedule(p.data(), (int)p.size(), o));
+  else printf("%s: ", name);
+  printf("phases:");
+  for (auto& ph : pl.phases) {
+    printf(" %s%zu", ph.empty() ? "?" : (const char*[]){"E","C","M","Z","F","X"}[ph[0].kind], ph.size());
+    std::map<double*, int> scr, wr;
+    std::set<double*> rd;
+    for (auto& it : ph) {
+      if (it.scr && ++scr[it.scr] > 1 && !(it.kind == fdet::IK_CHAIN && it.t0 == it.t1)) { printf(" [shared scr]"); bad++; }
+      if (it.kind == fdet::IK_COMBINE) {
+        double* w = it.o.X ? it.o.X : it.a.X;
+        if (++wr[w] > 1) { printf(" [double write]"); bad++; }
+        rd.insert(it.a.X); rd.insert(it.b.X);
+      } else if (it.kind == fdet::IK_CHAIN) {
+        if (++wr[it.a.X] > 1) { printf(" [double write chain]"); bad++; }
+      } else if (it.kind == fdet::IK_FORCE || it.kind == fdet::IK_CLOSE) {
+        rd.insert(it.a.X); if (it.b.X) rd.insert(it.b.X);
+      }
+    }
+    if (ph[0].kind == fdet::IK_COMBINE) {
+      std::map<double*, int> writer;
+      for (size_t x = 0; x < ph.size(); ++x) writer[ph[x].o.X ? ph[x].o.X : ph[x].a.X] = (int)x;
+      for (size_t x = 0; x < ph.size(); ++x)
+        for (double* r : {ph[x].a.X, ph[x].b.X})
+          if (writer.count(r) && writer[r] != (int)x) { printf(" [write/read race]"); bad++; }
+    }
+    if (ph[0].kind == fdet::IK_FORCE && verbose) {
+      int nl = 0;
+      for (auto& it : ph) if (it.flags & fdet::IF_OUT_LOGDET) nl++;
+      printf(" (logdet items %d)", nl);
+    }
+  }
+  printf("  %s\n", bad ? "BAD" : "ok");
+  return bad;
+}
+
+int main() {
+  static double dummy[8];
+  auto prob = [&](int N, int Nt, double dk) { fd_problem q; q.N = N; q.Nt = Nt; q.dk = dk; q.K = dummy; q.phi = dummy; return q; };
+  int bad = 0;
+  fd_options o{}; 
+  o = fd_options{8, 16, 0, 0};
+  bad += check("force_L8 (N128 Nt256 c16)", {prob(128, 256, 0.125)}, o, FD_WHAT_FORCE, true);
+  std::vector<fd_problem> hmc(32, prob(512, 512, 0.125));
+  o = fd_options{16, 16, 0, 0};
+  bad += check("hmc 32x(N512 Nt512 c16)", hmc, o, FD_WHAT_FORCE, true);
+  bad += check("L16 test 2x", std::vector<fd_problem>(2, prob(512, 512, 0.125)), o, FD_WHAT_FORCE, true);
+  for (int nt : {300, 301, 256}) {
+    o = fd_options{4, 1, 0, 0};
+    char nm[64]; snprintf(nm, 64, "grouped Nt=%d c=1", nt);
+    bad += check(nm, {prob(8, nt, 0.1)}, o, FD_WHAT_FORCE, true);
+    o.flags = FD_FORCE_SCANS;
+    snprintf(nm, 64, "grouped Nt=%d c=1 SCANS", nt);
+    bad += check(nm, {prob(8, nt, 0.1)}, o, FD_WHAT_FORCE, true);
+  }
+  o = fd_options{4, 1, 0, 0};
+  bad += check("6x100 c=1", std::vector<fd_problem>(6, prob(8, 100, 0.1)), o, FD_WHAT_FORCE, true);
+  for (int nt = 1; nt <= 70; ++nt) for (int c : {1, 3, 8, 16}) {
+    o = fd_options{4, c, 0, 0};
+    char nm[64]; snprintf(nm, 64, "Nt=%d c=%d", nt, c);
+    bad += check(nm, {prob(18, nt, 0.1)}, o, FD_WHAT_FORCE, false);
+    o.flags = FD_FORCE_SCANS;
+    bad += check(nm, {prob(18, nt, 0.1)}, o, FD_WHAT_FORCE, false);
+  }
+  for (int ns_nt : {1, 2, 3, 5, 8, 13, 16, 40, 100, 256}) for (int s : {1, 4, 8}) {
+    o = fd_options{s, 1, 0, 0};
+    char nm[64]; snprintf(nm, 64, "det N72 Nt=%d s=%d", ns_nt, s);
+    bad += check(nm, {prob(72, ns_nt, 0.1)}, o, FD_WHAT_LOGDET, false);
+    bad += check(nm, std::vector<fd_problem>(7, prob(40, ns_nt, 0.1)), o, FD_WHAT_GREENS, false);
+  }
+  // random batches of every kind
+  {
+    std::mt19937 g(12345);
+    auto U = [&](int a, int b) { return std::uniform_int_distribution<int>(a, b)(g); };
+    int nrun = 0;
+    for (int trial = 0; trial < 400; ++trial) {
+      const int nprob = U(1, 12);
+      std::vector<fd_problem> ps;
+      const int big = U(0, 3) == 0;
+      for (int i = 0; i < nprob; ++i) ps.push_back(prob(big ? U(1, 512) : U(1, 128), U(1, 300), 0.05));
+      const int what = U(0, 3);
+      fd_options oo{std::vector<int>{1, 2, 4, 8, 16}[U(0, 4)], U(1, 32), U(0, 1) ? 0 : U(1, 40), U(0, 3) == 0 ? FD_FORCE_SCANS : 0};
+      char nm[64]; snprintf(nm, 64, "fuzz %d what=%d nprob=%d", trial, what, nprob);
+      const int b = check(nm, ps, oo, what, false);
+      bad += b;
+      ++nrun;
+    }
+    printf("fuzz runs %d\n", nrun);
+  }
+  printf("bad %d\n", bad);
+  return bad != 0;
+}
