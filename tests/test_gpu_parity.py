@@ -523,6 +523,34 @@ def test_size_class_boundaries(fd, N):
     assert np.abs(F - Fo).max() <= TOL_F * scale
 
 
+def test_batched_every_small_class_in_one_launch(fd):
+    """One batch whose largest member (N = 128) sets the launch class, with
+    members of every smaller class (N = 20, 50, 72, 90): each runs its own
+    class's code inside the class-128 kernels.  log det, G and force against
+    the oracle."""
+    import torch
+    probs, refs, frefs = [], [], []
+    for i, N in enumerate((90, 20, 128, 50, 72)):
+        rng = np.random.default_rng(700 + N)
+        A = rng.normal(size=(N, N))
+        K = (A + A.T) / 2
+        K *= 3.0 / np.abs(np.linalg.eigvalsh(K)).max()
+        Nt, dk = 16, 0.25
+        phi = sample_phi(800 + N, Nt, N, dk, 3.0)
+        probs.append((to_dev(K), to_dev(phi), dk))
+        refs.append(O.stabilised_logdet_greens(K, dk, phi))
+        frefs.append(O.stabilised_force(K, dk, phi))
+    ld, Gs = fd.greens_batched(probs, s=4, segments=2)
+    ld = ld.cpu().numpy()
+    for i, (lo, Go) in enumerate(refs):
+        scale = max(1.0, np.abs(Go).max())
+        check_ld(ld[i], lo)
+        check_G(Gs[i].cpu().numpy(), Go, tol=TOL_G * scale)
+    Fs, _ = fd.force_batched(probs, s=4, checkpoint=8)
+    for F, Fo, (_, Go) in zip(Fs, frefs, refs):
+        assert np.abs(F.cpu().numpy() - Fo).max() <= TOL_F * max(1.0, np.abs(Go).max())
+
+
 @pytest.mark.parametrize("N", [257, 511])
 def test_large_class_ragged(fd, N):
     """The blocked (N > 128) class past its first panel boundaries and one
