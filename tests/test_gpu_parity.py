@@ -523,14 +523,14 @@ def test_size_class_boundaries(fd, N):
     assert np.abs(F - Fo).max() <= TOL_F * scale
 
 
-def test_batched_every_small_class_in_one_launch(fd):
-    """One batch whose largest member (N = 128) sets the launch class, with
-    members of every smaller class (N = 20, 50, 72, 90): each runs its own
-    class's code inside the class-128 kernels.  log det, G and force against
-    the oracle."""
-    import torch
+@pytest.mark.parametrize("sizes", [(90, 20, 128, 50, 72), (90, 20, 50, 72), (72, 20, 50), (50, 20)])
+def test_batched_every_small_class_in_one_launch(fd, sizes):
+    """One batch whose largest member sets the launch class (128, 96, 80,
+    64), with members of every smaller class: each runs its own class's code
+    inside the larger class's kernels.  log det, G and force against the
+    oracle."""
     probs, refs, frefs = [], [], []
-    for i, N in enumerate((90, 20, 128, 50, 72)):
+    for i, N in enumerate(sizes):
         rng = np.random.default_rng(700 + N)
         A = rng.normal(size=(N, N))
         K = (A + A.T) / 2
