@@ -479,6 +479,32 @@ def main():
             if int(st_h.min()) < 0:
                 raise SystemExit(f"HMC step status {st_h.tolist()}")
             hflops = sum(alg_force_flops(wb.N, wb.Nt, wb.s, wb.c) for wb in hb)
+            # per-phase model FLOP rates of the same step (one eager call, HIP
+            # events around each launch): chains of c slices with one QR per s,
+            # stabilised products, and per checkpoint item a product, a close
+            # with G and the carried slices (two real x complex products each)
+            del traj
+            hph = phase_split(lambda: fd.force_batched(hprobs, s=hb[0].s, checkpoint=hb[0].c,
+                                                       check=False))
+            Nh, Nth, ch, sh = hb[0].N, hb[0].Nt, hb[0].c, hb[0].s
+            nch = (Nth + ch - 1) // ch
+            model = {
+                "chain": len(hb) * nch * chain_flops(Nh, ch, sh),
+                "force": len(hb) * (nch * (combine_flops(Nh) + close_flops(Nh))
+                                    + (Nth - nch) * 8.0 * Nh ** 3),
+            }
+            hphases = {}
+            for name, nitems, ms in hph:
+                rec = hphases.setdefault(name, {"launches": 0, "items": 0, "ms": 0.0})
+                rec["launches"] += 1
+                rec["items"] += nitems
+                rec["ms"] += ms
+            model["combine"] = hphases.get("combine", {"items": 0})["items"] * combine_flops(Nh)
+            for name, rec in hphases.items():
+                if name in model and rec["ms"] > 0:
+                    rate = model[name] / (rec["ms"] * 1e-3)
+                    rec["model_tflop_s"] = rate / 1e12
+                    rec["frac_fp64_mfma_peak"] = rate / PEAK_FP64_MFMA
             result["hmc_step"] = {
                 "workload": "32 fields, honeycomb L=16 (N=512), Nt=512, beta=64, U=3, s=16, "
                             "c=16; log det, G and full force per field in one graph replay",
@@ -487,9 +513,9 @@ def main():
                 "alg_tflop_s": hflops / dth / 1e12,
                 "fp64_mfma_pct_peak": 100.0 * hflops / dth / PEAK_FP64_MFMA,
                 "setup_s": setup,
+                "phases_eager": hphases,
             }
             print(f"[bench] HMC step L16 x32: {dth:.3f} s", file=sys.stderr, flush=True)
-            del traj
 
     print(json.dumps(result), flush=True)
 
