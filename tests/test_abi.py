@@ -235,3 +235,27 @@ def test_hmc_plan_argument_checks(lib):
     assert not h.value
     assert lib.fd_hmc_plan_launch(None, None) == fd.FD_ERR_INVALID_ARG
     lib.fd_hmc_plan_destroy(None)
+
+
+def test_header_is_plain_c(lib, tmp_path):
+    """include/fdet.h compiles as strict C99 (no C++ in the boundary), and a C
+    program links against the library's exported names."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("needs gcc")
+    src = tmp_path / "use.c"
+    src.write_text('#include "fdet.h"\n'
+                   "int main(void) {\n"
+                   "  fd_options o = {0, 0, 0, 0};\n"
+                   "  (void)o;\n"
+                   "  return fd_response_trace_workspace_bytes(0) == 0 ? 0 : 1;\n"
+                   "}\n")
+    inc = os.path.join(ROOT, "include")
+    res = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", inc,
+                          "-o", str(tmp_path / "use"), str(src), fd.LIB_PATH,
+                          f"-Wl,-rpath,{os.path.dirname(fd.LIB_PATH)}"],
+                         capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr[-2000:]
+    run = subprocess.run([str(tmp_path / "use")], capture_output=True, text=True, timeout=60)
+    assert run.returncode == 0, run.stderr[-2000:]
