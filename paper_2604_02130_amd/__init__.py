@@ -363,15 +363,17 @@ def hmc_leapfrog(problems, pi, dU, eps, nsteps, s=0, checkpoint=0, flags=0, chec
 
 
 def hmc_trajectory(problems, dU, eps, nsteps, rng, **kw):
-    """Momenta drawn from N(0, 1) with the numpy Generator `rng`, one leapfrog
-    trajectory, and the Metropolis step: field i keeps its new value with
-    probability min(1, exp(-dH_i)), else gets its old one back.  Returns
-    (dH as numpy array, accepted flags)."""
+    """Momenta drawn from N(0, 1) with the numpy Generator `rng` (one draw of
+    all fields' momenta, then one uniform per field: the same sequence as
+    HmcPlan.trajectory), one leapfrog trajectory, and the Metropolis step:
+    field i keeps its new value with probability min(1, exp(-dH_i)), else
+    gets its old one back.  Returns (dH as numpy array, accepted flags)."""
     torch = _torch()
     old = [phi.clone() for _, phi, _ in problems]
-    pis = [torch.from_numpy(rng.standard_normal(tuple(phi.shape))).to(phi.device)
-           for _, phi, _ in problems]
-    dH = hmc_leapfrog(problems, pis, dU, eps, nsteps, **kw).cpu().numpy()
+    # one flat draw in the layout of force_batched, as HmcPlan.trajectory draws
+    total = sum(phi.numel() for _, phi, _ in problems)
+    pi = torch.from_numpy(rng.standard_normal(total)).to(problems[0][1].device)
+    dH = hmc_leapfrog(problems, pi, dU, eps, nsteps, **kw).cpu().numpy()
     return dH, _metropolis(problems, old, dH, rng)
 
 

@@ -752,6 +752,12 @@ def test_hmc_plan_and_graph_replays_match_leapfrog(fd):
         plan.replay()
         check()
         del junk
+    # the one-call form draws the same momenta from the same generator state
+    reset()
+    dH1, acc1 = fd.hmc_trajectory(probs, 0.75, 0.05, 3, np.random.default_rng(11), s=4, checkpoint=8)
+    reset()
+    dH2, acc2 = plan.trajectory(np.random.default_rng(11))
+    assert np.array_equal(dH1, dH2) and np.array_equal(acc1, acc2)
     # the step as a whole: draw, run, accept; dH against the oracle's
     # leapfrog from the same momenta (a large dH is physics: the trajectory of
     # field 0 passes close to a zero of det M)
