@@ -278,7 +278,9 @@ int fd_diag_response(int32_t Nt, int32_t N, const double *force, const double *f
 /* Text for a return/status code; the last error message of this thread.      */
 const char *fd_strerror(int code);
 const char *fd_last_error(void);
-/* Library version string.                                                    */
+/* Library version string: "fdet <version> (gfx950) src <digest>", the digest
+ * being the first 16 hex digits of a sha256 over the library's source files
+ * (the binding compares it with the sources it ships beside).               */
 const char *fd_version(void);
 
 /* Diagnostics: after fd_profile_start, every kernel phase launched by this

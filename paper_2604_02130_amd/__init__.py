@@ -64,6 +64,20 @@ class FdError(RuntimeError):
 _lib = None
 
 
+def _check_sources(ver: str, path: str):
+    """The library carries a digest of the sources it was built from; refuse
+    one built from other sources than those next to this file."""
+    from . import build as _build
+    if not os.path.isdir(_build.CSRC):
+        return
+    want = _build.source_digest()
+    got = ver.rsplit(" ", 1)[-1] if " src " in ver else "none"
+    if got != want:
+        raise FdError(FD_ERR_UNSUPPORTED,
+                      f"{path} was built from other sources (src {got}, this tree {want}); "
+                      "rebuild with `python -m paper_2604_02130_amd.build`")
+
+
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     """Load libfdet.so (raises if it has not been built)."""
     global _lib
@@ -73,6 +87,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         raise FdError(FD_ERR_UNSUPPORTED,
                       f"{path} is not built; run `python -m paper_2604_02130_amd.build`")
     lib = ctypes.CDLL(path)
+    lib.fd_version.argtypes = []
+    lib.fd_version.restype = ctypes.c_char_p
+    _check_sources(lib.fd_version().decode(), path)
     P = ctypes.POINTER(FdProblem)
     O = ctypes.POINTER(FdOptions)
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t

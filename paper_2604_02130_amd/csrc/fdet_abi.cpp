@@ -17,8 +17,17 @@
 #include "fdet_hmc.h"
 #include "fdet_plan.h"
 
-extern "C" hipError_t fdet_launch_items(int maxn, int kind, const fdet::Prob* probs,
-                                        const fdet::Item* items, int nitems, hipStream_t st);
+#define FDET_DECLARE_CLASS(NC)                                                          \
+  extern "C" hipError_t fdet_launch_items_##NC(int kind, const fdet::Prob* probs,        \
+                                               const fdet::Item* items, int nitems,      \
+                                               hipStream_t st);
+FDET_DECLARE_CLASS(32)
+FDET_DECLARE_CLASS(64)
+FDET_DECLARE_CLASS(80)
+FDET_DECLARE_CLASS(96)
+FDET_DECLARE_CLASS(128)
+FDET_DECLARE_CLASS(512)
+#undef FDET_DECLARE_CLASS
 extern "C" hipError_t fdet_launch_init_status(const fdet::Prob* probs, int nprob, hipStream_t st);
 extern "C" hipError_t fdet_launch_hmc(int op, const fdet::HmcProb* hp, int nprob, int64_t maxn,
                                       double* pi, const double* force, const double* logdet,
@@ -35,6 +44,20 @@ namespace {
 using fdet::Item;
 using fdet::Prob;
 using fdet::Udv;
+
+// Launch of one phase in the size class of its largest problem (each class
+// is a separate kernel object; items smaller than the class run their own
+// class's code inside it).
+hipError_t fdet_launch_items(int maxn, int kind, const Prob* probs, const Item* items, int nitems,
+                             hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  if (maxn <= 32) return fdet_launch_items_32(kind, probs, items, nitems, st);
+  if (maxn <= 64) return fdet_launch_items_64(kind, probs, items, nitems, st);
+  if (maxn <= 80) return fdet_launch_items_80(kind, probs, items, nitems, st);
+  if (maxn <= 96) return fdet_launch_items_96(kind, probs, items, nitems, st);
+  if (maxn <= 128) return fdet_launch_items_128(kind, probs, items, nitems, st);
+  return fdet_launch_items_512(kind, probs, items, nitems, st);
+}
 
 thread_local std::string g_last_error;
 
@@ -1343,7 +1366,10 @@ int fd_diag_response(int32_t Nt, int32_t N, const double* force, const double* f
   return FD_OK;
 }
 
-const char* fd_version(void) { return "fdet 0.1.0 (gfx950)"; }
+#ifndef FDET_SRC_DIGEST
+#define FDET_SRC_DIGEST "unknown"
+#endif
+const char* fd_version(void) { return "fdet 0.2.0 (gfx950) src " FDET_SRC_DIGEST; }
 
 int fd_profile_start(void) {
   for (auto& r : g_prof) {

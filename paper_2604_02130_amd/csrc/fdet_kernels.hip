@@ -725,10 +725,12 @@ FDET_KERNEL(k_close, do_close<C>(P, it.a, cmat_at(it.scr, P.Np),
 FDET_KERNEL(k_force, do_force<C>(P, it, S))
 FDET_KERNEL(k_export, do_export<C>(P, it, S))
 
+#if FDET_NC == 32
 __global__ void k_init_status(const Prob* __restrict__ probs, int nprob) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nprob && probs[i].status) *probs[i].status = 0;
 }
+#endif
 
 }  // namespace fdet
 
@@ -750,18 +752,25 @@ static hipError_t launch_kind(int kind, const fdet::Prob* probs, const fdet::Ite
   return hipGetLastError();
 }
 
-extern "C" hipError_t fdet_launch_items(int maxn, int kind, const fdet::Prob* probs,
-                                        const fdet::Item* items, int nitems, hipStream_t st) {
+// This file is compiled once per launch class (-DFDET_NC=32, 64, 80, 96, 128
+// or 512) so that the classes build in parallel; the host dispatches on the
+// largest N of a launch (fdet_launch_items in fdet_abi.cpp).
+#ifndef FDET_NC
+#error "compile with -DFDET_NC=<launch class>"
+#endif
+#define FDET_CAT2(a, b) a##b
+#define FDET_CAT(a, b) FDET_CAT2(a, b)
+
+extern "C" hipError_t FDET_CAT(fdet_launch_items_, FDET_NC)(int kind, const fdet::Prob* probs,
+                                                          const fdet::Item* items, int nitems,
+                                                          hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
-  if (maxn <= 32) return launch_kind<32>(kind, probs, items, nitems, st);
-  if (maxn <= 64) return launch_kind<64>(kind, probs, items, nitems, st);
-  if (maxn <= 80) return launch_kind<80>(kind, probs, items, nitems, st);
-  if (maxn <= 96) return launch_kind<96>(kind, probs, items, nitems, st);
-  if (maxn <= 128) return launch_kind<128>(kind, probs, items, nitems, st);
-  return launch_kind<512>(kind, probs, items, nitems, st);
+  return launch_kind<FDET_NC>(kind, probs, items, nitems, st);
 }
 
+#if FDET_NC == 32
 extern "C" hipError_t fdet_launch_init_status(const fdet::Prob* probs, int nprob, hipStream_t st) {
   hipLaunchKernelGGL(fdet::k_init_status, dim3((nprob + 255) / 256), dim3(256), 0, st, probs, nprob);
   return hipGetLastError();
 }
+#endif

@@ -10,7 +10,12 @@
 #include <set>
 #include <random>
 #include <map>
-extern "C" hipError_t fdet_launch_items(int, int, const fdet::Prob*, const fdet::Item*, int, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_items_32(int, const fdet::Prob*, const fdet::Item*, int, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_items_64(int, const fdet::Prob*, const fdet::Item*, int, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_items_80(int, const fdet::Prob*, const fdet::Item*, int, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_items_96(int, const fdet::Prob*, const fdet::Item*, int, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_items_128(int, const fdet::Prob*, const fdet::Item*, int, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_items_512(int, const fdet::Prob*, const fdet::Item*, int, hipStream_t) { return hipSuccess; }
 extern "C" hipError_t fdet_launch_init_status(const fdet::Prob*, int, hipStream_t) { return hipSuccess; }
 extern "C" hipError_t fdet_launch_trace(int, const double*, const double*, double*, double*, hipStream_t) { return hipSuccess; }
 extern "C" hipError_t fdet_launch_diag_response(int, int, const double*, const double*, const double*, double*, hipStream_t) { return hipSuccess; }
