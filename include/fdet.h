@@ -177,6 +177,13 @@ int fd_plan_create(int32_t what, const fd_problem *p, int32_t nprob, const fd_op
                    size_t ws_bytes, int32_t *status, void *stream, fd_plan **plan);
 int fd_plan_launch(const fd_plan *plan, void *stream);
 void fd_plan_destroy(fd_plan *plan);
+/* Work units a plan gave each problem: for FD_WHAT_LOGDET / _GREENS the time
+ * segments (independent slice ranges combined by stabilised products), for
+ * FD_WHAT_FORCE the checkpoint intervals.  Writes min(n, nprob) int32 to the
+ * host array seg (may be NULL) and returns nprob, or FD_ERR_INVALID_ARG for a
+ * NULL plan.  A single call with options.segments set to a problem's value
+ * repeats that problem's part of a batched plan work item for work item.    */
+int fd_plan_segments(const fd_plan *plan, int32_t *seg, int32_t n);
 
 /* Autotuning of the stabilisation interval s (Sec. 9 leaves its choice to
  * the conditioning: candidates 4, 8, 16 within s*dk*radius(K) <= 6, radius

@@ -39,7 +39,7 @@ SYMBOLS = (
     "fd_plan_create", "fd_plan_launch", "fd_plan_destroy", "fd_autotune", "fd_tune_save",
     "fd_tune_load", "fd_tune_clear", "fd_response_trace_workspace_bytes", "fd_response_trace",
     "fd_hmc_leapfrog", "fd_diag_response", "fd_hmc_plan_create", "fd_hmc_plan_launch",
-    "fd_hmc_plan_destroy",
+    "fd_hmc_plan_destroy", "fd_plan_segments",
 )
 
 PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export"}
@@ -86,6 +86,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise FdError(FD_ERR_UNSUPPORTED,
                       f"{path} is not built; run `python -m paper_2604_02130_amd.build`")
+    from . import build as _build
+    if os.path.isdir(_build.CSRC):
+        _check_sources(f"libfdet src {_build.library_digest(path)}", path)
     lib = ctypes.CDLL(path)
     lib.fd_version.argtypes = []
     lib.fd_version.restype = ctypes.c_char_p
@@ -123,6 +126,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fd_plan_launch.restype = ctypes.c_int
     lib.fd_plan_destroy.argtypes = [vp]
     lib.fd_plan_destroy.restype = None
+    lib.fd_plan_segments.argtypes = [vp, vp, i32]
+    lib.fd_plan_segments.restype = ctypes.c_int
     lib.fd_autotune.argtypes = [i32, P, i32, O, vp, O, ctypes.POINTER(ctypes.c_float)]
     lib.fd_autotune.restype = ctypes.c_int
     lib.fd_tune_save.argtypes = [ctypes.c_char_p]
@@ -686,6 +691,13 @@ class Plan:
     def launch(self):
         """Enqueue the plan's kernels on the current stream."""
         _check(self.lib.fd_plan_launch(self.handle, _stream()))
+
+    def segments(self):
+        """Per problem: time segments (logdet / greens) or checkpoint
+        intervals (force) of this plan."""
+        buf = (ctypes.c_int32 * self.n)()
+        _check(min(0, self.lib.fd_plan_segments(self.handle, buf, self.n)))
+        return [int(v) for v in buf]
 
     def greens(self):
         """[G_i] views (greens, or force with want_g); [] otherwise."""

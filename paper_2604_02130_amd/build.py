@@ -51,6 +51,24 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
+def library_digest(path: str = LIB) -> str | None:
+    """The source digest compiled into a built library (read from the file,
+    without loading it), or None."""
+    import re
+    try:
+        with open(path, "rb") as f:
+            data = f.read()
+    except OSError:
+        return None
+    m = re.search(rb"fdet \d+\.\d+\.\d+ \(gfx950\) src ([0-9a-f]{16})", data)
+    return m.group(1).decode() if m else None
+
+
+def is_stale(path: str = LIB) -> bool:
+    """True if the library is missing or was built from other sources."""
+    return library_digest(path) != source_digest()
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):

@@ -212,6 +212,7 @@ struct Plan {
   size_t desc_bytes = 0;
   size_t total = 0;
   int maxN = 0;
+  std::vector<int> units;   // per problem: time segments (det / G) or checkpoint intervals (force)
 };
 
 struct Cursor {
@@ -444,6 +445,7 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   const bool force = what == FD_WHAT_FORCE;
   std::vector<int> nseg = plan_segments(p, nprob, o), nck(nprob);
   const int sgroup = force ? force_schedule(p, nprob, o) : 1;
+  pl.units.assign(nprob, 0);
   int maxlev = 0;
   size_t nforce = 0;
   for (int i = 0; i < nprob; ++i) {
@@ -465,11 +467,13 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
       // products, and 2 nc force items at most (forward / backward halves)
       nitems += 2 + (size_t)nc + 1 + prods + 2 * (size_t)nc;
       nforce += nc;
+      pl.units[i] = nc;
     } else {
       int lev = 0;
       while ((1 << lev) < nseg[i]) ++lev;
       maxlev = std::max(maxlev, lev);
       nitems += 1 + nseg[i] + nseg[i] + 1;
+      pl.units[i] = nseg[i];
     }
   }
   pl.desc_bytes = align_up(sizeof(Prob) * nprob) + align_up(sizeof(Item) * nitems);
@@ -1085,6 +1089,14 @@ int fd_plan_launch(const fd_plan* plan, void* stream) {
 }
 
 void fd_plan_destroy(fd_plan* plan) { delete plan; }
+
+int fd_plan_segments(const fd_plan* plan, int32_t* seg, int32_t n) {
+  if (!plan) return fail(FD_ERR_INVALID_ARG, "plan must not be NULL");
+  const int np = (int)plan->pl.units.size();
+  if (seg)
+    for (int i = 0; i < std::min<int>(n, np); ++i) seg[i] = plan->pl.units[i];
+  return np;
+}
 
 int fd_autotune(int32_t what, const fd_problem* p, int32_t nprob, const fd_options* o,
                 void* stream, fd_options* best, float* best_ms) {

@@ -18,10 +18,16 @@ def declared_symbols():
 
 @pytest.fixture(scope="module")
 def lib():
-    if not os.path.exists(fd.LIB_PATH):
-        from paper_2604_02130_amd import build
+    from paper_2604_02130_amd import build
+    if build.is_stale(fd.LIB_PATH):
         build.build()
     return fd.load_library()
+
+
+def test_library_matches_sources(lib):
+    """The digest compiled into the library is that of the sources beside it."""
+    from paper_2604_02130_amd import build
+    assert fd.version().endswith("src " + build.source_digest())
 
 
 def test_every_declared_symbol_is_exported(lib):
