@@ -185,6 +185,21 @@ void fd_plan_destroy(fd_plan *plan);
  * repeats that problem's part of a batched plan work item for work item.    */
 int fd_plan_segments(const fd_plan *plan, int32_t *seg, int32_t n);
 
+/* fd_greens without a caller workspace, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  The workspace is a fixed array of
+ * FD_NOALLOC_MAX_BYTES inside the library, one per GPU, held until the
+ * process ends; the call allocates nothing (no hipMalloc / hipFree).  Same
+ * arguments and results as fd_greens for one problem, bit for bit, on the
+ * same options.  FD_ERR_WORKSPACE if the call would need more than the
+ * fixed size (fd_workspace_bytes with FD_WHAT_GREENS; fewer segments need
+ * less).  All calls on one GPU share its array: calls that overlap in time
+ * on one GPU (other streams, other threads) race and must be serialised by
+ * the caller.                                                              */
+#define FD_NOALLOC_MAX_BYTES (64u << 20)
+int fd_greens_noalloc(const fd_problem *p, const fd_options *o, double *logdet, double *G,
+                      int32_t *status, void *stream);
+
 /* Autotuning of the stabilisation interval s (Sec. 9 leaves its choice to
  * the conditioning: candidates 4, 8, 16 within s*dk*radius(K) <= 6, radius
  * bounded by the largest absolute row sum of K) and of the time segments

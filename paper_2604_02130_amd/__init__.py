@@ -39,7 +39,7 @@ SYMBOLS = (
     "fd_plan_create", "fd_plan_launch", "fd_plan_destroy", "fd_autotune", "fd_tune_save",
     "fd_tune_load", "fd_tune_clear", "fd_response_trace_workspace_bytes", "fd_response_trace",
     "fd_hmc_leapfrog", "fd_diag_response", "fd_hmc_plan_create", "fd_hmc_plan_launch",
-    "fd_hmc_plan_destroy", "fd_plan_segments",
+    "fd_hmc_plan_destroy", "fd_plan_segments", "fd_greens_noalloc",
 )
 
 PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export"}
@@ -128,6 +128,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fd_plan_destroy.restype = None
     lib.fd_plan_segments.argtypes = [vp, vp, i32]
     lib.fd_plan_segments.restype = ctypes.c_int
+    lib.fd_greens_noalloc.argtypes = [P, O, vp, vp, vp, vp]
+    lib.fd_greens_noalloc.restype = ctypes.c_int
     lib.fd_autotune.argtypes = [i32, P, i32, O, vp, O, ctypes.POINTER(ctypes.c_float)]
     lib.fd_autotune.restype = ctypes.c_int
     lib.fd_tune_save.argtypes = [ctypes.c_char_p]
@@ -304,6 +306,18 @@ def greens(K, phi, dk, s=0, segments=0, flags=0, check=True, ws: Workspace | Non
                          status.data_ptr(), _stream()))
     _status_check(status, check)
     return torch.view_as_complex(ld), torch.view_as_complex(G)
+
+
+def greens_noalloc(K, phi, dk, logdet, G, status, s=0, segments=0, flags=0):
+    """fd_greens_noalloc: log det and G into caller tensors (logdet: 2 float64,
+    G: N*N*2 float64, status: 1 int32, all on the device) with the library's
+    fixed workspace; nothing is allocated.  The caller reads status after
+    synchronising."""
+    lib = load_library()
+    p = _prob(K, phi, dk)
+    o = _opts(s=s, segments=segments, flags=flags)
+    _check(lib.fd_greens_noalloc(ctypes.byref(p), ctypes.byref(o), logdet.data_ptr(),
+                                 G.data_ptr(), status.data_ptr(), _stream()))
 
 
 def force(K, phi, dk, s=0, checkpoint=0, flags=0, check=True, ws: Workspace | None = None,

@@ -24,7 +24,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfdet.so")
 
 KERNEL_CLASSES = (32, 64, 80, 96, 128, 512)
-OTHER_SOURCES = ["fdet_obs.hip", "fdet_hmc.hip", "fdet_abi.cpp"]
+OTHER_SOURCES = ["fdet_obs.hip", "fdet_hmc.hip", "fdet_noalloc.hip", "fdet_abi.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

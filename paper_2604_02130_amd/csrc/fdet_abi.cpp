@@ -1413,3 +1413,6 @@ int fd_profile_stop(int32_t max, int32_t* kinds, int32_t* nitems, float* ms) {
 }
 
 }  // extern "C"
+
+// Error reporting for the library's other translation units.
+int fdet_fail(int code, const char* msg) { return fail(code, msg ? msg : ""); }

@@ -265,3 +265,18 @@ def test_header_is_plain_c(lib, tmp_path):
     assert res.returncode == 0, res.stderr[-2000:]
     run = subprocess.run([str(tmp_path / "use")], capture_output=True, text=True, timeout=60)
     assert run.returncode == 0, run.stderr[-2000:]
+
+
+def test_greens_noalloc_argument_checks(lib):
+    """fd_greens_noalloc rejects missing outputs and a call larger than its
+    fixed array before it looks up a device (no GPU needed)."""
+    p = prob(N=512, Nt=512, dk=0.125)
+    o = fd.FdOptions(16, 0, 32, 0)
+    rc = lib.fd_greens_noalloc(ctypes.byref(p), ctypes.byref(o), 0x3000, 0x5000, 0x4000, None)
+    assert rc == fd.FD_ERR_WORKSPACE
+    assert "fixed" in lib.fd_last_error().decode()
+    p = prob()
+    assert lib.fd_greens_noalloc(ctypes.byref(p), None, 0x3000, None, 0x4000, None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_greens_noalloc(ctypes.byref(p), None, 0x3000, 0x5000, None, None) == fd.FD_ERR_INVALID_ARG
+    # within the limit: the workspace the call would use fits the fixed array
+    assert 0 < lib.fd_workspace_bytes(ctypes.byref(p), 1, None, fd.FD_WHAT_GREENS) <= (64 << 20)
