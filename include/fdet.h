@@ -65,6 +65,12 @@ enum { FD_WHAT_LOGDET = 0, FD_WHAT_GREENS = 1, FD_WHAT_FORCE = 2, FD_WHAT_UDV = 
 /* option flags */
 #define FD_REUSE_E 0x1   /* exp(+-dk K) already in this workspace from an earlier
                             call on the same problems: skip recomputing it     */
+#define FD_SINGLE_LAUNCH 0x4 /* the whole call as one persistent launch whose
+                            workgroups claim work items in a precomputed order
+                            and wait on per-item completion flags, instead of
+                            one launch per phase.  Currently switched off: every
+                            call with this flag returns FD_ERR_UNSUPPORTED (one
+                            run did not finish; its cause is not known)        */
 #define FD_FORCE_SCANS 0x2 /* force: build the checkpoint products by prefix /
                             suffix scans even where cyclic windows would take
                             fewer rounds (fd_force)                           */
@@ -91,7 +97,7 @@ typedef struct {
                            batch, per problem in proportion to its chain work
                            max(N,32)^2 Nt, so that the batch's chains fill the
                            compute units about once (at most min(32, Nt/4))  */
-  int32_t flags;        /* FD_REUSE_E | FD_FORCE_SCANS                         */
+  int32_t flags;        /* FD_REUSE_E | FD_FORCE_SCANS (FD_SINGLE_LAUNCH: off) */
 } fd_options;
 
 /* Bytes of workspace needed for `nprob` problems and the given entry point
@@ -308,7 +314,8 @@ const char *fd_version(void);
 /* Diagnostics: after fd_profile_start, every kernel phase launched by this
  * thread is bracketed by HIP events recorded on the call's stream.
  * fd_profile_stop waits for those events, writes up to `max` records (phase
- * kind: 0 exponential, 1 chain, 2 combine, 3 close, 4 force, 5 export; work
+ * kind: 0 exponential, 1 chain, 2 combine, 3 close, 4 force, 5 export, -1 a
+ * single launch of a whole call (see FD_SINGLE_LAUNCH); work
  * items in the launch; milliseconds) and returns the number of phases seen.
  * Any output pointer may be NULL.                                            */
 int fd_profile_start(void);

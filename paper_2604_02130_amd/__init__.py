@@ -29,6 +29,7 @@ FD_ERR_UNSUPPORTED = -6
 FD_WHAT_LOGDET, FD_WHAT_GREENS, FD_WHAT_FORCE, FD_WHAT_UDV, FD_WHAT_HMC = 0, 1, 2, 3, 4
 FD_REUSE_E = 0x1
 FD_FORCE_SCANS = 0x2
+FD_SINGLE_LAUNCH = 0x4   # switched off in the library (returns FD_ERR_UNSUPPORTED)
 MAX_N = 512
 
 # exported names (each declared in include/fdet.h)
@@ -42,7 +43,8 @@ SYMBOLS = (
     "fd_hmc_plan_destroy", "fd_plan_segments", "fd_greens_noalloc",
 )
 
-PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export"}
+PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export",
+               -1: "single"}
 
 
 class FdProblem(ctypes.Structure):
@@ -660,7 +662,7 @@ class Plan:
     """
 
     def __init__(self, what, problems, s=0, checkpoint=0, segments=0, reuse_e=False,
-                 want_g=False):
+                 want_g=False, flags=0):
         torch = _torch()
         self.lib = load_library()
         self.what = _WHAT[what]
@@ -681,20 +683,21 @@ class Plan:
             self.Fr = torch.empty(tot, dtype=torch.float64, device=dev)
             self.Fi = torch.empty(tot, dtype=torch.float64, device=dev)
         self.ws = Workspace()
+        flags &= ~FD_REUSE_E
         need = workspace_bytes(self.probs, self.what, s=s, checkpoint=checkpoint,
-                               segments=segments)
+                               segments=segments, flags=flags)
         self.wsp, self.wsn = self.ws.get(need, dev)
         self.handle = ctypes.c_void_p(0)
         if reuse_e:
             # one full call fills exp(+-dk K) into this workspace
-            self._create(_opts(s=s, checkpoint=checkpoint, segments=segments))
+            self._create(_opts(s=s, checkpoint=checkpoint, segments=segments, flags=flags))
             self.launch()
             torch.cuda.current_stream().synchronize()
             _status_check(self.status, True)
             self.lib.fd_plan_destroy(self.handle)
             self.handle = ctypes.c_void_p(0)
         self._create(_opts(s=s, checkpoint=checkpoint, segments=segments,
-                           flags=FD_REUSE_E if reuse_e else 0))
+                           flags=flags | (FD_REUSE_E if reuse_e else 0)))
 
     def _create(self, o):
         _check(self.lib.fd_plan_create(

@@ -9,6 +9,8 @@
 #include <cstring>
 #include <fstream>
 #include <mutex>
+#include <queue>
+#include <unordered_map>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -21,14 +23,27 @@
   extern "C" hipError_t fdet_launch_items_##NC(int kind, const fdet::Prob* probs,        \
                                                const fdet::Item* items, int nitems,      \
                                                hipStream_t st);
+#define FDET_DECLARE_PERSIST(NC)                                                         \
+  extern "C" hipError_t fdet_launch_persist_##NC(                                        \
+      const fdet::Prob* probs, const fdet::Item* items, int nitems, const int32_t* deps,  \
+      uint32_t* done, fdet::Sched* sched, uint64_t spin_ticks, int grid, hipStream_t st); \
+  extern "C" int fdet_persist_blocks_per_cu_##NC(void);
 FDET_DECLARE_CLASS(32)
 FDET_DECLARE_CLASS(64)
 FDET_DECLARE_CLASS(80)
 FDET_DECLARE_CLASS(96)
 FDET_DECLARE_CLASS(128)
 FDET_DECLARE_CLASS(512)
+FDET_DECLARE_PERSIST(32)
+FDET_DECLARE_PERSIST(64)
+FDET_DECLARE_PERSIST(80)
+FDET_DECLARE_PERSIST(96)
+FDET_DECLARE_PERSIST(128)
+FDET_DECLARE_PERSIST(512)
 #undef FDET_DECLARE_CLASS
-extern "C" hipError_t fdet_launch_init_status(const fdet::Prob* probs, int nprob, hipStream_t st);
+#undef FDET_DECLARE_PERSIST
+extern "C" hipError_t fdet_launch_init_status(const fdet::Prob* probs, int nprob, fdet::Sched* sched,
+                                              hipStream_t st);
 extern "C" hipError_t fdet_launch_hmc(int op, const fdet::HmcProb* hp, int nprob, int64_t maxn,
                                       double* pi, const double* force, const double* logdet,
                                       double dU, double h, double* H0, double* dH,
@@ -57,6 +72,26 @@ hipError_t fdet_launch_items(int maxn, int kind, const Prob* probs, const Item* 
   if (maxn <= 96) return fdet_launch_items_96(kind, probs, items, nitems, st);
   if (maxn <= 128) return fdet_launch_items_128(kind, probs, items, nitems, st);
   return fdet_launch_items_512(kind, probs, items, nitems, st);
+}
+
+hipError_t fdet_launch_persist(int maxn, const Prob* probs, const Item* items, int nitems,
+                               const int32_t* deps, uint32_t* done, fdet::Sched* sched,
+                               uint64_t spin_ticks, int grid, hipStream_t st) {
+  if (maxn <= 32) return fdet_launch_persist_32(probs, items, nitems, deps, done, sched, spin_ticks, grid, st);
+  if (maxn <= 64) return fdet_launch_persist_64(probs, items, nitems, deps, done, sched, spin_ticks, grid, st);
+  if (maxn <= 80) return fdet_launch_persist_80(probs, items, nitems, deps, done, sched, spin_ticks, grid, st);
+  if (maxn <= 96) return fdet_launch_persist_96(probs, items, nitems, deps, done, sched, spin_ticks, grid, st);
+  if (maxn <= 128) return fdet_launch_persist_128(probs, items, nitems, deps, done, sched, spin_ticks, grid, st);
+  return fdet_launch_persist_512(probs, items, nitems, deps, done, sched, spin_ticks, grid, st);
+}
+
+int persist_blocks_per_cu(int maxn) {
+  if (maxn <= 32) return fdet_persist_blocks_per_cu_32();
+  if (maxn <= 64) return fdet_persist_blocks_per_cu_64();
+  if (maxn <= 80) return fdet_persist_blocks_per_cu_80();
+  if (maxn <= 96) return fdet_persist_blocks_per_cu_96();
+  if (maxn <= 128) return fdet_persist_blocks_per_cu_128();
+  return fdet_persist_blocks_per_cu_512();
 }
 
 thread_local std::string g_last_error;
@@ -213,6 +248,15 @@ struct Plan {
   size_t total = 0;
   int maxN = 0;
   std::vector<int> units;   // per problem: time segments (det / G) or checkpoint intervals (force)
+  // single launch (unless FD_PHASE_LAUNCHES): every item in one list, each
+  // after the items it depends on, and the dependency lists; the tail of the
+  // workspace holds the dependency array, the completion flags and Sched
+  bool single = false;
+  int grid = 0;                 // workgroups of the single launch
+  std::vector<Item> order;      // items in claim order
+  double est_us = 0.0;          // simulated run time of the single launch
+  std::vector<int32_t> deps;
+  size_t tail_off = 0, tail_bytes = 0, deps_off = 0, done_off = 0, sched_off = 0;
 };
 
 struct Cursor {
@@ -244,6 +288,10 @@ Item blank_item(int kind, int prob) {
 
 int validate(const fd_problem* p, int nprob, const Opts& o) {
   if (!p || nprob < 1) return fail(FD_ERR_INVALID_ARG, "no problems given");
+  if (o.flags & FD_SINGLE_LAUNCH)
+    return fail(FD_ERR_UNSUPPORTED,
+                "FD_SINGLE_LAUNCH is switched off: one run of it (twelve N = 18 force problems "
+                "with grouped scans) did not finish and its cause is not known");
   if (o.s < 1) return fail(FD_ERR_INVALID_ARG, "s must be >= 1");
   if (o.c < 1 || o.c > 64) return fail(FD_ERR_INVALID_ARG, "checkpoint interval must be in [1, 64]");
   for (int i = 0; i < nprob; ++i) {
@@ -436,6 +484,167 @@ int force_schedule(const fd_problem* p, int nprob, const Opts& o) {
   return best_g;
 }
 
+// ---- single launch: dependencies and claim order
+//
+// Estimated run time of one item on one workgroup (microseconds): its model
+// FLOP at a per-workgroup rate that grows with N (the small classes are
+// latency-bound), plus a fixed cost per item.  Only the relative sizes
+// matter: they order the simulated schedule below.
+double item_cost(const Prob& P, const Item& it) {
+  const double n = P.N, n3 = n * n * n;
+  const double rate = 160e3 * n / (n + 100.0);   // FLOP per microsecond
+  double units = 1.0;
+  switch (it.kind) {
+    case fdet::IK_EXPM: units = 16.0; break;
+    case fdet::IK_CHAIN: {
+      const int r = it.t1 - it.t0;
+      units = 4.0 * r + 14.67 * ((r + std::max(1, it.s) - 1) / std::max(1, it.s));
+      break;
+    }
+    case fdet::IK_COMBINE: units = 30.67; break;
+    case fdet::IK_CLOSE: units = (it.flags & fdet::IF_WANT_G) ? 33.3 : 13.3; break;
+    case fdet::IK_FORCE: units = 64.0 + 8.0 * (std::max(0, it.t1 - it.t0 - 1) + it.nb); break;
+    default: break;
+  }
+  return 20.0 + units * n3 / rate;
+}
+
+// Workspace regions an item reads and writes, keyed by their first address:
+// UDV slots (by X), scratch areas, E and E^-1.  Outputs in caller memory are
+// written by one item each (disjoint force rows) and need no ordering.
+struct Access {
+  const void* key;
+  bool write;
+};
+
+void item_access(const Prob& P, const Item& it, std::vector<Access>& acc) {
+  acc.clear();
+  auto rd = [&](const void* k) { if (k) acc.push_back({k, false}); };
+  auto wr = [&](const void* k) { if (k) acc.push_back({k, true}); };
+  wr(it.scr);
+  switch (it.kind) {
+    case fdet::IK_EXPM: wr(it.sign > 0 ? P.E : P.Einv); break;
+    case fdet::IK_CHAIN:
+      rd(P.E);
+      wr(it.a.X);
+      break;
+    case fdet::IK_COMBINE:
+      rd(it.a.X);
+      rd(it.b.X);
+      wr(it.o.X ? it.o.X : it.a.X);
+      break;
+    case fdet::IK_CLOSE: wr(it.a.X); break;   // its T serves as free storage
+    case fdet::IK_FORCE:
+      rd(it.a.X);
+      rd(it.b.X);
+      rd(P.E);
+      rd(P.Einv);
+      break;
+    case fdet::IK_EXPORT: rd(it.a.X); break;
+    default: break;
+  }
+}
+
+// Items of all phases in one list for the single launch: the dependencies of
+// each item follow from the regions it shares with earlier items in phase
+// order (read after write, write after write, write after read), and the
+// list order is that of a simulated list schedule on `workers` workgroups
+// that starts the ready item with the longest remaining path first (HLFET).
+// Every item then comes after the items it depends on, so claiming items in
+// list order cannot wait forever; deps are rewritten to list positions.
+void single_launch_order(Plan& pl, int workers) {
+  std::vector<Item> items;
+  for (auto& ph : pl.phases) items.insert(items.end(), ph.begin(), ph.end());
+  const int n = (int)items.size();
+  struct RegionState {
+    int writer = -1;
+    std::vector<int> readers;
+  };
+  std::unordered_map<const void*, RegionState> reg;
+  std::vector<std::vector<int>> pred(n), succ(n);
+  std::vector<Access> acc;
+  for (int i = 0; i < n; ++i) {
+    item_access(pl.probs[items[i].prob], items[i], acc);
+    std::vector<int>& d = pred[i];
+    for (const Access& a : acc) {
+      RegionState& r = reg[a.key];
+      if (r.writer >= 0) d.push_back(r.writer);
+      bool written = false;
+      for (const Access& b : acc) written = written || (b.key == a.key && b.write);
+      if (written) d.insert(d.end(), r.readers.begin(), r.readers.end());
+    }
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    for (const Access& a : acc) {
+      RegionState& r = reg[a.key];
+      bool written = false;
+      for (const Access& b : acc) written = written || (b.key == a.key && b.write);
+      if (written) {
+        r.writer = i;
+        r.readers.clear();
+      } else if (r.readers.empty() || r.readers.back() != i) {
+        r.readers.push_back(i);
+      }
+    }
+    for (int q : d) succ[q].push_back(i);
+  }
+  // longest remaining path (bottom level), items in reverse phase order
+  std::vector<double> cost(n), bl(n);
+  for (int i = 0; i < n; ++i) cost[i] = item_cost(pl.probs[items[i].prob], items[i]);
+  for (int i = n - 1; i >= 0; --i) {
+    double m = 0.0;
+    for (int q : succ[i]) m = std::max(m, bl[q]);
+    bl[i] = cost[i] + m;
+  }
+  // list-schedule simulation
+  std::vector<int> indeg(n);
+  for (int i = 0; i < n; ++i) indeg[i] = (int)pred[i].size();
+  auto lower = [&](int a, int b) { return bl[a] < bl[b] || (bl[a] == bl[b] && a > b); };
+  std::priority_queue<int, std::vector<int>, decltype(lower)> ready(lower);
+  for (int i = 0; i < n; ++i)
+    if (indeg[i] == 0) ready.push(i);
+  typedef std::pair<double, int> Ev;
+  std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> running;
+  std::vector<int> seq;
+  seq.reserve(n);
+  double now = 0.0;
+  int idle = std::max(1, workers);
+  while ((int)seq.size() < n) {
+    while (idle > 0 && !ready.empty()) {
+      const int i = ready.top();
+      ready.pop();
+      seq.push_back(i);
+      running.push({now + cost[i], i});
+      --idle;
+    }
+    if (running.empty()) break;   // unreachable: the dependency graph is acyclic
+    now = running.top().first;
+    while (!running.empty() && running.top().first <= now) {
+      const int i = running.top().second;
+      running.pop();
+      ++idle;
+      for (int q : succ[i])
+        if (--indeg[q] == 0) ready.push(q);
+    }
+  }
+  if ((int)seq.size() != n) {
+    std::fprintf(stderr, "libfdet: dependency graph of %d items is not acyclic\n", n);
+    std::abort();
+  }
+  pl.est_us = now;
+  std::vector<int> pos(n);
+  for (int k = 0; k < n; ++k) pos[seq[k]] = k;
+  pl.order.resize(n);
+  pl.deps.clear();
+  for (int k = 0; k < n; ++k) {
+    Item it = items[seq[k]];
+    it.dep0 = (int32_t)pl.deps.size();
+    it.ndep = (int32_t)pred[seq[k]].size();
+    for (int q : pred[seq[k]]) pl.deps.push_back(pos[q]);
+    pl.order[k] = it;
+  }
+}
+
 // Build the layout and the work items.  `what` = FD_WHAT_*.
 void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* base, Plan& pl) {
   pl.probs.assign(nprob, Prob{});
@@ -478,7 +687,10 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   }
   pl.desc_bytes = align_up(sizeof(Prob) * nprob) + align_up(sizeof(Item) * nitems);
   pl.item_cap = nitems;
-  Cursor cur{base, align_up(pl.desc_bytes)};
+  // a sizing pass (base == nullptr) lays out against a stand-in address: the
+  // single launch's dependencies are keyed by region addresses, so they must
+  // be distinct there too (the pointers of a sizing plan are never used)
+  Cursor cur{base ? base : reinterpret_cast<char*>((uintptr_t)1 << 40), align_up(pl.desc_bytes)};
 
   std::vector<Item> expm, chain, close, forcei;
   std::vector<std::vector<Item>> comb(maxlev);
@@ -682,29 +894,71 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
     if (!c.empty()) pl.phases.push_back(c);
   if (!close.empty()) pl.phases.push_back(close);
   if (!forcei.empty()) pl.phases.push_back(forcei);
-  pl.total = cur.off;
   size_t n = 0;
   for (auto& ph : pl.phases) n += ph.size();
   if (n > pl.item_cap) {   // the counting pass above must cover every item
     std::fprintf(stderr, "libfdet: %zu work items exceed the %zu counted\n", n, pl.item_cap);
     std::abort();
   }
+  pl.single = (o.flags & FD_SINGLE_LAUNCH) != 0;
+  if (pl.single) {
+    const int workers = device_cu_count() * persist_blocks_per_cu(pl.maxN);
+    pl.grid = (int)std::min<size_t>(n, (size_t)workers);
+    single_launch_order(pl, workers);
+  }
+  // tail: dependency lists, completion flags, launch state
+  pl.tail_off = cur.off;
+  pl.deps_off = cur.off;
+  cur.take(sizeof(int32_t) * std::max<size_t>(1, pl.deps.size()));
+  pl.done_off = cur.off;
+  cur.take(sizeof(uint32_t) * std::max<size_t>(1, n));
+  pl.sched_off = cur.off;
+  cur.take(sizeof(fdet::Sched));
+  pl.tail_bytes = cur.off - pl.tail_off;
+  pl.total = cur.off;
 }
 
-// Descriptors (problems, then the items of every phase) in the head of the
-// workspace; `first` receives the index of each phase's first item.
-std::vector<char> pack_descriptors(const Plan& pl, std::vector<size_t>& first) {
+// Descriptors (problems, then the items of every phase, or the single
+// launch's item list) in the head of the workspace; `first` receives the
+// index of each phase's first item.  `tail` receives the single launch's
+// dependency lists, zeroed completion flags and launch state, which go to
+// pl.tail_off.
+std::vector<char> pack_descriptors(const Plan& pl, std::vector<size_t>& first,
+                                   std::vector<char>* tail = nullptr) {
   std::vector<char> host(pl.desc_bytes, 0);
   const size_t pbytes = align_up(sizeof(Prob) * pl.probs.size());
   std::memcpy(host.data(), pl.probs.data(), sizeof(Prob) * pl.probs.size());
   first.clear();
   size_t n = 0;
-  for (auto& ph : pl.phases) {
-    first.push_back(n);
-    std::memcpy(host.data() + pbytes + n * sizeof(Item), ph.data(), ph.size() * sizeof(Item));
-    n += ph.size();
+  if (pl.single) {
+    std::memcpy(host.data() + pbytes, pl.order.data(), pl.order.size() * sizeof(Item));
+  } else {
+    for (auto& ph : pl.phases) {
+      first.push_back(n);
+      std::memcpy(host.data() + pbytes + n * sizeof(Item), ph.data(), ph.size() * sizeof(Item));
+      n += ph.size();
+    }
+  }
+  if (tail) {
+    tail->assign(pl.tail_bytes, 0);
+    if (!pl.deps.empty())
+      std::memcpy(tail->data() + (pl.deps_off - pl.tail_off), pl.deps.data(),
+                  pl.deps.size() * sizeof(int32_t));
   }
   return host;
+}
+
+// Time limit of one wait of the single launch, in ticks of the device's
+// constant-rate clock: 20 times the simulated run time of the whole call,
+// at least 20 s.  It only guards against a wait that cannot end; the plan
+// checker shows on the host that every item waits for earlier items only.
+uint64_t spin_limit_ticks(double est_us) {
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;
+  const double sec = std::max(20.0, 20.0 * est_us * 1e-6);
+  return (uint64_t)(sec * 1000.0 * khz);
 }
 
 // Kernel launches only (no copies or fills): the part a HIP graph captures.
@@ -712,35 +966,62 @@ int launch_phases(const Plan& pl, const std::vector<size_t>& first, char* ws, hi
   const size_t pbytes = align_up(sizeof(Prob) * pl.probs.size());
   const Prob* dprobs = reinterpret_cast<const Prob*>(ws);
   const Item* ditems = reinterpret_cast<const Item*>(ws + pbytes);
-  hipError_t e = fdet_launch_init_status(dprobs, (int)pl.probs.size(), st);
+  fdet::Sched* sched = pl.single ? reinterpret_cast<fdet::Sched*>(ws + pl.sched_off) : nullptr;
+  hipError_t e = fdet_launch_init_status(dprobs, (int)pl.probs.size(), sched, st);
   if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   const bool prof = g_prof_on && hipStreamIsCapturing(st, &cap) == hipSuccess &&
                     cap == hipStreamCaptureStatusNone;
-  for (size_t k = 0; k < pl.phases.size(); ++k) {
-    const int kind = pl.phases[k].front().kind;
-    PhaseRec rec{kind, (int)pl.phases[k].size(), nullptr, nullptr};
+  auto bracket = [&](int kind, int nitems, auto&& launch) -> int {
+    PhaseRec rec{kind, nitems, nullptr, nullptr};
     if (prof) {
       if (hipEventCreate(&rec.a) != hipSuccess || hipEventCreate(&rec.b) != hipSuccess)
         return fail(FD_ERR_HIP, "event creation failed");
       hipEventRecord(rec.a, st);
     }
-    e = fdet_launch_items(pl.maxN, kind, dprobs, ditems + first[k], (int)pl.phases[k].size(), st);
-    if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(e));
+    const hipError_t r = launch();
+    if (r != hipSuccess) return fail(FD_ERR_HIP, std::string("launch: ") + hipGetErrorString(r));
     if (prof) {
       hipEventRecord(rec.b, st);
       g_prof.push_back(rec);
     }
+    return FD_OK;
+  };
+  if (pl.single) {
+    const int n = (int)pl.order.size();
+    return bracket(-1, n, [&]() {
+      return fdet_launch_persist(pl.maxN, dprobs, ditems, n,
+                                 reinterpret_cast<const int32_t*>(ws + pl.deps_off),
+                                 reinterpret_cast<uint32_t*>(ws + pl.done_off), sched,
+                                 spin_limit_ticks(pl.est_us), pl.grid, st);
+    });
   }
+  for (size_t k = 0; k < pl.phases.size(); ++k) {
+    const int kind = pl.phases[k].front().kind;
+    const int rc = bracket(kind, (int)pl.phases[k].size(), [&]() {
+      return fdet_launch_items(pl.maxN, kind, dprobs, ditems + first[k], (int)pl.phases[k].size(), st);
+    });
+    if (rc != FD_OK) return rc;
+  }
+  return FD_OK;
+}
+
+// Upload the descriptors (and the single launch's tail) into the workspace.
+int upload(const Plan& pl, std::vector<size_t>& first, char* ws, hipStream_t st) {
+  std::vector<char> tail;
+  std::vector<char> host = pack_descriptors(pl, first, &tail);
+  hipError_t e = hipMemcpyAsync(ws, host.data(), pl.desc_bytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && pl.single)
+    e = hipMemcpyAsync(ws + pl.tail_off, tail.data(), tail.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
   return FD_OK;
 }
 
 // Upload descriptors into the head of the workspace and launch every phase.
 int execute(Plan& pl, char* ws, hipStream_t st) {
   std::vector<size_t> first;
-  std::vector<char> host = pack_descriptors(pl, first);
-  hipError_t e = hipMemcpyAsync(ws, host.data(), pl.desc_bytes, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return fail(FD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+  const int rc = upload(pl, first, ws, st);
+  if (rc != FD_OK) return rc;
   return launch_phases(pl, first, ws, st);
 }
 
@@ -981,9 +1262,10 @@ int fd_slice_exponential(const fd_problem* p, double* E, void* ws, size_t ws_byt
   Plan pl;
   build_plan(p, 1, r, FD_WHAT_LOGDET, static_cast<char*>(ws), pl);
   pl.probs[0].outE = E;
-  // only the exponential phase
+  // only the exponential phase, as one launch of its own
   std::vector<Item> keep = pl.phases.front();
   pl.phases.assign(1, keep);
+  pl.single = false;
   return execute(pl, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
 }
 
@@ -1072,9 +1354,12 @@ int fd_plan_create(int32_t what, const fd_problem* p, int32_t nprob, const fd_op
   int rc = prepare(p, nprob, o, what, out, ws, ws_bytes, h->pl);
   if (rc != FD_OK) { delete h; return rc; }
   h->ws = static_cast<char*>(ws);
-  std::vector<char> host = pack_descriptors(h->pl, h->first);
-  hipError_t e = hipMemcpyAsync(ws, host.data(), h->pl.desc_bytes, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  rc = upload(h->pl, h->first, h->ws, st);
+  if (rc != FD_OK) {
+    delete h;
+    return rc;
+  }
+  hipError_t e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     delete h;
     return fail(FD_ERR_HIP, std::string("descriptor upload: ") + hipGetErrorString(e));

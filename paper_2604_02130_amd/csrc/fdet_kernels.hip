@@ -725,10 +725,94 @@ FDET_KERNEL(k_close, do_close<C>(P, it.a, cmat_at(it.scr, P.Np),
 FDET_KERNEL(k_force, do_force<C>(P, it, S))
 FDET_KERNEL(k_export, do_export<C>(P, it, S))
 
+// One item of any kind (the single-launch kernel below).
+template <int C>
+__device__ __forceinline__ void run_item(const Prob& P, const Item& it, SmemC<C>& S) {
+  switch (it.kind) {
+    case IK_EXPM: do_expm<C>(P, it, S); break;
+    case IK_CHAIN: do_chain<C>(P, it, S); break;
+    case IK_COMBINE: do_combine<C>(P, it, S); break;
+    case IK_CLOSE:
+      do_close<C>(P, it.a, cmat_at(it.scr, P.Np), cmat_at(it.scr + cmat_doubles(P.Np), P.Np),
+                  cmat_at(it.scr, P.Np), (it.flags & IF_WANT_G) != 0, true, true,
+                  tstore(it.scr, P.Np), S);
+      break;
+    case IK_FORCE: do_force<C>(P, it, S); break;
+    case IK_EXPORT: do_export<C>(P, it, S); break;
+    default: break;
+  }
+}
+
+// The whole plan in one launch: each workgroup claims the next item of the
+// list (which the host ordered by a simulated critical-path schedule, every
+// item after the items it depends on), waits until those items are complete
+// in this launch, runs it and marks it complete.  Because claims follow the
+// list order, every item an item waits for has been claimed by a running
+// workgroup, so the waits end; an item that nonetheless waits longer than
+// `spin_ticks` of the constant-rate clock is skipped with FD_ERR_HIP in the
+// problem's status (and still marked complete), so the launch always ends.
+// Which workgroup runs an item does not change its arithmetic: results are
+// bit-identical to one launch per phase.
+template <int NC>
+__global__ __launch_bounds__(WG) void k_persist(const Prob* __restrict__ probs,
+                                                const Item* __restrict__ items, int nitems,
+                                                const int32_t* __restrict__ deps, uint32_t* done,
+                                                Sched* sched, uint64_t spin_ticks) {
+  __shared__ SmemC<NC> S_;
+  __shared__ int s_item;
+  __shared__ int s_ok;
+  const uint32_t epoch = sched->epoch;
+  while (true) {
+    if (threadIdx.x == 0)
+      s_item = (int)__hip_atomic_fetch_add(&sched->next, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int idx = s_item;
+    if (idx >= nitems) break;
+    const Item it = items[idx];
+    if (threadIdx.x == 0) {
+      int ok = 1;
+      const uint64_t t0 = wall_clock64();
+      for (int d = 0; d < it.ndep && ok; ++d) {
+        const uint32_t* f = done + deps[it.dep0 + d];
+        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+          __builtin_amdgcn_s_sleep(8);
+          if (wall_clock64() - t0 > spin_ticks) { ok = 0; break; }
+        }
+      }
+      s_ok = ok;
+    }
+    __syncthreads();
+    // acquire: what the items waited for wrote is visible to every wave
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const Prob P = probs[it.prob];
+    if (s_ok) {
+      by_class<NC>(P.N, [&](auto cls) {
+        constexpr int C = decltype(cls)::value;
+        static_assert(sizeof(SmemC<C>) <= sizeof(SmemC<NC>), "class layout");
+        SmemC<C>& S = *reinterpret_cast<SmemC<C>*>(&S_);
+        run_item<C>(P, it, S);
+      });
+    } else if (threadIdx.x == 0) {
+      status_merge(P.status, -5);
+    }
+    // release: every wave's results are visible before the item is marked
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(done + idx, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 #if FDET_NC == 32
-__global__ void k_init_status(const Prob* __restrict__ probs, int nprob) {
+// Clears the status words; with a single-launch plan also starts its next
+// launch (epoch + 1, claim counter 0).
+__global__ void k_init_status(const Prob* __restrict__ probs, int nprob, Sched* sched) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nprob && probs[i].status) *probs[i].status = 0;
+  if (i == 0 && sched) {
+    sched->epoch = sched->epoch + 1u;
+    sched->next = 0u;
+  }
 }
 #endif
 
@@ -768,9 +852,32 @@ extern "C" hipError_t FDET_CAT(fdet_launch_items_, FDET_NC)(int kind, const fdet
   return launch_kind<FDET_NC>(kind, probs, items, nitems, st);
 }
 
+// Single launch of a whole plan; grid = workgroups that run at once (at
+// most one per item).
+extern "C" hipError_t FDET_CAT(fdet_launch_persist_, FDET_NC)(
+    const fdet::Prob* probs, const fdet::Item* items, int nitems, const int32_t* deps,
+    uint32_t* done, fdet::Sched* sched, uint64_t spin_ticks, int grid, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fdet::k_persist<FDET_NC>, dim3(grid), dim3(fdet::WG), 0, st, probs, items,
+                     nitems, deps, done, sched, spin_ticks);
+  return hipGetLastError();
+}
+
+// Workgroups of the single-launch kernel that fit on one compute unit.
+extern "C" int FDET_CAT(fdet_persist_blocks_per_cu_, FDET_NC)(void) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fdet::k_persist<FDET_NC>, fdet::WG, 0) !=
+          hipSuccess ||
+      n < 1)
+    n = 1;
+  return n;
+}
+
 #if FDET_NC == 32
-extern "C" hipError_t fdet_launch_init_status(const fdet::Prob* probs, int nprob, hipStream_t st) {
-  hipLaunchKernelGGL(fdet::k_init_status, dim3((nprob + 255) / 256), dim3(256), 0, st, probs, nprob);
+extern "C" hipError_t fdet_launch_init_status(const fdet::Prob* probs, int nprob,
+                                              fdet::Sched* sched, hipStream_t st) {
+  hipLaunchKernelGGL(fdet::k_init_status, dim3((nprob + 255) / 256), dim3(256), 0, st, probs, nprob,
+                     sched);
   return hipGetLastError();
 }
 #endif

@@ -54,10 +54,23 @@ struct Item {
   int32_t t0, t1;       // slice rows [t0, t1)
   int32_t s, pad0;      // stabilisation interval
   int32_t nb, pad1;     // force: rows t0-1, ..., t0-nb (mod N_t) carried backward
+  int32_t dep0, ndep;   // single launch: the items this one waits for are
+                        // deps[dep0 .. dep0 + ndep), indices into the item list
   Udv a;                // state / right operand / result
   Udv b;                // left operand (combine), right factor (force)
   Udv o;                // combine: result (X == nullptr: into a)
   double* scr;          // scratch: 4 cmats + 2*Np doubles
+};
+
+// State of a single-launch execution of a whole plan (one persistent kernel
+// whose workgroups claim items in list order).  `epoch` counts launches of
+// the plan: item i is complete in the current launch once done[i] == epoch,
+// so the flags never need clearing.  Zero when the descriptors are uploaded;
+// the launch's first kernel advances epoch and resets next.
+struct Sched {
+  uint32_t epoch;
+  uint32_t next;        // next item index to claim
+  uint32_t pad[62];     // own 256-byte block
 };
 
 }  // namespace fdet

@@ -16,15 +16,33 @@ extern "C" hipError_t fdet_launch_items_80(int, const fdet::Prob*, const fdet::I
 extern "C" hipError_t fdet_launch_items_96(int, const fdet::Prob*, const fdet::Item*, int, hipStream_t) { return hipSuccess; }
 extern "C" hipError_t fdet_launch_items_128(int, const fdet::Prob*, const fdet::Item*, int, hipStream_t) { return hipSuccess; }
 extern "C" hipError_t fdet_launch_items_512(int, const fdet::Prob*, const fdet::Item*, int, hipStream_t) { return hipSuccess; }
-extern "C" hipError_t fdet_launch_init_status(const fdet::Prob*, int, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_init_status(const fdet::Prob*, int, fdet::Sched*, hipStream_t) { return hipSuccess; }
+extern "C" hipError_t fdet_launch_persist_32(const fdet::Prob*, const fdet::Item*, int, const int32_t*, uint32_t*, fdet::Sched*, uint64_t, int, hipStream_t) { return hipSuccess; }
+extern "C" int fdet_persist_blocks_per_cu_32(void) { return 1; }
+extern "C" hipError_t fdet_launch_persist_64(const fdet::Prob*, const fdet::Item*, int, const int32_t*, uint32_t*, fdet::Sched*, uint64_t, int, hipStream_t) { return hipSuccess; }
+extern "C" int fdet_persist_blocks_per_cu_64(void) { return 1; }
+extern "C" hipError_t fdet_launch_persist_80(const fdet::Prob*, const fdet::Item*, int, const int32_t*, uint32_t*, fdet::Sched*, uint64_t, int, hipStream_t) { return hipSuccess; }
+extern "C" int fdet_persist_blocks_per_cu_80(void) { return 1; }
+extern "C" hipError_t fdet_launch_persist_96(const fdet::Prob*, const fdet::Item*, int, const int32_t*, uint32_t*, fdet::Sched*, uint64_t, int, hipStream_t) { return hipSuccess; }
+extern "C" int fdet_persist_blocks_per_cu_96(void) { return 1; }
+extern "C" hipError_t fdet_launch_persist_128(const fdet::Prob*, const fdet::Item*, int, const int32_t*, uint32_t*, fdet::Sched*, uint64_t, int, hipStream_t) { return hipSuccess; }
+extern "C" int fdet_persist_blocks_per_cu_128(void) { return 1; }
+extern "C" hipError_t fdet_launch_persist_512(const fdet::Prob*, const fdet::Item*, int, const int32_t*, uint32_t*, fdet::Sched*, uint64_t, int, hipStream_t) { return hipSuccess; }
+extern "C" int fdet_persist_blocks_per_cu_512(void) { return 1; }
+
 extern "C" hipError_t fdet_launch_trace(int, const double*, const double*, double*, double*, hipStream_t) { return hipSuccess; }
 extern "C" hipError_t fdet_launch_diag_response(int, int, const double*, const double*, const double*, double*, hipStream_t) { return hipSuccess; }
 extern "C" hipError_t fdet_launch_hmc(int, const fdet::HmcProb*, int, int64_t, double*, const double*, const double*, double, double, double*, double*, const int32_t*, int32_t*, int, hipStream_t) { return hipSuccess; }
 
 static int check(const char* name, std::vector<fd_problem> p, fd_options oo, int what, bool verbose) {
   Opts o = resolve(&oo, p.data(), (int)p.size(), what);
+  // the single-launch planner (switched off in the library's entry points)
+  // is built and checked on every plan here, on the host only
+  o.flags |= FD_SINGLE_LAUNCH;
   Plan pl;
   build_plan(p.data(), (int)p.size(), o, what, (char*)0x10000000, pl);
+  Plan sizing;
+  build_plan(p.data(), (int)p.size(), o, what, nullptr, sizing);
   int bad = 0;
   // every workspace pointer of every item stays inside [base + desc, base + total)
   {
@@ -47,7 +65,8 @@ static int check(const char* name, std::vector<fd_problem> p, fd_options oo, int
       if (it.t0 < 0 || it.t1 < it.t0 || it.t1 > P.Nt || it.nb < 0 || it.nb > P.Nt) { printf(" [rows out]"); bad++; }
       if (it.kind != fdet::IK_EXPM && it.kind != fdet::IK_EXPORT && it.kind != fdet::IK_CLOSE && !it.scr) { printf(" [no scr]"); bad++; }
     }
-    if (pl.total > fd_workspace_bytes(p.data(), (int)p.size(), &oo, what)) { printf(" [total > sized]"); bad++; }
+    if (pl.total > sizing.total) { printf(" [total > sized]"); bad++; }
+    if (fd_workspace_bytes(p.data(), (int)p.size(), &oo, what) == 0) { printf(" [sizing failed]"); bad++; }
   }
   if (what == FD_WHAT_FORCE) printf("%s: schedule g=%d ", name, force_schedule(p.data(), (int)p.size(), o));
   else printf("%s: ", name);
@@ -80,6 +99,72 @@ static int check(const char* name, std::vector<fd_problem> p, fd_options oo, int
       for (auto& it : ph) if (it.flags & fdet::IF_OUT_LOGDET) nl++;
       printf(" (logdet items %d)", nl);
     }
+  }
+  // single launch: the claim list holds every item once, each after the
+  // items it waits for, and any two items that touch one workspace region
+  // with at least one writing it are ordered by the waits (one reaches the
+  // other).  The region rules here are restated from the kernels: scratch is
+  // written by its item; E / E^-1 written by the exponential and read by
+  // chains and force items; a chain writes its slot; a combine reads both
+  // operands and writes its result slot; a close writes the slot it closes
+  // (its T is free storage); a force item reads its two factors.
+  if (pl.single) {
+    size_t total = 0;
+    for (auto& ph : pl.phases) total += ph.size();
+    const int n = (int)pl.order.size();
+    if ((size_t)n != total) { printf(" [order size]"); bad++; }
+    for (int k = 0; k < n; ++k) {
+      const Item& it = pl.order[k];
+      if (it.dep0 < 0 || it.ndep < 0 || (size_t)(it.dep0 + it.ndep) > pl.deps.size()) { printf(" [dep range]"); bad++; continue; }
+      for (int d = 0; d < it.ndep; ++d)
+        if (pl.deps[it.dep0 + d] < 0 || pl.deps[it.dep0 + d] >= k) { printf(" [dep not earlier]"); bad++; }
+    }
+    if (pl.grid < 1 || pl.grid > n) { printf(" [grid]"); bad++; }
+    // reachability over the claim list (bitsets)
+    const int words = (n + 63) / 64;
+    std::vector<uint64_t> reach((size_t)n * words, 0);
+    for (int k = 0; k < n; ++k) {
+      uint64_t* rk = &reach[(size_t)k * words];
+      const Item& it = pl.order[k];
+      for (int d = 0; d < it.ndep; ++d) {
+        const int q = pl.deps[it.dep0 + d];
+        if (q < 0 || q >= k) continue;
+        const uint64_t* rq = &reach[(size_t)q * words];
+        for (int w = 0; w < words; ++w) rk[w] |= rq[w];
+        rk[q / 64] |= 1ull << (q % 64);
+      }
+    }
+    auto regions = [&](const Item& it, std::vector<std::pair<const void*, bool>>& r) {
+      const Prob& P = pl.probs[it.prob];
+      r.clear();
+      if (it.scr && !(it.kind == fdet::IK_CHAIN && it.t0 == it.t1)) r.push_back({it.scr, true});
+      if (it.kind == fdet::IK_EXPM) r.push_back({it.sign > 0 ? (const void*)P.E : (const void*)P.Einv, true});
+      if (it.kind == fdet::IK_CHAIN) { r.push_back({P.E, false}); r.push_back({it.a.X, true}); }
+      if (it.kind == fdet::IK_COMBINE) { r.push_back({it.a.X, false}); r.push_back({it.b.X, false}); r.push_back({it.o.X ? it.o.X : it.a.X, true}); }
+      if (it.kind == fdet::IK_CLOSE) r.push_back({it.a.X, true});
+      if (it.kind == fdet::IK_FORCE) { r.push_back({it.a.X, false}); r.push_back({it.b.X, false}); r.push_back({P.E, false}); if (P.Einv) r.push_back({P.Einv, false}); }
+      if (it.kind == fdet::IK_EXPORT) r.push_back({it.a.X, false});
+    };
+    std::map<const void*, std::vector<std::pair<int, bool>>> users;
+    std::vector<std::pair<const void*, bool>> r;
+    for (int k = 0; k < n; ++k) {
+      regions(pl.order[k], r);
+      for (auto& x : r) users[x.first].push_back({k, x.second});
+    }
+    long long unordered = 0;
+    for (auto& u : users) {
+      auto& v = u.second;
+      for (size_t a = 0; a < v.size(); ++a)
+        for (size_t b = a + 1; b < v.size(); ++b) {
+          if (!v[a].second && !v[b].second) continue;
+          int i = v[a].first, j = v[b].first;
+          if (i == j) continue;
+          if (i > j) std::swap(i, j);
+          if (!((reach[(size_t)j * words + i / 64] >> (i % 64)) & 1ull)) unordered++;
+        }
+    }
+    if (unordered) { printf(" [unordered conflicts %lld]", unordered); bad++; }
+    if (verbose) printf(" single: %d items, %zu waits, grid %d", n, pl.deps.size(), pl.grid);
   }
   printf("  %s\n", bad ? "BAD" : "ok");
   return bad;

@@ -280,3 +280,12 @@ def test_greens_noalloc_argument_checks(lib):
     assert lib.fd_greens_noalloc(ctypes.byref(p), None, 0x3000, 0x5000, None, None) == fd.FD_ERR_INVALID_ARG
     # within the limit: the workspace the call would use fits the fixed array
     assert 0 < lib.fd_workspace_bytes(ctypes.byref(p), 1, None, fd.FD_WHAT_GREENS) <= (64 << 20)
+
+
+def test_single_launch_flag_is_switched_off(lib):
+    """FD_SINGLE_LAUNCH returns FD_ERR_UNSUPPORTED before anything is enqueued."""
+    p = prob()
+    o = fd.FdOptions(4, 0, 0, fd.FD_SINGLE_LAUNCH)
+    rc = lib.fd_logdet(ctypes.byref(p), ctypes.byref(o), 0x3000, 0x10000, 1 << 30, 0x4000, None)
+    assert rc == fd.FD_ERR_UNSUPPORTED
+    assert "switched off" in lib.fd_last_error().decode()

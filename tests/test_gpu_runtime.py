@@ -194,3 +194,72 @@ def test_batched_trajectory(fd):
             assert torch.equal(ld[j], ld_e), (rep, j)
             _, G_e = fd.greens(Kd, to_dev(f), dk, s=4, segments=1)
             assert np.abs(Gs[j].cpu().numpy() - G_e.cpu().numpy()).max() <= TOL
+
+
+# ---------------------------------------------------------------------------
+# single launch (default) against one launch per phase: bit-identical
+# ---------------------------------------------------------------------------
+
+def _single_vs_phased_cases():
+    from workload import WORKLOADS, batched_mix, honeycomb_hopping, sample_phi
+    return WORKLOADS, batched_mix, honeycomb_hopping, sample_phi
+
+
+@pytest.mark.gpu
+@pytest.mark.skip(reason="FD_SINGLE_LAUNCH is switched off: its run of force_batch_scans (twelve "
+                         "N = 18 force problems, grouped scans) did not finish and the cause is "
+                         "not known; lowT_L6, batched_mix64 and force_L8 had matched bit for bit")
+@pytest.mark.parametrize("case", ["lowT_L6", "batched_mix64", "force_L8", "force_batch_scans",
+                                  "large_mixed"])
+def test_single_launch_matches_phase_launches(fd, case):
+    """The whole call in one persistent launch (FD_SINGLE_LAUNCH: workgroups
+    claim items in a precomputed order and wait on completion flags) gives the
+    same bits as one launch per phase, for det / G, a mixed batch, the force
+    with cyclic windows and with grouped scans, and a batch in the blocked
+    class.  """
+    import torch
+    WORKLOADS, batched_mix, honeycomb_hopping, sample_phi = _single_vs_phased_cases()
+    dev = torch.device("cuda:0")
+
+    def t(a):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+    S = fd.FD_SINGLE_LAUNCH
+    if case == "lowT_L6":
+        w = WORKLOADS[case]
+        K, phi = t(w.K()), t(w.phi())
+        for seg in (1, 8, 32):
+            a = fd.greens(K, phi, w.dk, s=w.s, segments=seg, flags=S)
+            b = fd.greens(K, phi, w.dk, s=w.s, segments=seg)
+            assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), seg
+    elif case == "batched_mix64":
+        probs = [(t(w.K()), t(w.phi()), w.dk) for w in batched_mix(64)]
+        a = fd.greens_batched(probs, s=8, flags=S)
+        b = fd.greens_batched(probs, s=8)
+        assert torch.equal(a[0], b[0])
+        assert all(torch.equal(x, y) for x, y in zip(a[1], b[1]))
+    elif case == "force_L8":
+        w = WORKLOADS[case]
+        K, phi = t(w.K()), t(w.phi())
+        a, la = fd.force(K, phi, w.dk, s=w.s, checkpoint=w.c, with_logdet=True, flags=S)
+        b, lb = fd.force(K, phi, w.dk, s=w.s, checkpoint=w.c, with_logdet=True)
+        assert torch.equal(a, b) and torch.equal(la, lb)
+    elif case == "force_batch_scans":
+        K = honeycomb_hopping(3)
+        probs = [(t(K), t(sample_phi(40 + i, 96, 18, 0.125, 3.0)), 0.125) for i in range(12)]
+        a = fd.force_batched(probs, s=4, checkpoint=4, flags=fd.FD_FORCE_SCANS | S)
+        b = fd.force_batched(probs, s=4, checkpoint=4, flags=fd.FD_FORCE_SCANS)
+        assert all(torch.equal(x, y) for x, y in zip(a[0], b[0]))
+        assert torch.equal(a[1], b[1])
+    else:
+        probs = []
+        for i, L in enumerate((9, 2, 5, 10)):
+            K = honeycomb_hopping(L)
+            probs.append((t(K), t(sample_phi(70 + i, 24, K.shape[0], 0.125, 3.0)), 0.125))
+        a = fd.greens_batched(probs, s=8, segments=2, flags=S)
+        b = fd.greens_batched(probs, s=8, segments=2)
+        assert torch.equal(a[0], b[0])
+        assert all(torch.equal(x, y) for x, y in zip(a[1], b[1]))
+        fa = fd.force_batched(probs, s=8, checkpoint=8, flags=S)
+        fb = fd.force_batched(probs, s=8, checkpoint=8)
+        assert all(torch.equal(x, y) for x, y in zip(fa[0], fb[0]))
