@@ -854,21 +854,32 @@ extern "C" hipError_t FDET_CAT(fdet_launch_items_, FDET_NC)(int kind, const fdet
 
 // Single launch of a whole plan; grid = workgroups that run at once (at
 // most one per item).
+// The single launch is switched off in the entry points (FD_SINGLE_LAUNCH
+// returns FD_ERR_UNSUPPORTED); its kernel is only compiled with
+// -DFDET_SINGLE_LAUNCH_KERNEL.
 extern "C" hipError_t FDET_CAT(fdet_launch_persist_, FDET_NC)(
     const fdet::Prob* probs, const fdet::Item* items, int nitems, const int32_t* deps,
     uint32_t* done, fdet::Sched* sched, uint64_t spin_ticks, int grid, hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
+#ifdef FDET_SINGLE_LAUNCH_KERNEL
   hipLaunchKernelGGL(fdet::k_persist<FDET_NC>, dim3(grid), dim3(fdet::WG), 0, st, probs, items,
                      nitems, deps, done, sched, spin_ticks);
   return hipGetLastError();
+#else
+  (void)probs; (void)items; (void)deps; (void)done; (void)sched; (void)spin_ticks; (void)grid;
+  (void)st;
+  return hipErrorNotSupported;
+#endif
 }
 
 // Workgroups of the single-launch kernel that fit on one compute unit.
 extern "C" int FDET_CAT(fdet_persist_blocks_per_cu_, FDET_NC)(void) {
   int n = 0;
+#ifdef FDET_SINGLE_LAUNCH_KERNEL
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fdet::k_persist<FDET_NC>, fdet::WG, 0) !=
           hipSuccess ||
       n < 1)
+#endif
     n = 1;
   return n;
 }
