@@ -4,8 +4,9 @@
 //   lg_qrp        column-pivoted blocked Householder QR (pivot order refreshed
 //                 per panel, compact WY panels of 16 reflectors, trailing
 //                 updates as MFMA products),
-//   lg_form_q     explicit Q by backward accumulation of the panels,
-//   lg_apply_qh   Y <- Q^H Y, panel by panel,
+//   lg_form_q     explicit Q by backward accumulation of blocks of 64
+//                 reflectors (compact WY, rank-64 MFMA updates),
+//   lg_apply_qh   Y <- Q^H Y, by the same blocks,
 //   lg_backsolve  Y <- R^{-1} Y, blocked by 16 rows.
 //
 // An unblocked QR streams the whole trailing matrix through device memory at
@@ -563,8 +564,138 @@ __device__ void lg_qrp(CMat W, int N, const double* keys, CMat F, double* tst, S
   __syncthreads();
 }
 
-// Q = H_0 ... H_{N-1} explicitly into Q: backward over the panels, each
-// acting on Q(j0:N, j0:N) (columns left of j0 are still unit vectors there).
+// Reflectors per block of the aggregated applications below (four panels).
+constexpr int LG_NB = 64;
+
+// Y(j0:j0+M, ycol0:ycol0+Nc) <- (I - V T' V^H) Y for the block of reflectors
+// j0 .. j0+pw-1 (pw <= LG_NB) as one compact WY product, T' = T (herm false)
+// or T^H (herm true): rank-pw updates instead of one rank-16 pass per panel,
+// so Y is read and written once per 64 reflectors.  T follows from the
+// block's Gram matrix G = V^H V column by column, T(j, j) = beta_j and
+// T(0:j, j) = -beta_j T(0:j, 0:j) G(0:j, j) (the recurrence of the panel T
+// factors, over 64 columns).  Scratch: the raw storage of the free matrix F
+// (2 Np^2 doubles, at least 128 Np + 16384 for Np >= 144): V^H Y and then
+// T' V^H Y at ld 64, T' and G (64 x 64 each, re then im).
+template <int NC>
+__device__ void lg_apply_block(const LgPanel& pn, CMat Y, int ycol0, int M, int Nc, CMat F,
+                               bool herm, SmemC<NC>& S) {
+  const int j0 = pn.j0, pw = pn.pw, Np = F.ld;
+  double* f0r = F.re;
+  double* f0i = F.re + (size_t)LG_NB * Np;
+  double* tgr = F.re + (size_t)2 * LG_NB * Np;
+  double* tgi = tgr + LG_NB * LG_NB;
+  double* ggr = tgi + LG_NB * LG_NB;
+  double* ggi = ggr + LG_NB * LG_NB;
+  auto vh = [&](int i, int k, double& ar, double& ai) {   // V^H (i, k) = conj V(j0 + k, i)
+    double vr, vi;
+    pn.v(j0 + k, i, vr, vi);
+    ar = vr;
+    ai = -vi;
+  };
+  // G = V^H V
+  lg_gemm<64, 64, true, true>(
+      pw, pw, M, vh, [&](int k, int j, double& br, double& bi) { pn.v(j0 + k, j, br, bi); },
+      [&](int i, int j, double cr, double ci) {
+        ggr[j * LG_NB + i] = cr;
+        ggi[j * LG_NB + i] = ci;
+      }, S.big);
+  // T by columns in LDS (the staging area is free between products)
+  double* tr = S.big;
+  double* ti = S.big + LG_NB * LG_NB;
+  for (int e = threadIdx.x; e < LG_NB * LG_NB; e += WG) { tr[e] = 0.0; ti[e] = 0.0; }
+  __syncthreads();
+  // column j of G staged in LDS (two buffers, so one barrier per column)
+  double* gcol = S.lgt;
+  if (threadIdx.x < pw) {
+    gcol[threadIdx.x] = ggr[threadIdx.x];
+    gcol[LG_NB + threadIdx.x] = ggi[threadIdx.x];
+  }
+  __syncthreads();
+  for (int j = 0; j < pw; ++j) {
+    const double bj = S.beta[j0 + j];
+    const double* gc = gcol + (j & 1) * 2 * LG_NB;
+    double* gn = gcol + ((j + 1) & 1) * 2 * LG_NB;
+    if (j + 1 < pw && threadIdx.x >= 256 && threadIdx.x - 256 < pw) {
+      const int k = threadIdx.x - 256;
+      gn[k] = ggr[(j + 1) * LG_NB + k];
+      gn[LG_NB + k] = ggi[(j + 1) * LG_NB + k];
+    }
+    if (threadIdx.x < j) {
+      const int i = threadIdx.x;
+      double sr = 0.0, si = 0.0;
+      for (int k = i; k < j; ++k) {
+        const double a_r = tr[k * LG_NB + i], a_i = ti[k * LG_NB + i];
+        const double b_r = gc[k], b_i = gc[LG_NB + k];
+        sr += a_r * b_r - a_i * b_i;
+        si += a_r * b_i + a_i * b_r;
+      }
+      tr[j * LG_NB + i] = -bj * sr;
+      ti[j * LG_NB + i] = -bj * si;
+    }
+    if (threadIdx.x == j) { tr[j * LG_NB + j] = bj; ti[j * LG_NB + j] = 0.0; }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < LG_NB * LG_NB; e += WG) {
+    const int i = e % LG_NB, k = e / LG_NB;
+    if (!herm) { tgr[e] = tr[e]; tgi[e] = ti[e]; }
+    else { tgr[e] = tr[i * LG_NB + k]; tgi[e] = -ti[i * LG_NB + k]; }
+  }
+  __syncthreads();
+  // F = V^H Y
+  lg_gemm<64, 128, true, true>(
+      pw, Nc, M, vh,
+      [&](int k, int j, double& br, double& bi) {
+        br = Y.r(j0 + k, ycol0 + j);
+        bi = Y.m(j0 + k, ycol0 + j);
+      },
+      [&](int i, int j, double cr, double ci) {
+        f0r[(size_t)j * LG_NB + i] = cr;
+        f0i[(size_t)j * LG_NB + i] = ci;
+      }, S.big);
+  // F <- T' F in place: one macro tile holds all pw rows, and each tile's
+  // columns of F are in registers before the tile is stored
+  lg_gemm<64, 128, true, true>(
+      pw, Nc, pw,
+      [&](int i, int k, double& ar, double& ai) {
+        ar = tgr[k * LG_NB + i];
+        ai = tgi[k * LG_NB + i];
+      },
+      [&](int k, int j, double& br, double& bi) {
+        br = f0r[(size_t)j * LG_NB + k];
+        bi = f0i[(size_t)j * LG_NB + k];
+      },
+      [&](int i, int j, double cr, double ci) {
+        f0r[(size_t)j * LG_NB + i] = cr;
+        f0i[(size_t)j * LG_NB + i] = ci;
+      }, S.big);
+  // Y -= V F
+  lg_gemm_sub<128, 128, true, true>(
+      M, Nc, pw, [&](int i, int k, double& ar, double& ai) { pn.v(j0 + i, k, ar, ai); },
+      [&](int k, int j, double& br, double& bi) {
+        br = f0r[(size_t)j * LG_NB + k];
+        bi = f0i[(size_t)j * LG_NB + k];
+      },
+      [&](int i, int j, double& cr, double& ci) {
+        cr = Y.r(j0 + i, ycol0 + j);
+        ci = Y.m(j0 + i, ycol0 + j);
+      },
+      [&](int i, int j, double cr, double ci) {
+        Y.r(j0 + i, ycol0 + j) = cr;
+        Y.m(j0 + i, ycol0 + j) = ci;
+      }, S.big);
+}
+
+// Whether the free matrix of padded size Np holds lg_apply_block's scratch
+// (Np >= 144, i.e. every N > 128; smaller problems that run this class's
+// code inside a batch use one rank-16 pass per panel instead).
+__device__ __forceinline__ bool lg_block_fits(int Np) {
+  return (size_t)2 * LG_NB * Np + (size_t)4 * LG_NB * LG_NB <= (size_t)2 * Np * Np;
+}
+
+// Q = H_0 ... H_{N-1} explicitly into Q: backward over blocks of 64
+// reflectors (or of 16, see lg_block_fits), each acting on Q(j0:N, j0:N)
+// (columns left of j0 are still unit vectors there, on which the block acts
+// as the identity).
 template <int NC>
 __device__ void lg_form_q(CMat W, int N, CMat Q, CMat F, const double* tst, SmemC<NC>& S) {
   for (int idx = threadIdx.x; idx < N * N; idx += WG) {
@@ -573,22 +704,40 @@ __device__ void lg_form_q(CMat W, int N, CMat Q, CMat F, const double* tst, Smem
     Q.m(i, c) = 0.0;
   }
   __syncthreads();
-  const int np = (N + LG_PW - 1) / LG_PW;
-  for (int p = np - 1; p >= 0; --p) {
-    const int j0 = p * LG_PW, pw = min(LG_PW, N - j0);
-    const LgPanel pn{W, S.u0r, S.u0i, j0, pw, nullptr};
-    lg_apply_panel<NC>(pn, tst + (size_t)p * LG_TDBL, Q, j0, N - j0, N - j0, F, false, nullptr, S);
+  if (lg_block_fits(F.ld)) {
+    const int nb = (N + LG_NB - 1) / LG_NB;
+    for (int b = nb - 1; b >= 0; --b) {
+      const int j0 = b * LG_NB, pw = min(LG_NB, N - j0);
+      const LgPanel pn{W, S.u0r, S.u0i, j0, pw, nullptr};
+      lg_apply_block<NC>(pn, Q, j0, N - j0, N - j0, F, false, S);
+    }
+  } else {
+    const int np = (N + LG_PW - 1) / LG_PW;
+    for (int p = np - 1; p >= 0; --p) {
+      const int j0 = p * LG_PW, pw = min(LG_PW, N - j0);
+      const LgPanel pn{W, S.u0r, S.u0i, j0, pw, nullptr};
+      lg_apply_panel<NC>(pn, tst + (size_t)p * LG_TDBL, Q, j0, N - j0, N - j0, F, false, nullptr, S);
+    }
   }
 }
 
-// Y <- Q^H Y (all N columns), forward over the panels.
+// Y <- Q^H Y (all N columns), forward over the blocks of lg_form_q.
 template <int NC>
 __device__ void lg_apply_qh(CMat W, int N, CMat Y, CMat F, const double* tst, SmemC<NC>& S) {
-  const int np = (N + LG_PW - 1) / LG_PW;
-  for (int p = 0; p < np; ++p) {
-    const int j0 = p * LG_PW, pw = min(LG_PW, N - j0);
-    const LgPanel pn{W, S.u0r, S.u0i, j0, pw, nullptr};
-    lg_apply_panel<NC>(pn, tst + (size_t)p * LG_TDBL, Y, 0, N - j0, N, F, true, nullptr, S);
+  if (lg_block_fits(F.ld)) {
+    const int nb = (N + LG_NB - 1) / LG_NB;
+    for (int b = 0; b < nb; ++b) {
+      const int j0 = b * LG_NB, pw = min(LG_NB, N - j0);
+      const LgPanel pn{W, S.u0r, S.u0i, j0, pw, nullptr};
+      lg_apply_block<NC>(pn, Y, 0, N - j0, N, F, true, S);
+    }
+  } else {
+    const int np = (N + LG_PW - 1) / LG_PW;
+    for (int p = 0; p < np; ++p) {
+      const int j0 = p * LG_PW, pw = min(LG_PW, N - j0);
+      const LgPanel pn{W, S.u0r, S.u0i, j0, pw, nullptr};
+      lg_apply_panel<NC>(pn, tst + (size_t)p * LG_TDBL, Y, 0, N - j0, N, F, true, nullptr, S);
+    }
   }
 }
 
