@@ -1,28 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the stabilised fermion determinant on one MI355X.
 
-Headline: det+G evaluations per second of the low-temperature single
-configuration (honeycomb L = 6, N = 72 sites, N_t = 256, beta = 32, U = 3,
-QR every s = 8 slices).  One step = one complete evaluation: slice
-exponential, stabilised slice chain, time-segment combines, close, log det and
-G, all on inputs already resident in HBM.
-
-The timed region replays a graph captured from a prepared call (the same
-launches as an eager call, exponential included, without the per-call
-descriptor upload); --no-graph times eager calls instead.
+Headline (the largest configuration): one HMC step of 32 auxiliary fields on
+the honeycomb lattice L = 16 (N = 512 sites), N_t = 512, beta = 64, U = 3,
+QR every s = 16 slices, checkpoints every c = 16 slices.  One step = for
+every field: the slice exponential exp(+-dk K), the stabilised checkpoint
+interval products, the prefix / suffix products, log det M, G = M^-1 and the
+full force d log det M / d phi (N_t x N).  The step is a prepared force plan
+(exponential included) captured once in a graph and replayed on inputs
+resident in HBM; `value` counts field evaluations (log det + G + force of one
+field) per second.
 
 Printed as one JSON line, with
-  roofline      the dominant kernel's algorithmic FLOP/s against FP64 MFMA peak,
-                its launch time from HIP events around every kernel phase on
-                the launch stream, in a pass of as many eager evaluations,
-  cpu_baseline  the CPU oracle timed on a bounded sample on the host cores,
-  force         HMC force evals/s (L = 8, N = 128, N_t = 256): checkpointed
-                adjoint (c = 16) against the plain per-slice inversion (c = 1),
-  batched       256 mixed-size configurations: one launch sequence against
-                one configuration per call,
-  hmc_step      the largest configuration: 32 fields of L = 16 (N = 512),
-                N_t = 512, beta = 64; log det, G and force of every field in
-                one replay of a captured graph.
+  roofline      the step's dominant kernel (largest summed launch time per
+                step): model FLOP per launch / average launch time from HIP
+                events around every launch on the launch stream (a pass of
+                eager calls of the same plan) against the FP64 MFMA peak;
+                HBM bytes per launch from committed rocprofv3 counters;
+  cpu_baseline  the CPU oracle on the host cores: its own per-slice steps
+                timed on a bounded sample at N = 512 and scaled to one field;
+and further legs: lowT_L6 (det+G of one N = 72 field, N_t = 256), force
+(N = 128 checkpointed adjoint vs the plain per-slice inversion), batched
+(256 mixed configurations in one launch sequence vs one call per
+configuration), observables and an HMC trajectory.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -41,6 +41,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6e12      # MI355X dense FP64 matrix, FLOP/s
 PEAK_HBM = 8.0e12             # bytes/s
+METRIC = "det+G evals/s & FP64 MFMA %peak; HMC force evals/s, batched/adjoint vs plain"
 
 
 # ---------------------------------------------------------------------------
@@ -63,6 +64,11 @@ def close_flops(N, want_g=True):
     return N ** 3 * (8.0 + 16 / 3 + ((8.0 + 4.0 + 8.0) if want_g else 0.0))
 
 
+def expm_flops(N):
+    """Six real products of the Paterson-Stockmeyer Taylor polynomial."""
+    return 12.0 * N ** 3
+
+
 def alg_det_flops(N, Nt, s):
     """Algorithmic FLOP of one det+G evaluation: N^3 [4 Nt + 14.67 ceil(Nt/s)
     + 33.3] (slices, per-chunk QR / Q / T update, close with G); the one-time
@@ -72,10 +78,10 @@ def alg_det_flops(N, Nt, s):
 
 def det_flops(N, Nt, s, nseg):
     """FLOP the segmented evaluation executes: segment chains, nseg - 1
-    combines, the close with G and the exponential (six real products)."""
+    combines, the close with G and the exponential."""
     bounds = [Nt * k // nseg for k in range(nseg + 1)]
     f = sum(chain_flops(N, bounds[k + 1] - bounds[k], s) for k in range(nseg))
-    return f + (nseg - 1) * combine_flops(N) + close_flops(N) + 12.0 * N ** 3
+    return f + (nseg - 1) * combine_flops(N) + close_flops(N) + expm_flops(N)
 
 
 def alg_force_flops(N, Nt, s, c):
@@ -83,6 +89,14 @@ def alg_force_flops(N, Nt, s, c):
     F_det + N^3 Nt (12 + 14.67/s + 64/c) -- a suffix chain, two products per
     carried slice and a recomputation of G~ at every checkpoint."""
     return alg_det_flops(N, Nt, s) + N ** 3 * Nt * (12.0 + (16 / 3 + 16 / 3 + 4.0) / s + 64.0 / c)
+
+
+def force_item_flops(N, Nt, c, fields):
+    """Model FLOP of the force launch: per checkpoint a stabilised product and
+    a close with G (the checkpoint's G~), and two real x complex products per
+    carried slice (N_t - nc carried slices per field)."""
+    nc = math.ceil(Nt / c)
+    return fields * (nc * (combine_flops(N) + close_flops(N)) + (Nt - nc) * 8.0 * N ** 3)
 
 
 def phase_split(call):
@@ -97,12 +111,8 @@ def phase_split(call):
 
 
 def src_digest():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2604_02130_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
-    return h.hexdigest()[:16]
+    from paper_2604_02130_amd import build
+    return build.source_digest()
 
 
 def traffic_from_profiles(kernel, workload):
@@ -112,11 +122,418 @@ def traffic_from_profiles(kernel, workload):
     try:
         with open(path) as f:
             rec = json.load(f)
-    except OSError:
+    except (OSError, ValueError):
         return None
     if rec.get("src_digest") != src_digest():
         return None
     return rec.get("bytes_per_launch")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def host_threads():
+    try:
+        import threadpoolctl
+        return max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or 1
+    except Exception:
+        return os.cpu_count()
+
+
+# ---------------------------------------------------------------------------
+# headline: the 32-field N = 512 HMC step
+# ---------------------------------------------------------------------------
+
+def headline(args, fd, torch, dev):
+    from workload import hmc_batch
+    hb = hmc_batch(32)
+    w0 = hb[0]
+    N, Nt, s, c = w0.N, w0.Nt, w0.s, w0.c
+    Kh = torch.from_numpy(w0.K()).to(dev)
+    hprobs = [(Kh, torch.from_numpy(wb.phi()).to(dev), wb.dk) for wb in hb]
+    a = time.perf_counter()
+    plan = fd.Plan("force", hprobs, s=s, checkpoint=c, want_g=True)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.launch()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.launch()
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - a
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    log(f"headline set up in {setup:.1f} s; warmup done; timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = plan.status.cpu()
+    if int(st.min()) < 0:
+        raise SystemExit(f"HMC step status {st.tolist()}")
+    ld_graph = plan.ld.clone()
+    step_s = (t1 - t0) / args.steps
+    log(f"HMC step (32 fields, N=512): {step_s:.3f} s")
+
+    # per-launch times from HIP events on the launch stream: eager launches
+    # of the same plan
+    fd.profile_start()
+    reps = 1
+    for _ in range(reps):
+        plan.launch()
+    torch.cuda.synchronize()
+    phases = fd.profile_stop()
+    if not torch.equal(ld_graph, plan.ld):
+        raise SystemExit("graph replay and eager launch disagree")
+    nc = math.ceil(Nt / c)
+    fields = len(hb)
+    per_kind = {}
+    for name, nitems, ms in phases:
+        rec = per_kind.setdefault(name, {"launches": 0, "items": 0, "ms": 0.0})
+        rec["launches"] += 1
+        rec["items"] += nitems
+        rec["ms"] += ms
+    model = {
+        "expm": 2 * fields * expm_flops(N),
+        "chain": fields * nc * chain_flops(N, c, s),
+        "combine": per_kind.get("combine", {"items": 0})["items"] * combine_flops(N),
+        "force": force_item_flops(N, Nt, c, fields) * reps,
+    }
+    for name, rec in per_kind.items():
+        rec["launches"] //= reps
+        rec["items"] //= reps
+        rec["ms_per_step"] = rec.pop("ms") / reps
+        if name in model and rec["ms_per_step"] > 0:
+            rate = model[name] / reps / (rec["ms_per_step"] * 1e-3)
+            rec["model_tflop_s"] = rate / 1e12
+            rec["frac_fp64_mfma_peak"] = rate / PEAK_FP64_MFMA
+    dom = max(per_kind, key=lambda k: per_kind[k]["ms_per_step"])
+    drec = per_kind[dom]
+    avg_ms = drec["ms_per_step"] / drec["launches"]
+    flop_per_launch = model[dom] / reps / drec["launches"]
+    achieved = flop_per_launch / (avg_ms * 1e-3)
+    kernel = f"k_{dom}<512>"
+    roofline = {
+        "bound": "mfma",
+        "kernel": kernel,
+        "achieved": achieved / 1e12,
+        "peak": PEAK_FP64_MFMA / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP64_MFMA,
+        "traffic": traffic_from_profiles(f"k_{dom}", "hmc_L16"),
+        "avg_launch_ms": avg_ms,
+        "model_flop_per_launch": flop_per_launch,
+        "phases_per_step": per_kind,
+    }
+    alg = sum(alg_force_flops(wb.N, wb.Nt, wb.s, wb.c) for wb in hb)
+    result = {
+        "metric": METRIC,
+        "value": fields / step_s,
+        "unit": "det+G+force evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "hmc_L16: 32 auxiliary fields, honeycomb L=16 (N=512), Nt=512, beta=64, "
+                        "kappa=1, U=3, phi~N(0, delta*U) seeds 5000..5031, s=16, c=16; per step and "
+                        "field: exp(+-dk K), log det M, G and the full force dlogdetM/dphi",
+            "fields": fields,
+            "timed": "graph replay of a prepared force plan (exponential included every step)",
+            "parallelism": "single GPU",
+        },
+        "fp64_mfma_pct_peak": 100.0 * alg / step_s / PEAK_FP64_MFMA,
+        "alg_flop_per_step": alg,
+        "roofline": roofline,
+        "setup_s": setup,
+    }
+    del graph, plan
+    torch.cuda.empty_cache()
+    return result, hb
+
+
+def cpu_baseline_hmc(hb):
+    """The oracle's own force method (stabilised prefix and suffix products
+    of single slices, one stabilised inversion per row) timed on a bounded
+    sample of its steps at N = 512 and scaled to one field: 2 N_t slice
+    products and N_t row inversions (row 1 is G, its close gives log det)."""
+    import numpy as np
+    from oracle import fdet_oracle as F
+    w = hb[0]
+    K, phi = w.K(), w.phi()
+    N, Nt = w.N, w.Nt
+    U, e = F._slice_factors(K, w.dk)
+    slices = [F._slice_udv(U, e, np.exp(1j * phi[t])) for t in range(24)]
+    P = F.udv_product(slices[0], F.udv_identity(N))      # warm-up
+    n_prod, t_prod = 0, 0.0
+    a = time.perf_counter()
+    for t in range(1, 21):
+        P = F.udv_product(slices[t], P)
+        n_prod += 1
+    t_prod = (time.perf_counter() - a) / n_prod
+    S = F.udv_product(F.udv_identity(N), slices[23])
+    F.udv_close(F.udv_product(P, S))                    # warm-up
+    n_close = 8
+    a = time.perf_counter()
+    for _ in range(n_close):
+        F.udv_close(F.udv_product(P, S))
+    t_close = (time.perf_counter() - a) / n_close
+    per_field = 2 * Nt * t_prod + Nt * t_close
+    return {
+        "value": 1.0 / per_field,
+        "unit": "det+G+force evals/s",
+        "cores": host_threads(),
+        "kind": "oracle",
+        "sample": f"extrapolated from a timed sample of the oracle's own steps at N={N}: "
+                  f"{n_prod} stabilised single-slice products ({t_prod:.3f} s each) and "
+                  f"{n_close} row inversions (product + close, {t_close:.3f} s each); one field "
+                  f"= 2*{Nt} products + {Nt} inversions = {per_field:.0f} s",
+    }
+
+
+# ---------------------------------------------------------------------------
+# further legs
+# ---------------------------------------------------------------------------
+
+def leg_lowT(args, fd, torch, dev):
+    """det + G of the low-temperature single configuration (N = 72)."""
+    from workload import WORKLOADS
+    w = WORKLOADS["lowT_L6"]
+    N, Nt, s = w.N, w.Nt, w.s
+    Kd = torch.from_numpy(w.K()).to(dev)
+    pd = torch.from_numpy(w.phi()).to(dev)
+    tuned = fd.autotune([(Kd, pd, w.dk)], what="greens", s=s)
+    nseg = tuned["segments"]
+    plan = fd.Plan("greens", [(Kd, pd, w.dk)], s=s, segments=nseg)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.launch()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.launch()
+    for _ in range(5):
+        graph.replay()
+    torch.cuda.synchronize()
+    reps = 50
+    a = time.perf_counter()
+    for _ in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - a) / reps
+    phases = phase_split(plan.launch)
+    per = {}
+    for name, nitems, ms in phases:
+        per.setdefault(name, []).append(ms)
+    out = {
+        "workload": "lowT_L6: honeycomb L=6 (N=72), Nt=256, beta=32, U=3, s=8; log det M and G",
+        "evals_per_s": 1.0 / dt,
+        "ms": dt * 1e3,
+        "segments": nseg,
+        "fp64_mfma_pct_peak": 100.0 * alg_det_flops(N, Nt, s) / dt / PEAK_FP64_MFMA,
+        "phases_ms": {k: v for k, v in per.items()},
+    }
+    if not args.no_cpu:
+        import oracle
+        K, phi = w.K(), w.phi()
+        oracle.sporadic_logdet_greens(K, w.dk, phi, s)
+        n, a = 0, time.perf_counter()
+        while True:
+            oracle.sporadic_logdet_greens(K, w.dk, phi, s)
+            n += 1
+            if time.perf_counter() - a > 5.0:
+                break
+        dtc = time.perf_counter() - a
+        out["cpu_oracle"] = {"evals_per_s": n / dtc, "cores": host_threads(),
+                             "sample": f"{n} det+G evals (QR every {s} slices), {dtc:.1f} s"}
+    log(f"lowT_L6 det+G: {dt * 1e3:.3f} ms")
+    return out
+
+
+def leg_force(fd, torch, dev):
+    from workload import WORKLOADS
+    wf = WORKLOADS["force_L8"]
+    Kf = torch.from_numpy(wf.K()).to(dev)
+    pf = torch.from_numpy(wf.phi()).to(dev)
+    wsf = fd.Workspace()
+    out = {}
+    for label, c, reps in (("adjoint_c16", wf.c, 5), ("plain_c1", 1, 2)):
+        fd.force(Kf, pf, wf.dk, s=wf.s, checkpoint=c, check=False, ws=wsf)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            fd.force(Kf, pf, wf.dk, s=wf.s, checkpoint=c, check=False, ws=wsf)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - a) / reps
+        out[label] = {"force_evals_per_s": 1.0 / dt, "ms": dt * 1e3,
+                      "alg_tflop_s": alg_force_flops(wf.N, wf.Nt, wf.s, 16) / dt / 1e12,
+                      "phases_ms": phase_split(lambda: fd.force(
+                          Kf, pf, wf.dk, s=wf.s, checkpoint=c, check=False, ws=wsf))}
+        log(f"force {label}: {dt * 1e3:.2f} ms")
+    trf = fd.Trajectory(Kf, pf, wf.dk, s=wf.s, checkpoint=wf.c)
+    trf.replay()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(10):
+        trf.replay()
+    torch.cuda.synchronize()
+    out["adjoint_c16"]["graph_ms"] = (time.perf_counter() - a) / 10 * 1e3
+    del trf
+    out["workload"] = "force_L8: honeycomb L=8 (N=128), Nt=256, beta=32, U=3, s=8"
+    out["adjoint_vs_plain"] = out["adjoint_c16"]["force_evals_per_s"] / out["plain_c1"]["force_evals_per_s"]
+    return out
+
+
+def leg_batched(fd, torch, dev):
+    from workload import batched_mix
+    mix = batched_mix()
+    cache = {}
+    probs = []
+    for wb in mix:
+        if wb.L not in cache:
+            cache[wb.L] = torch.from_numpy(wb.K()).to(dev)
+        probs.append((cache[wb.L], torch.from_numpy(wb.phi()).to(dev), wb.dk))
+    wsb = fd.Workspace()
+    fd.greens_batched(probs, s=8, check=False, ws=wsb)
+    torch.cuda.synchronize()
+    reps = 3
+    a = time.perf_counter()
+    for _ in range(reps):
+        fd.greens_batched(probs, s=8, check=False, ws=wsb)
+    torch.cuda.synchronize()
+    dtb = (time.perf_counter() - a) / reps
+    plain = {}
+    # one call per configuration: the library's single-configuration default
+    # segments, and one segment (one sequential chain per call); one warm-up
+    # pass per form
+    for label, seg in (("plain_default_segments", 0), ("plain_one_segment", 1)):
+        for (Kb, pb, dkb) in probs:
+            fd.greens(Kb, pb, dkb, s=8, segments=seg, check=False, ws=wsb)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for (Kb, pb, dkb) in probs:
+            fd.greens(Kb, pb, dkb, s=8, segments=seg, check=False, ws=wsb)
+        torch.cuda.synchronize()
+        plain[label] = time.perf_counter() - a
+    bflops = sum(alg_det_flops(wb.N, wb.Nt, 8) for wb in mix)
+    bphases = phase_split(lambda: fd.greens_batched(probs, s=8, check=False, ws=wsb))
+    log(f"batched {dtb * 1e3:.1f} ms vs plain {plain['plain_default_segments'] * 1e3:.1f} ms "
+        f"(default segments) / {plain['plain_one_segment'] * 1e3:.1f} ms (one segment)")
+    return {
+        "workload": "256 configs, L in {3,5,6,7,8}, Nt in {32..512}, delta=0.125, U=3, s=8",
+        "batched_evals_per_s": len(mix) / dtb,
+        "batched_ms": dtb * 1e3,
+        "plain_default_segments_evals_per_s": len(mix) / plain["plain_default_segments"],
+        "plain_one_segment_evals_per_s": len(mix) / plain["plain_one_segment"],
+        "batched_vs_plain_default_segments": plain["plain_default_segments"] / dtb,
+        "batched_vs_plain_one_segment": plain["plain_one_segment"] / dtb,
+        "fp64_mfma_pct_peak": 100.0 * bflops / dtb / PEAK_FP64_MFMA,
+        "phases_ms": bphases,
+    }
+
+
+def leg_observables(fd, torch, dev):
+    import numpy as np
+    obs = {"workload": "tr((1 - G) A) of one random complex G and A (k_trace_tiles + "
+                       "k_trace_final); algorithmic bytes 2 N^2 x 16 B read"}
+    rng = np.random.default_rng(5)
+    for No in (72, 512):
+        Go = torch.from_numpy(rng.normal(size=(No, No)) + 1j * rng.normal(size=(No, No))).to(dev)
+        Ao = torch.from_numpy(rng.normal(size=(No, No)) + 1j * rng.normal(size=(No, No))).to(dev)
+        wso = fd.Workspace()
+        for _ in range(10):
+            fd.response_trace(Go, Ao, ws=wso)
+        reps = 200
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(reps):
+            fd.response_trace(Go, Ao, ws=wso)
+        ev1.record()
+        torch.cuda.synchronize()
+        us = ev0.elapsed_time(ev1) * 1e3 / reps
+        gr = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fd.response_trace(Go, Ao, ws=wso)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(gr):
+            for _ in range(20):
+                fd.response_trace(Go, Ao, ws=wso)
+        gr.replay()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(10):
+            gr.replay()
+        ev1.record()
+        torch.cuda.synchronize()
+        us_g = ev0.elapsed_time(ev1) * 1e3 / 200
+        del gr
+        nbytes = 2 * No * No * 16
+        obs[f"N{No}"] = {"us_per_call": us, "us_per_call_graph": us_g,
+                         "hbm_gb_s": nbytes / (us_g * 1e-6) / 1e9,
+                         "frac_hbm_peak": nbytes / (us_g * 1e-6) / PEAK_HBM}
+        log(f"response trace N={No}: {us:.1f} us per call, {us_g:.1f} us in a graph")
+    return obs
+
+
+def leg_trajectory(fd, torch, dev):
+    """One leapfrog trajectory of the force_L8 field; the step size keeps the
+    energy error of order one (it grows as eps^2)."""
+    import numpy as np
+    from workload import WORKLOADS
+    wm = WORKLOADS["force_L8"]
+    Km = torch.from_numpy(wm.K()).to(dev)
+    pm = torch.from_numpy(wm.phi()).to(dev)
+    rng = np.random.default_rng(6)
+    pim = torch.from_numpy(rng.standard_normal(wm.phi().shape).reshape(-1)).to(dev)
+    wsm = fd.Workspace()
+    nmd, epsm, dUm = 4, 0.0015, wm.dk * 3.0
+    fd.hmc_leapfrog([(Km, pm, wm.dk)], pim.clone(), dUm, epsm, nmd, s=wm.s, checkpoint=wm.c,
+                    ws=wsm)
+    torch.cuda.synchronize()
+    reps = 3
+    a = time.perf_counter()
+    for _ in range(reps):
+        dHm = fd.hmc_leapfrog([(Km, pm, wm.dk)], pim.clone(), dUm, epsm, nmd, s=wm.s,
+                              checkpoint=wm.c, ws=wsm)
+    torch.cuda.synchronize()
+    dtm = (time.perf_counter() - a) / reps
+    hplan = fd.HmcPlan([(Km, pm, wm.dk)], dUm, epsm, nmd, s=wm.s, checkpoint=wm.c)
+    hplan.pi.copy_(pim)
+    hplan.capture()
+    hplan.replay()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(reps):
+        hplan.replay()
+    torch.cuda.synchronize()
+    dtg = (time.perf_counter() - a) / reps
+    hplan.close()
+    log(f"HMC trajectory (4 steps, N=128): {dtm * 1e3:.1f} ms, graph {dtg * 1e3:.1f} ms, "
+        f"dH {float(dHm[0]):.3f}")
+    return {
+        "workload": f"force_L8 field (N=128, Nt=256, s=8, c=16), leapfrog of {nmd} steps "
+                    f"({nmd + 1} force evaluations), eps={epsm}, dU=delta*U",
+        "ms": dtm * 1e3,
+        "ms_per_force_eval": dtm * 1e3 / (nmd + 1),
+        "graph_ms": dtg * 1e3,
+        "dH": float(dHm[0]),
+    }
 
 
 # ---------------------------------------------------------------------------
@@ -124,15 +541,10 @@ def traffic_from_profiles(kernel, workload):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--segments", type=int, default=0,
-                    help="time segments (0 = chosen by the library's autotuner before timing)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extra", action="store_true", help="skip the force, batched and HMC legs")
-    ap.add_argument("--no-hmc", action="store_true", help="skip the 32-field L=16 HMC step")
-    ap.add_argument("--no-graph", action="store_true",
-                    help="time eager calls instead of the captured evaluation")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--no-extra", action="store_true", help="only the headline")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -143,11 +555,9 @@ def main():
               "is not supported by this single-GPU build", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2604_02130_amd as fd
-    from workload import WORKLOADS, batched_mix, hmc_batch
 
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
@@ -163,383 +573,16 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    # ---------------- headline: det + G of the low-temperature configuration
-    w = WORKLOADS["lowT_L6"]
-    N, Nt, s = w.N, w.Nt, w.s
-    Kd = torch.from_numpy(w.K()).to(dev)
-    pd = torch.from_numpy(w.phi()).to(dev)
-    tuned = None
-    if args.segments > 0:
-        nseg = args.segments
-    else:
-        # set-up, outside the timed region: the autotuner picks the segments
-        # for this shape with s fixed by the workload
-        tuned = fd.autotune([(Kd, pd, w.dk)], what="greens", s=s)
-        nseg = tuned["segments"]
-        print(f"[bench] autotuned segments {nseg} ({tuned['ms']:.3f} ms)", file=sys.stderr,
-              flush=True)
-    ws = fd.Workspace()
-    ld = torch.empty(2, dtype=torch.float64, device=dev)
-    G = torch.empty((N, N, 2), dtype=torch.float64, device=dev)
-    status = torch.empty(1, dtype=torch.int32, device=dev)
-
-    def step():
-        fd.greens(Kd, pd, w.dk, s=s, segments=nseg, check=False, ws=ws, out=(ld, G),
-                  status=status)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    if args.no_graph:
-        timed = step
-    else:
-        # the same launches (exponential, chain, combine levels, close) captured
-        # once from a prepared call and replayed: no descriptor upload and no
-        # host launch path per evaluation
-        plan = fd.Plan("greens", [(Kd, pd, w.dk)], s=s, segments=nseg)
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            plan.launch()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            plan.launch()
-        for _ in range(args.warmup):
-            graph.replay()
-        torch.cuda.synchronize()
-        timed = graph.replay
-    print(f"[bench] warmup done; timing {args.steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        timed()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if not args.no_graph:
-        st_g = int(plan.status.item())
-        if st_g < 0:
-            raise SystemExit(f"status {st_g}: {fd.strerror(st_g)}")
-        ld_g = torch.view_as_complex(plan.ld)[0]
-    # per-phase launch times (HIP events around every phase) from eager calls
-    fd.profile_start()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    phases = fd.profile_stop()
-    st = int(status.item())
-    if st < 0:
-        raise SystemExit(f"status {st}: {fd.strerror(st)}")
-    if not args.no_graph and not torch.equal(ld_g, torch.view_as_complex(ld)):
-        raise SystemExit("graph replay and eager call disagree")
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    evals_per_s = args.steps / (t1 - t0)
-
-    # dominant phase of the step and its model FLOP per launch
-    per_phase = {}
-    for name, nitems, ms in phases:
-        tot, cnt, items = per_phase.get(name, (0.0, 0, nitems))
-        per_phase[name] = (tot + ms, cnt + 1, nitems)
-    bounds = [Nt * k // nseg for k in range(nseg + 1)]
-    phase_flops = {
-        "expm": 12.0 * N ** 3,
-        "chain": sum(chain_flops(N, bounds[k + 1] - bounds[k], s) for k in range(nseg)),
-        "close": close_flops(N),
-    }
-    dom = max(per_phase, key=lambda k: per_phase[k][0])
-    dom_ms = per_phase[dom][0] / per_phase[dom][1]
-    if dom == "combine":
-        launches = per_phase[dom][1] / args.steps
-        combines_per_step = nseg - 1
-        dom_flops = combine_flops(N) * combines_per_step / launches
-    else:
-        dom_flops = phase_flops.get(dom, float("nan"))
-    achieved = dom_flops / (dom_ms * 1e-3)
-    kernel_name = f"k_{dom}"
-    roofline = {
-        "bound": "mfma",
-        "kernel": kernel_name,
-        "achieved": achieved / 1e12,
-        "peak": PEAK_FP64_MFMA / 1e12,
-        "unit": "TFLOP/s",
-        "frac": achieved / PEAK_FP64_MFMA,
-        "traffic": traffic_from_profiles(kernel_name, "lowT_L6"),
-        "avg_launch_ms": dom_ms,
-        "model_flop_per_launch": dom_flops,
-        "phases_ms_per_step": {k: v[0] / args.steps for k, v in per_phase.items()},
-    }
-    step_flops = det_flops(N, Nt, s, nseg)
-    alg_flops = alg_det_flops(N, Nt, s)
-
-    result = {
-        "metric": "det+G evals/s & FP64 MFMA %peak; HMC force evals/s, batched/adjoint vs plain",
-        "value": evals_per_s,
-        "unit": "det+G evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": "lowT_L6: honeycomb L=6 (N=72), Nt=256, beta=32, kappa=1, U=3, "
-                        "phi~N(0, delta*U) seed 2, s=8; log det M and G per step",
-            "segments": nseg,
-            "segments_autotuned": tuned is not None,
-            "timed": "eager calls" if args.no_graph else "graph replay of the prepared call",
-            "parallelism": "single GPU",
-        },
-        "fp64_mfma_pct_peak": 100.0 * alg_flops / (ms_per_step * 1e-3) / PEAK_FP64_MFMA,
-        "alg_flop_per_step": alg_flops,
-        "executed_model_flop_per_step": step_flops,
-        "roofline": roofline,
-    }
-
-    # ---------------- CPU oracle on the host cores (bounded sample)
+    result, hb = headline(args, fd, torch, dev)
     if not args.no_cpu:
-        import oracle
-        try:
-            import threadpoolctl
-            cores = max(i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()) or 1
-        except Exception:
-            cores = os.cpu_count()
-        K, phi = w.K(), w.phi()
-        oracle.sporadic_logdet_greens(K, w.dk, phi, s)      # warm-up
-        n, tc0 = 0, time.perf_counter()
-        while True:
-            oracle.sporadic_logdet_greens(K, w.dk, phi, s)
-            n += 1
-            if time.perf_counter() - tc0 > 10.0:
-                break
-        dt = time.perf_counter() - tc0
-        result["cpu_baseline"] = {
-            "value": n / dt, "unit": "det+G evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} full det+G evals of the same workload (numpy/scipy stabilised "
-                      f"oracle, QR every {s} slices), {dt:.1f} s",
-        }
-        print(f"[bench] cpu oracle: {n / dt:.3f} evals/s", file=sys.stderr, flush=True)
-
-    # ---------------- force leg: checkpointed adjoint vs plain per-slice inversion
+        result["cpu_baseline"] = cpu_baseline_hmc(hb)
+        log(f"cpu oracle: {result['cpu_baseline']['value']:.3e} evals/s (extrapolated)")
     if not args.no_extra:
-        wf = WORKLOADS["force_L8"]
-        Kf = torch.from_numpy(wf.K()).to(dev)
-        pf = torch.from_numpy(wf.phi()).to(dev)
-        wsf = fd.Workspace()
-        out = {}
-        for label, c, reps in (("adjoint_c16", wf.c, 5), ("plain_c1", 1, 2)):
-            fd.force(Kf, pf, wf.dk, s=wf.s, checkpoint=c, check=False, ws=wsf)
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            for _ in range(reps):
-                fd.force(Kf, pf, wf.dk, s=wf.s, checkpoint=c, check=False, ws=wsf)
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - a) / reps
-            out[label] = {"force_evals_per_s": 1.0 / dt, "ms": dt * 1e3,
-                          "alg_tflop_s": alg_force_flops(wf.N, wf.Nt, wf.s, 16) / dt / 1e12,
-                          "phases_ms": phase_split(lambda: fd.force(
-                              Kf, pf, wf.dk, s=wf.s, checkpoint=c, check=False, ws=wsf))}
-            print(f"[bench] force {label}: {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
-        # the adjoint force as a prepared call replayed from a graph (E computed once)
-        trf = fd.Trajectory(Kf, pf, wf.dk, s=wf.s, checkpoint=wf.c)
-        trf.replay()
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        for _ in range(10):
-            trf.replay()
-        torch.cuda.synchronize()
-        out["adjoint_c16"]["graph_ms"] = (time.perf_counter() - a) / 10 * 1e3
-        del trf
-        out["workload"] = "force_L8: honeycomb L=8 (N=128), Nt=256, beta=32, U=3, s=8"
-        out["adjoint_vs_plain"] = out["adjoint_c16"]["force_evals_per_s"] / out["plain_c1"]["force_evals_per_s"]
-        result["force"] = out
-
-        # ---------------- batched leg: 256 mixed configurations
-        mix = batched_mix()
-        cache = {}
-        probs = []
-        for wb in mix:
-            if wb.L not in cache:
-                cache[wb.L] = torch.from_numpy(wb.K()).to(dev)
-            probs.append((cache[wb.L], torch.from_numpy(wb.phi()).to(dev), wb.dk))
-        wsb = fd.Workspace()
-        seg_b = 0   # per-problem segments balanced by chain work
-        fd.greens_batched(probs, s=8, segments=seg_b, check=False, ws=wsb)
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        reps = 3
-        for _ in range(reps):
-            fd.greens_batched(probs, s=8, segments=seg_b, check=False, ws=wsb)
-        torch.cuda.synchronize()
-        dtb = (time.perf_counter() - a) / reps
-        a = time.perf_counter()
-        for (Kb, pb, dkb) in probs:
-            fd.greens(Kb, pb, dkb, s=8, segments=1, check=False, ws=wsb)
-        torch.cuda.synchronize()
-        dtp = time.perf_counter() - a
-        bflops = sum(alg_det_flops(wb.N, wb.Nt, 8) for wb in mix)
-        bphases = phase_split(lambda: fd.greens_batched(probs, s=8, segments=seg_b, check=False,
-                                                        ws=wsb))
-        result["batched"] = {
-            "workload": "256 configs, L in {3,5,6,7,8}, Nt in {32..512}, delta=0.125, U=3, s=8",
-            "batched_evals_per_s": len(mix) / dtb,
-            "plain_evals_per_s": len(mix) / dtp,
-            "batched_vs_plain": dtp / dtb,
-            "batched_ms": dtb * 1e3,
-            "fp64_mfma_pct_peak": 100.0 * bflops / dtb / PEAK_FP64_MFMA,
-            "phases_ms": bphases,
-        }
-        print(f"[bench] batched {dtb * 1e3:.1f} ms vs plain {dtp * 1e3:.1f} ms",
-              file=sys.stderr, flush=True)
-
-        # ---------------- observables: tr((1 - G) A) and n = 1 - tr G / N from G
-        obs = {"workload": "tr((1 - G) A) of one random complex G and A (k_trace_tiles + "
-                           "k_trace_final); algorithmic bytes 2 N^2 x 16 B read"}
-        rng = np.random.default_rng(5)
-        for No in (72, 512):
-            Go = torch.from_numpy(rng.normal(size=(No, No)) + 1j * rng.normal(size=(No, No))).to(dev)
-            Ao = torch.from_numpy(rng.normal(size=(No, No)) + 1j * rng.normal(size=(No, No))).to(dev)
-            wso = fd.Workspace()
-            for _ in range(10):
-                fd.response_trace(Go, Ao, ws=wso)
-            reps = 200
-            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            ev0.record()
-            for _ in range(reps):
-                fd.response_trace(Go, Ao, ws=wso)
-            ev1.record()
-            torch.cuda.synchronize()
-            us = ev0.elapsed_time(ev1) * 1e3 / reps
-            # the same calls replayed from a graph: GPU time without the host
-            # overhead of each Python call
-            gr = torch.cuda.CUDAGraph()
-            side = torch.cuda.Stream()
-            side.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(side):
-                fd.response_trace(Go, Ao, ws=wso)
-            torch.cuda.current_stream().wait_stream(side)
-            torch.cuda.synchronize()
-            with torch.cuda.graph(gr):
-                for _ in range(20):
-                    fd.response_trace(Go, Ao, ws=wso)
-            gr.replay()
-            torch.cuda.synchronize()
-            ev0.record()
-            for _ in range(10):
-                gr.replay()
-            ev1.record()
-            torch.cuda.synchronize()
-            us_g = ev0.elapsed_time(ev1) * 1e3 / 200
-            del gr
-            nbytes = 2 * No * No * 16
-            obs[f"N{No}"] = {"us_per_call": us, "us_per_call_graph": us_g,
-                             "hbm_gb_s": nbytes / (us_g * 1e-6) / 1e9,
-                             "frac_hbm_peak": nbytes / (us_g * 1e-6) / PEAK_HBM}
-            print(f"[bench] response trace N={No}: {us:.1f} us per call, {us_g:.1f} us in a graph",
-                  file=sys.stderr, flush=True)
-        result["observables"] = obs
-
-        # ---------------- HMC molecular dynamics: one leapfrog trajectory
-        wm = WORKLOADS["force_L8"]
-        Km = torch.from_numpy(wm.K()).to(dev)
-        pm = torch.from_numpy(wm.phi()).to(dev)
-        rng = np.random.default_rng(6)
-        pim = torch.from_numpy(rng.standard_normal(wm.phi().shape).reshape(-1)).to(dev)
-        wsm = fd.Workspace()
-        nmd, epsm, dUm = 4, 0.02, wm.dk * 3.0
-        fd.hmc_leapfrog([(Km, pm, wm.dk)], pim, dUm, epsm, nmd, s=wm.s, checkpoint=wm.c, ws=wsm)
-        torch.cuda.synchronize()
-        reps = 3
-        a = time.perf_counter()
-        for _ in range(reps):
-            dHm = fd.hmc_leapfrog([(Km, pm, wm.dk)], pim, dUm, epsm, nmd, s=wm.s,
-                                  checkpoint=wm.c, ws=wsm)
-        torch.cuda.synchronize()
-        dtm = (time.perf_counter() - a) / reps
-        # the same trajectory prepared once and replayed from a captured graph
-        hplan = fd.HmcPlan([(Km, pm, wm.dk)], dUm, epsm, nmd, s=wm.s, checkpoint=wm.c)
-        hplan.pi.copy_(pim)
-        hplan.capture()
-        hplan.replay()
-        torch.cuda.synchronize()
-        a = time.perf_counter()
-        for _ in range(reps):
-            hplan.replay()
-        torch.cuda.synchronize()
-        dtg = (time.perf_counter() - a) / reps
-        hplan.close()
-        result["hmc_trajectory"] = {
-            "workload": "force_L8 field (N=128, Nt=256, s=8, c=16), leapfrog of 4 steps "
-                        "(5 force evaluations), eps=0.02, dU=delta*U",
-            "ms": dtm * 1e3,
-            "ms_per_force_eval": dtm * 1e3 / (nmd + 1),
-            "graph_ms": dtg * 1e3,
-            "last_dH": float(dHm[0]),
-        }
-        print(f"[bench] HMC trajectory (4 steps, N=128): {dtm * 1e3:.1f} ms, "
-              f"graph {dtg * 1e3:.1f} ms", file=sys.stderr, flush=True)
-
-        # ---------------- largest configuration: one HMC step of 32 fields
-        if not args.no_hmc:
-            hb = hmc_batch(32)
-            Kh = torch.from_numpy(hb[0].K()).to(dev)
-            hprobs = [(Kh, torch.from_numpy(wb.phi()).to(dev), wb.dk) for wb in hb]
-            a = time.perf_counter()
-            traj = fd.Trajectory(problems=hprobs, s=hb[0].s, checkpoint=hb[0].c, want_g=True)
-            setup = time.perf_counter() - a
-            traj.replay()
-            torch.cuda.synchronize()
-            reps = 2
-            a = time.perf_counter()
-            for _ in range(reps):
-                traj.replay()
-            torch.cuda.synchronize()
-            dth = (time.perf_counter() - a) / reps
-            st_h = traj.plan.status.cpu()
-            if int(st_h.min()) < 0:
-                raise SystemExit(f"HMC step status {st_h.tolist()}")
-            hflops = sum(alg_force_flops(wb.N, wb.Nt, wb.s, wb.c) for wb in hb)
-            # per-phase model FLOP rates of the same step (one eager call, HIP
-            # events around each launch): chains of c slices with one QR per s,
-            # stabilised products, and per checkpoint item a product, a close
-            # with G and the carried slices (two real x complex products each)
-            del traj
-            hph = phase_split(lambda: fd.force_batched(hprobs, s=hb[0].s, checkpoint=hb[0].c,
-                                                       check=False))
-            Nh, Nth, ch, sh = hb[0].N, hb[0].Nt, hb[0].c, hb[0].s
-            nch = (Nth + ch - 1) // ch
-            model = {
-                "chain": len(hb) * nch * chain_flops(Nh, ch, sh),
-                "force": len(hb) * (nch * (combine_flops(Nh) + close_flops(Nh))
-                                    + (Nth - nch) * 8.0 * Nh ** 3),
-            }
-            hphases = {}
-            for name, nitems, ms in hph:
-                rec = hphases.setdefault(name, {"launches": 0, "items": 0, "ms": 0.0})
-                rec["launches"] += 1
-                rec["items"] += nitems
-                rec["ms"] += ms
-            model["combine"] = hphases.get("combine", {"items": 0})["items"] * combine_flops(Nh)
-            for name, rec in hphases.items():
-                if name in model and rec["ms"] > 0:
-                    rate = model[name] / (rec["ms"] * 1e-3)
-                    rec["model_tflop_s"] = rate / 1e12
-                    rec["frac_fp64_mfma_peak"] = rate / PEAK_FP64_MFMA
-            result["hmc_step"] = {
-                "workload": "32 fields, honeycomb L=16 (N=512), Nt=512, beta=64, U=3, s=16, "
-                            "c=16; log det, G and full force per field in one graph replay",
-                "step_s": dth,
-                "force_evals_per_s": len(hb) / dth,
-                "alg_tflop_s": hflops / dth / 1e12,
-                "fp64_mfma_pct_peak": 100.0 * hflops / dth / PEAK_FP64_MFMA,
-                "setup_s": setup,
-                "phases_eager": hphases,
-            }
-            print(f"[bench] HMC step L16 x32: {dth:.3f} s", file=sys.stderr, flush=True)
-
+        result["lowT_L6"] = leg_lowT(args, fd, torch, dev)
+        result["force"] = leg_force(fd, torch, dev)
+        result["batched"] = leg_batched(fd, torch, dev)
+        result["observables"] = leg_observables(fd, torch, dev)
+        result["hmc_trajectory"] = leg_trajectory(fd, torch, dev)
     print(json.dumps(result), flush=True)
 
 
