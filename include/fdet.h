@@ -71,6 +71,18 @@ enum { FD_WHAT_LOGDET = 0, FD_WHAT_GREENS = 1, FD_WHAT_FORCE = 2, FD_WHAT_UDV = 
                             one launch per phase.  Currently switched off: every
                             call with this flag returns FD_ERR_UNSUPPORTED (one
                             run did not finish; its cause is not known)        */
+#define FD_KEEP_CHECKPOINTS 0x8 /* log det / G leave the UDV checkpoints (the
+                            products of every checkpoint interval and the
+                            prefix / suffix or window products built from
+                            them) in the workspace, which is then sized and
+                            laid out as for FD_WHAT_FORCE; fd_force with this
+                            flag on the same problems, options and workspace
+                            runs only the checkpoint items on them: G~ at each
+                            checkpoint and the carried slices (the autograd
+                            forward / backward pair).  Nothing may use the
+                            workspace in between.  segments are not used (the
+                            checkpoint intervals take their place); not for
+                            fd_udv.                                            */
 #define FD_FORCE_SCANS 0x2 /* force: build the checkpoint products by prefix /
                             suffix scans even where cyclic windows would take
                             fewer rounds (fd_force)                           */
@@ -97,7 +109,8 @@ typedef struct {
                            batch, per problem in proportion to its chain work
                            max(N,32)^2 Nt, so that the batch's chains fill the
                            compute units about once (at most min(32, Nt/4))  */
-  int32_t flags;        /* FD_REUSE_E | FD_FORCE_SCANS (FD_SINGLE_LAUNCH: off) */
+  int32_t flags;        /* FD_REUSE_E | FD_FORCE_SCANS | FD_KEEP_CHECKPOINTS
+                           (FD_SINGLE_LAUNCH: switched off)                    */
 } fd_options;
 
 /* Bytes of workspace needed for `nprob` problems and the given entry point

@@ -30,6 +30,7 @@ FD_WHAT_LOGDET, FD_WHAT_GREENS, FD_WHAT_FORCE, FD_WHAT_UDV, FD_WHAT_HMC = 0, 1, 
 FD_REUSE_E = 0x1
 FD_FORCE_SCANS = 0x2
 FD_SINGLE_LAUNCH = 0x4   # switched off in the library (returns FD_ERR_UNSUPPORTED)
+FD_KEEP_CHECKPOINTS = 0x8
 MAX_N = 512
 
 # exported names (each declared in include/fdet.h)
@@ -274,15 +275,18 @@ def slice_exponential(K, dk, ws: Workspace | None = None):
     return E
 
 
-def logdet(K, phi, dk, s=0, segments=0, flags=0, check=True, ws: Workspace | None = None):
-    """log det(1 + B_{N_t}...B_1) as a complex128 scalar tensor on the device."""
+def logdet(K, phi, dk, s=0, segments=0, flags=0, check=True, ws: Workspace | None = None,
+           checkpoint=0):
+    """log det(1 + B_{N_t}...B_1) as a complex128 scalar tensor on the device.
+    checkpoint: the checkpoint interval when flags has FD_KEEP_CHECKPOINTS."""
     torch = _torch()
     lib = load_library()
     p = _prob(K, phi, dk)
-    o = _opts(s=s, segments=segments, flags=flags)
+    o = _opts(s=s, checkpoint=checkpoint, segments=segments, flags=flags)
     out = torch.empty(2, dtype=torch.float64, device=K.device)
     status = torch.empty(1, dtype=torch.int32, device=K.device)
-    need = workspace_bytes([p], FD_WHAT_LOGDET, s=s, segments=segments, flags=flags)
+    need = workspace_bytes([p], FD_WHAT_LOGDET, s=s, checkpoint=checkpoint, segments=segments,
+                           flags=flags)
     wsp, wsn = (ws or _default_ws).get(need, K.device)
     _check(lib.fd_logdet(ctypes.byref(p), ctypes.byref(o), out.data_ptr(), wsp, wsn,
                          status.data_ptr(), _stream()))
@@ -291,18 +295,20 @@ def logdet(K, phi, dk, s=0, segments=0, flags=0, check=True, ws: Workspace | Non
 
 
 def greens(K, phi, dk, s=0, segments=0, flags=0, check=True, ws: Workspace | None = None,
-           out=None, status=None):
-    """(log det M, G = M^{-1}); G is an N x N complex128 tensor."""
+           out=None, status=None, checkpoint=0):
+    """(log det M, G = M^{-1}); G is an N x N complex128 tensor.
+    checkpoint: the checkpoint interval when flags has FD_KEEP_CHECKPOINTS."""
     torch = _torch()
     lib = load_library()
     p = _prob(K, phi, dk)
     N = p.N
-    o = _opts(s=s, segments=segments, flags=flags)
+    o = _opts(s=s, checkpoint=checkpoint, segments=segments, flags=flags)
     ld = torch.empty(2, dtype=torch.float64, device=K.device) if out is None else out[0]
     G = torch.empty((N, N, 2), dtype=torch.float64, device=K.device) if out is None else out[1]
     if status is None:
         status = torch.empty(1, dtype=torch.int32, device=K.device)
-    need = workspace_bytes([p], FD_WHAT_GREENS, s=s, segments=segments, flags=flags)
+    need = workspace_bytes([p], FD_WHAT_GREENS, s=s, checkpoint=checkpoint, segments=segments,
+                           flags=flags)
     wsp, wsn = (ws or _default_ws).get(need, K.device)
     _check(lib.fd_greens(ctypes.byref(p), ctypes.byref(o), ld.data_ptr(), G.data_ptr(), wsp, wsn,
                          status.data_ptr(), _stream()))
@@ -819,26 +825,37 @@ def _logdet_function():
     class LogDet(torch.autograd.Function):
         """log det M as a differentiable function of phi (K, dk fixed).
 
-        Forward computes log det M; when phi needs a gradient it runs the
-        force path, which yields log det M and F = d log det M / d phi in one
-        pass.  For a real loss L with upstream gradient g = dL/dRe + i dL/dIm,
-        the backward returns g.real * Re F + g.imag * Im F.
+        Forward computes log det M with FD_KEEP_CHECKPOINTS when phi needs a
+        gradient: the UDV products of the checkpoint intervals (and the
+        prefix / suffix or window products built from them) stay in a
+        workspace owned by the autograd context.  Backward runs only the
+        force's checkpoint items on that workspace: G~ at every checkpoint
+        from its two stored factors, then the slices in between carried from
+        it (recomputed, not stored), F = d log det M / d phi.  For a real
+        loss with upstream gradient g = dL/dRe + i dL/dIm the backward
+        returns g.real * Re F + g.imag * Im F.
         """
 
         @staticmethod
         def forward(ctx, phi, K, dk, s, checkpoint):
             if ctx.needs_input_grad[0]:
-                F, ld = force(K, phi.detach(), dk, s=s, checkpoint=checkpoint, with_logdet=True)
-                ctx.save_for_backward(torch.view_as_real(F))
+                ws = Workspace()
+                ld = logdet(K, phi.detach(), dk, s=s, checkpoint=checkpoint,
+                            flags=FD_KEEP_CHECKPOINTS, ws=ws)
+                ctx.save_for_backward(phi)
+                ctx.fd_args = (K, dk, s, checkpoint, ws)
             else:
                 ld = logdet(K, phi.detach(), dk, s=s)
             return ld.clone()
 
         @staticmethod
         def backward(ctx, g):
-            (F,) = ctx.saved_tensors
+            (phi,) = ctx.saved_tensors
+            K, dk, s, checkpoint, ws = ctx.fd_args
+            F = force(K, phi.detach(), dk, s=s, checkpoint=checkpoint,
+                      flags=FD_KEEP_CHECKPOINTS, ws=ws)
             g = g.to(torch.complex128)
-            return g.real * F[..., 0] + g.imag * F[..., 1], None, None, None, None
+            return g.real * F.real + g.imag * F.imag, None, None, None, None
 
     return LogDet
 

@@ -650,8 +650,12 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   pl.probs.assign(nprob, Prob{});
   pl.maxN = 0;
   size_t nitems = 0;
-  // count items to size the descriptor region
-  const bool force = what == FD_WHAT_FORCE;
+  // count items to size the descriptor region.  With FD_KEEP_CHECKPOINTS
+  // every call uses the force layout: log det / G run its first phases and
+  // leave the checkpoint products in the workspace, the force then runs only
+  // the checkpoint items on them.
+  const bool keep = (o.flags & FD_KEEP_CHECKPOINTS) != 0;
+  const bool force = what == FD_WHAT_FORCE || keep;
   std::vector<int> nseg = plan_segments(p, nprob, o), nck(nprob);
   const int sgroup = force ? force_schedule(p, nprob, o) : 1;
   pl.units.assign(nprob, 0);
@@ -856,6 +860,17 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
       // G~ is then formed twice, the carries run side by side).
       const bool split = 2 * nforce <= (size_t)device_cu_count();
       const int last_gap = q.Nt - (nc - 1) * o.c;
+      if (keep && what != FD_WHAT_FORCE) {
+        // log det (and G) of the whole product C_0 = M - 1: checkpoint 0's
+        // item without carried rows
+        Item f = blank_item(fdet::IK_FORCE, i);
+        f.a = left[0];
+        f.b = right[0];
+        f.scr = sf[0];
+        f.flags = fdet::IF_OUT_LOGDET | (what == FD_WHAT_GREENS ? fdet::IF_OUT_G : 0);
+        forcei.push_back(f);
+        continue;
+      }
       for (int k = 0; k < nc; ++k) {
         Item f = blank_item(fdet::IK_FORCE, i);
         const int gap_fwd = (k + 1 < nc) ? o.c : last_gap;
@@ -888,12 +903,17 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   std::stable_sort(chain.begin(), chain.end(),
                    [&](const Item& a, const Item& b) { return work(a) > work(b); });
   pl.phases.clear();
-  if (!expm.empty()) pl.phases.push_back(expm);
-  pl.phases.push_back(chain);
-  for (auto& c : comb)
-    if (!c.empty()) pl.phases.push_back(c);
-  if (!close.empty()) pl.phases.push_back(close);
-  if (!forcei.empty()) pl.phases.push_back(forcei);
+  if (keep && what == FD_WHAT_FORCE) {
+    // the checkpoint products are in the workspace from the log det call
+    pl.phases.push_back(forcei);
+  } else {
+    if (!expm.empty()) pl.phases.push_back(expm);
+    pl.phases.push_back(chain);
+    for (auto& c : comb)
+      if (!c.empty()) pl.phases.push_back(c);
+    if (!close.empty()) pl.phases.push_back(close);
+    if (!forcei.empty()) pl.phases.push_back(forcei);
+  }
   size_t n = 0;
   for (auto& ph : pl.phases) n += ph.size();
   if (n > pl.item_cap) {   // the counting pass above must cover every item
@@ -911,7 +931,7 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   pl.deps_off = cur.off;
   cur.take(sizeof(int32_t) * std::max<size_t>(1, pl.deps.size()));
   pl.done_off = cur.off;
-  cur.take(sizeof(uint32_t) * std::max<size_t>(1, n));
+  cur.take(sizeof(uint32_t) * std::max<size_t>(1, pl.item_cap));   // the same for every phase subset
   pl.sched_off = cur.off;
   cur.take(sizeof(fdet::Sched));
   pl.tail_bytes = cur.off - pl.tail_off;
@@ -1287,6 +1307,8 @@ int fd_force(const fd_problem* p, const fd_options* o, double* logdet, double* f
 int fd_udv(const fd_problem* p, const fd_options* o, double* X, double* D, double* T, void* ws,
            size_t ws_bytes, int32_t* status, void* stream) {
   if (!X || !D || !T) return fail(FD_ERR_INVALID_ARG, "X, D and T must be device pointers");
+  if (o && (o->flags & FD_KEEP_CHECKPOINTS))
+    return fail(FD_ERR_INVALID_ARG, "fd_udv does not keep checkpoints");
   Outs out;
   out.X = X;
   out.D = D;

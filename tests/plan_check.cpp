@@ -204,6 +204,32 @@ int main() {
     bad += check(nm, {prob(72, ns_nt, 0.1)}, o, FD_WHAT_LOGDET, false);
     bad += check(nm, std::vector<fd_problem>(7, prob(40, ns_nt, 0.1)), o, FD_WHAT_GREENS, false);
   }
+  // FD_KEEP_CHECKPOINTS: the force call's items read only workspace slots
+  // that the log det call's items write (same layout), and E / E^-1
+  for (int nt : {16, 90, 256}) for (int c : {4, 16}) for (int sc : {0, (int)FD_FORCE_SCANS}) {
+    fd_options ok{4, c, 0, FD_KEEP_CHECKPOINTS | sc};
+    std::vector<fd_problem> v = {prob(72, nt, 0.1), prob(18, nt / 2 + 1, 0.1)};
+    Opts oo = resolve(&ok, v.data(), 2, FD_WHAT_FORCE);
+    Plan fw, bw;
+    build_plan(v.data(), 2, oo, FD_WHAT_LOGDET, (char*)0x10000000, fw);
+    build_plan(v.data(), 2, oo, FD_WHAT_FORCE, (char*)0x10000000, bw);
+    std::set<const void*> written;
+    for (auto& ph : fw.phases) for (auto& it : ph) {
+      if (it.kind == fdet::IK_CHAIN) written.insert(it.a.X);
+      if (it.kind == fdet::IK_COMBINE) written.insert(it.o.X ? it.o.X : it.a.X);
+      if (it.kind == fdet::IK_EXPM) written.insert(it.sign > 0 ? (const void*)fw.probs[it.prob].E : (const void*)fw.probs[it.prob].Einv);
+    }
+    int b = 0;
+    if (bw.phases.size() != 1 || bw.total != fw.total) b++;
+    for (auto& it : bw.phases.front()) {
+      if (it.kind != fdet::IK_FORCE) b++;
+      if (!written.count(it.a.X) || !written.count(it.b.X)) b++;
+      if (!written.count(bw.probs[it.prob].E) || !written.count(bw.probs[it.prob].Einv)) b++;
+    }
+    printf("keep Nt=%d c=%d scans=%d: %zu forward phases, %zu force items %s\n", nt, c, sc ? 1 : 0,
+           fw.phases.size(), bw.phases.front().size(), b ? "BAD" : "ok");
+    bad += b;
+  }
   // random batches of every kind
   {
     std::mt19937 g(12345);

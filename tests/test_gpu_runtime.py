@@ -263,3 +263,36 @@ def test_single_launch_matches_phase_launches(fd, case):
         fa = fd.force_batched(probs, s=8, checkpoint=8, flags=S)
         fb = fd.force_batched(probs, s=8, checkpoint=8)
         assert all(torch.equal(x, y) for x, y in zip(fa[0], fb[0]))
+
+
+# ---------------------------------------------------------------------------
+# FD_KEEP_CHECKPOINTS: log det keeps the checkpoints, the force reuses them
+# ---------------------------------------------------------------------------
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("L,Nt,beta,s,c,scans", [(3, 64, 8.0, 4, 8, False), (2, 90, 9.0, 4, 4, True),
+                                                 (6, 256, 32.0, 8, 16, False), (9, 32, 4.0, 4, 8, False)])
+def test_keep_checkpoints_matches_full_force(fd, L, Nt, beta, s, c, scans):
+    """fd_logdet with FD_KEEP_CHECKPOINTS, then fd_force with it on the same
+    workspace (only the checkpoint items run), gives the bits of one full
+    fd_force call: log det, G and every force row; fd_greens with the flag
+    gives the force plan's G."""
+    import torch
+    K = honeycomb_hopping(L)
+    dk = beta / Nt
+    phi = sample_phi(2200 + L, Nt, K.shape[0], dk, 3.0)
+    Kd, pd = to_dev(K), to_dev(phi)
+    flags = fd.FD_FORCE_SCANS if scans else 0
+    keep = flags | fd.FD_KEEP_CHECKPOINTS
+    F_full, ld_full = fd.force(Kd, pd, dk, s=s, checkpoint=c, flags=flags, with_logdet=True)
+    ws = fd.Workspace()
+    ld_keep = fd.logdet(Kd, pd, dk, s=s, checkpoint=c, flags=keep, ws=ws)
+    F_keep, ld_again = fd.force(Kd, pd, dk, s=s, checkpoint=c, flags=keep, ws=ws, with_logdet=True)
+    assert torch.equal(ld_keep, ld_full) and torch.equal(ld_again, ld_full)
+    assert torch.equal(F_keep, F_full)
+    lg, G = fd.greens(Kd, pd, dk, s=s, checkpoint=c, flags=keep)
+    plan = fd.Plan("force", [(Kd, pd, dk)], s=s, checkpoint=c, want_g=True, flags=flags)
+    plan.launch()
+    assert torch.equal(G, plan.greens()[0]) and torch.equal(lg, ld_full)
+    lo, Go = O.stabilised_logdet_greens(K, dk, phi)
+    assert np.abs(G.cpu().numpy() - Go).max() <= 1e-10 * max(1.0, np.abs(Go).max())
