@@ -24,6 +24,9 @@ from .fdet_oracle import (  # noqa: F401
     logdet_close,
     response_trace,
     diag_response,
+    displaced_split,
+    bruteforce_displaced_greens,
+    displaced_greens,
     hmc_hamiltonian,
     hmc_leapfrog,
 )
@@ -32,5 +35,6 @@ from .closed_form import (  # noqa: F401
     uniform_field_logdet,
     uniform_field_greens,
     uniform_field_force,
+    uniform_field_displaced_greens,
     two_site,
 )

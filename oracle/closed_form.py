@@ -153,3 +153,32 @@ def two_site(dk: float, phi) -> tuple:
         gt, _ = _inv_one_plus2(c)
         force.append([1j * (1.0 - gt[0][0]), 1j * (1.0 - gt[1][1])])
     return logdet, np.array(g, dtype=complex), np.array(force, dtype=complex)
+
+
+def uniform_field_displaced_greens(K: np.ndarray, dk: float, c, t: int, t0: int) -> np.ndarray:
+    """G(t, t0) for a field constant in space, phi_{t,x} = c_t (every slice
+    is e^{i c_t} E and the slices commute): with theta = sum c and, for
+    t >= t0, the n = t - t0 slices of rows t0-1 .. t-2 carrying phase a,
+        G(t, t0) = U diag(e^{i a} e^{dk lam n} / (1 + e^{i theta} e^{dk lam N_t})) U^T,
+    and for t < t0, with n = t0 - t slices of rows t-1 .. t0-2 carrying a,
+        G(t, t0) = -U diag(e^{i (theta - a)} e^{dk lam (N_t - n)}
+                             / (1 + e^{i theta} e^{dk lam N_t})) U^T,
+    K = U diag(lam) U^T (numpy.linalg.eigh).  Each fraction is evaluated in
+    the form that cannot overflow."""
+    c = np.asarray(c, dtype=float)
+    Nt = len(c)
+    theta = float(c.sum())
+    lam, U = np.linalg.eigh(K)
+    if t >= t0:
+        n, a, pre = t - t0, float(c[t0 - 1:t - 1].sum()), 1.0
+        m = n
+    else:
+        n = t0 - t
+        a, pre = theta - float(c[t - 1:t0 - 1].sum()), -1.0
+        m = Nt - n
+    x = dk * lam
+    big = x > 0
+    num = np.where(big, np.exp(x * (m - Nt)), np.exp(x * m))
+    den = np.where(big, np.exp(-x * Nt) + np.exp(1j * theta), 1.0 + np.exp(1j * theta) * np.exp(x * Nt))
+    d = pre * np.exp(1j * a) * num / den
+    return (U * d[None, :]) @ U.T

@@ -410,3 +410,71 @@ def diag_response(F, a=None):
     Nt, N = F.shape
     w = np.full(N, 1.0 / N) if a is None else np.asarray(a, dtype=float)
     return complex(np.sum((-1j * F) @ w) / Nt)
+
+
+# ---------------------------------------------------------------------------
+# time-displaced Green's function (Sec. 4, matrix element derivatives,
+# eq. sausage_all_in_denominator; Sec. 7 steps 7-9)
+# ---------------------------------------------------------------------------
+# G(t, t0) is block (t, t0) of the inverse of the block fermion matrix
+# (1-based slice labels, G(1, 1) = G).  With P the product of the slices
+# from row r = t-1 up to (not including) row r0 = t0-1, cyclically, and Q the
+# product of the remaining slices from row r0 on (later slices to the left):
+#     t >= t0:  G(t, t0) = + (P + Q^{-1})^{-1},  P = B_{t0-1}...B_1 B_{N_t}...B_t,
+#                                               Q = B_{t-1}...B_{t0}
+#     t <  t0:  G(t, t0) = - (P + Q^{-1})^{-1},  P = B_{t0-1}...B_t,
+#                                               Q = B_{t-1}...B_1 B_{N_t}...B_{t0}
+# (for t = t0, P is the whole cyclic product from row r and Q = 1).  These
+# are eq. sausage_all_in_denominator in the time order of this oracle.
+
+def displaced_split(Nt: int, t: int, t0: int):
+    """(P rows start, P length, Q rows start, Q length, sign) for G(t, t0);
+    rows are 0-based and taken cyclically."""
+    if not (1 <= t <= Nt and 1 <= t0 <= Nt):
+        raise ValueError("t and t0 must lie in [1, N_t]")
+    r, r0 = t - 1, t0 - 1
+    lp = (r0 - r) % Nt
+    if lp == 0:
+        lp = Nt
+    return r, lp, r0, Nt - lp, (-1.0 if t < t0 else 1.0)
+
+
+def bruteforce_displaced_greens(K, dk, phi, t, t0):
+    """G(t, t0): block (t-1, t0-1) of the inverse block fermion matrix (tier 1)."""
+    Mb = block_fermion_matrix(K, dk, phi)
+    N = phi.shape[1]
+    Minv = np.linalg.inv(Mb)
+    return Minv[(t - 1) * N:t * N, (t0 - 1) * N:t0 * N].copy()
+
+
+def _udv_of_rows(U, e, phi, start, length):
+    """UDV of the product of `length` slices from row `start` on, cyclically
+    (later rows to the left), one uncontracted slice at a time (Sec. 7)."""
+    Nt, N = phi.shape
+    P = udv_identity(N)
+    for q in range(length):
+        row = (start + q) % Nt
+        P = udv_product(_slice_udv(U, e, np.exp(1j * phi[row])), P)
+    return P
+
+
+def displaced_greens(K, dk, phi, t, t0):
+    """G(t, t0) by Sec. 7 steps 7-9: P = X' D' Y'^-1 and
+    Q^-1 = Y'' D''^-1 X''^-1 (here from Q = X_Q D_Q Y_Q^-1: Y'' = Y_Q,
+    D''^-1 = D_Q^-1, X'' = X_Q); pivoted QR of
+    D' (Y'^-1 X'') + (X'^-1 Y'') D''^-1 = Q R; then
+    (P + Q^-1)^-1 = X'' R^-1 Q^H X'^-1 (pivot permutation applied to the rows
+    of R^-1), times the sign of the split."""
+    Nt, N = phi.shape
+    ps, pl, qs, ql, sign = displaced_split(Nt, t, t0)
+    U, e = _slice_factors(K, dk)
+    Xp, Dp, Ypinv = _udv_of_rows(U, e, phi, ps, pl)
+    Xq, Dq, Yqinv = _udv_of_rows(U, e, phi, qs, ql)
+    Yq = np.linalg.inv(Yqinv)
+    mid = Dp[:, None] * (Ypinv @ Xq) + (Xp.conj().T @ Yq) / Dq[None, :]
+    Qm, R, piv = sla.qr(mid, pivoting=True)
+    # mid[:, piv] = Qm R  =>  mid^-1 = Pi R^-1 Qm^H with (Pi v)[piv] = v
+    Z = sla.solve_triangular(R, Qm.conj().T @ Xp.conj().T, lower=False)
+    Y = np.empty_like(Z)
+    Y[piv, :] = Z
+    return sign * (Xq @ Y)

@@ -481,3 +481,118 @@ def test_md_pins_catch_planted_mistakes(monkeypatch):
         d2 = fo.hmc_leapfrog(K, dk, phi, pi, dU, 0.02, 10)[2]
         assert not (abs(d1) < 0.05 and 0.18 <= abs(d2 / d1) <= 0.32), (d1, d2)
     monkeypatch.undo()
+
+
+# ---------------------------------------------------------------------------
+# time-displaced Green's function G(t, t0) (eq. sausage_all_in_denominator,
+# Sec. 7 steps 7-9)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("beta", [1.5, 6.0])
+def test_displaced_matches_block_inverse_every_pair(beta):
+    """Every (t, t0) block of the inverse block fermion matrix (L = 2,
+    N_t = 12), including both signs of t - t0 and t = t0."""
+    K = honeycomb_hopping(2)
+    Nt = 12
+    dk = beta / Nt
+    phi = sample_phi(31, Nt, 8, dk, 3.0)
+    Minv = np.linalg.inv(O.block_fermion_matrix(K, dk, phi))
+    for t in range(1, Nt + 1):
+        for t0 in range(1, Nt + 1):
+            Gb = Minv[(t - 1) * 8:t * 8, (t0 - 1) * 8:t0 * 8]
+            G = O.displaced_greens(K, dk, phi, t, t0)
+            assert np.abs(G - Gb).max() <= 1e-12 * max(1.0, np.abs(Gb).max()), (t, t0)
+
+
+def test_displaced_block_inverse_helper():
+    K = honeycomb_hopping(2)
+    phi = sample_phi(32, 6, 8, 0.2, 3.0)
+    Minv = np.linalg.inv(O.block_fermion_matrix(K, 0.2, phi))
+    assert np.array_equal(O.bruteforce_displaced_greens(K, 0.2, phi, 4, 2), Minv[24:32, 8:16])
+
+
+def test_displaced_split_ranges():
+    """P and Q cover the N_t slices once; P starts at row t - 1."""
+    for Nt in (1, 2, 7):
+        for t in range(1, Nt + 1):
+            for t0 in range(1, Nt + 1):
+                ps, pl, qs, ql, sg = O.displaced_split(Nt, t, t0)
+                assert ps == t - 1 and qs == t0 - 1 and pl + ql == Nt and pl >= 1
+                assert sg == (-1.0 if t < t0 else 1.0)
+                rows = {(ps + q) % Nt for q in range(pl)} | {(qs + q) % Nt for q in range(ql)}
+                assert rows == set(range(Nt))
+
+
+def test_displaced_equal_time_is_shifted_greens():
+    """G(t, t) is the equal-time Green's function of the field rotated to start
+    at slice t; G(1, 1) = G."""
+    K = honeycomb_hopping(3)
+    Nt, beta = 40, 8.0
+    dk = beta / Nt
+    phi = sample_phi(33, Nt, 18, dk, 3.0)
+    _, G = O.stabilised_logdet_greens(K, dk, phi)
+    assert np.abs(O.displaced_greens(K, dk, phi, 1, 1) - G).max() <= 1e-12
+    _, Gt = O.stabilised_logdet_greens(K, dk, np.roll(phi, -9, axis=0))
+    assert np.abs(O.displaced_greens(K, dk, phi, 10, 10) - Gt).max() <= 1e-12
+
+
+def test_displaced_row_step():
+    """Rows of the block inverse obey the fermion matrix: for t0 != t + 1,
+    G(t + 1, t0) = B_t G(t, t0) (B_t the slice between t and t + 1), and
+    G(1, t0) = -B_{N_t} G(N_t, t0) across the anti-periodic boundary."""
+    K = honeycomb_hopping(3)
+    Nt, beta = 24, 12.0
+    dk = beta / Nt
+    phi = sample_phi(34, Nt, 18, dk, 3.0)
+    B = O.slice_matrices(K, dk, phi)
+    for t0 in (1, 9, 24):
+        for t in range(1, Nt):
+            if t + 1 == t0:
+                continue
+            G1 = O.displaced_greens(K, dk, phi, t + 1, t0)
+            G0 = O.displaced_greens(K, dk, phi, t, t0)
+            assert np.abs(G1 - B[t - 1] @ G0).max() <= 1e-11 * max(1.0, np.abs(G1).max()), (t, t0)
+        if t0 != 1:
+            G1 = O.displaced_greens(K, dk, phi, 1, t0)
+            GN = O.displaced_greens(K, dk, phi, Nt, t0)
+            assert np.abs(G1 + B[Nt - 1] @ GN).max() <= 1e-11 * max(1.0, np.abs(G1).max())
+
+
+@pytest.mark.parametrize("t,t0", [(1, 1), (200, 17), (17, 200), (256, 1), (1, 256), (129, 128)])
+def test_displaced_uniform_closed_form_low_temperature(t, t0):
+    """Space-uniform field at beta = 32 (cond of the slice product ~ 1e41):
+    the stabilised form against the eigenbasis closed form."""
+    L, Nt, beta = 3, 256, 32.0
+    K = honeycomb_hopping(L)
+    dk = beta / Nt
+    c = np.random.default_rng(2).normal(0, 0.6, Nt)
+    phi = uniform_phi(c, 18)
+    Gc = O.uniform_field_displaced_greens(K, dk, c, t, t0)
+    G = O.displaced_greens(K, dk, phi, t, t0)
+    assert np.abs(G - Gc).max() <= 1e-11
+
+
+def test_displaced_pins_catch_planted_mistakes(monkeypatch):
+    """A wrong sign for t < t0 or P and Q swapped fail the block inverse."""
+    from oracle import fdet_oracle as F
+    K = honeycomb_hopping(2)
+    Nt, dk = 6, 0.25
+    phi = sample_phi(35, Nt, 8, dk, 3.0)
+    Minv = np.linalg.inv(O.block_fermion_matrix(K, dk, phi))
+
+    def worst():
+        e = 0.0
+        for t in range(1, Nt + 1):
+            for t0 in range(1, Nt + 1):
+                Gb = Minv[(t - 1) * 8:t * 8, (t0 - 1) * 8:t0 * 8]
+                e = max(e, np.abs(F.displaced_greens(K, dk, phi, t, t0) - Gb).max())
+        return e
+
+    assert worst() < 1e-12
+    orig = F.displaced_split
+    monkeypatch.setattr(F, "displaced_split",
+                        lambda n, t, t0: orig(n, t, t0)[:4] + (1.0,))
+    assert worst() > 1e-3
+    monkeypatch.setattr(F, "displaced_split",
+                        lambda n, t, t0: (lambda r: (r[2], r[3], r[0], r[1], r[4]))(orig(n, t, t0)))
+    assert worst() > 1e-3
