@@ -27,6 +27,7 @@ from .fdet_oracle import (  # noqa: F401
     displaced_split,
     bruteforce_displaced_greens,
     displaced_greens,
+    dsplit_displaced_greens,
     hmc_hamiltonian,
     hmc_leapfrog,
 )

@@ -478,3 +478,25 @@ def displaced_greens(K, dk, phi, t, t0):
     Y = np.empty_like(Z)
     Y[piv, :] = Z
     return sign * (Xq @ Y)
+
+
+def dsplit_displaced_greens(K, dk, phi, t, t0):
+    """G(t, t0) from the same two chains as displaced_greens, closed with the
+    scales split (an algebraic identity, not from the paper).  With
+    P = X_P D_P T_P, Q = X_Q D_Q T_Q, D_b = max(D, 1) and D_s = min(D, 1):
+        P + Q^-1 = X_P D_Pb W D_Qs^-1 X_Q^H,
+        W = D_Ps (T_P X_Q) D_Qs + D_Pb^-1 (X_P^H T_Q^-1) D_Qb^-1,
+    so G(t, t0) = sign X_Q D_Qs W^-1 D_Pb^-1 X_P^H.  Every factor of W is
+    at most one in size, so no row or column of it mixes scales; the
+    unsplit middle matrix of Sec. 7 step 8 does, and loses digits at low
+    temperature when both chains are long."""
+    Nt, N = phi.shape
+    ps, pl, qs, ql, sign = displaced_split(Nt, t, t0)
+    U, e = _slice_factors(K, dk)
+    Xp, Dp, Tp = _udv_of_rows(U, e, phi, ps, pl)
+    Xq, Dq, Tq = _udv_of_rows(U, e, phi, qs, ql)
+    Dpb, Dps = np.maximum(Dp, 1.0), np.minimum(Dp, 1.0)
+    Dqb, Dqs = np.maximum(Dq, 1.0), np.minimum(Dq, 1.0)
+    W = (Dps[:, None] * (Tp @ Xq) * Dqs[None, :]
+         + (Xp.conj().T @ np.linalg.inv(Tq)) / (Dpb[:, None] * Dqb[None, :]))
+    return sign * (Xq * Dqs[None, :]) @ np.linalg.solve(W, Xp.conj().T / Dpb[:, None])

@@ -5,6 +5,7 @@ fermion matrix (paper Sec. 2), the momentum-space closed form of the uniform
 field, the textbook single-slice determinant, finite differences, and exact
 symmetries of the honeycomb model.
 """
+import functools
 import math
 
 import numpy as np
@@ -592,6 +593,87 @@ def test_displaced_pins_catch_planted_mistakes(monkeypatch):
     orig = F.displaced_split
     monkeypatch.setattr(F, "displaced_split",
                         lambda n, t, t0: orig(n, t, t0)[:4] + (1.0,))
+    assert worst() > 1e-3
+    monkeypatch.setattr(F, "displaced_split",
+                        lambda n, t, t0: (lambda r: (r[2], r[3], r[0], r[1], r[4]))(orig(n, t, t0)))
+    assert worst() > 1e-3
+
+
+@functools.lru_cache(maxsize=None)
+def _low_temperature_block_inverse():
+    """L = 2, N_t = 128, beta = 32: the block inverse (dimension 1024) and the
+    field, shared by the low-temperature displaced pins."""
+    K = honeycomb_hopping(2)
+    Nt, beta = 128, 32.0
+    dk = beta / Nt
+    phi = sample_phi(8, Nt, 8, dk, 3.0)
+    return K, dk, phi, np.linalg.inv(O.block_fermion_matrix(K, dk, phi))
+
+
+@pytest.mark.parametrize("t,t0", [(1, 1), (70, 3), (3, 70), (128, 1), (1, 128), (40, 39), (39, 40)])
+def test_dsplit_displaced_matches_block_inverse_low_temperature(t, t0):
+    """The split close of G(t, t0) against the block inverse at beta = 32,
+    random field, both chains long."""
+    K, dk, phi, Minv = _low_temperature_block_inverse()
+    Gb = Minv[(t - 1) * 8:t * 8, (t0 - 1) * 8:t0 * 8]
+    G = O.dsplit_displaced_greens(K, dk, phi, t, t0)
+    assert np.abs(G - Gb).max() <= 1e-12 * max(1.0, np.abs(Gb).max()), (t, t0)
+
+
+def test_unsplit_displaced_close_loses_digits_at_low_temperature():
+    """The middle matrix of Sec. 7 step 8 taken as written mixes scales in
+    its rows and columns: at beta = 32 with both chains long it is off the
+    block inverse by far more than rounding, while the split close is not
+    (the reason the GPU path and the low-temperature parity reference use
+    the split form)."""
+    K, dk, phi, Minv = _low_temperature_block_inverse()
+    Gb = Minv[69 * 8:70 * 8, 2 * 8:3 * 8]
+    assert np.abs(O.displaced_greens(K, dk, phi, 70, 3) - Gb).max() > 1e-9
+    assert np.abs(O.dsplit_displaced_greens(K, dk, phi, 70, 3) - Gb).max() < 1e-12
+
+
+def test_dsplit_displaced_every_pair_and_closed_form():
+    """Every pair at L = 2, N_t = 12, beta = 6 against the block inverse, and
+    the uniform-field closed form at beta = 32."""
+    K = honeycomb_hopping(2)
+    Nt, dk = 12, 0.5
+    phi = sample_phi(31, Nt, 8, dk, 3.0)
+    Minv = np.linalg.inv(O.block_fermion_matrix(K, dk, phi))
+    for t in range(1, Nt + 1):
+        for t0 in range(1, Nt + 1):
+            Gb = Minv[(t - 1) * 8:t * 8, (t0 - 1) * 8:t0 * 8]
+            G = O.dsplit_displaced_greens(K, dk, phi, t, t0)
+            assert np.abs(G - Gb).max() <= 1e-12 * max(1.0, np.abs(Gb).max()), (t, t0)
+    K = honeycomb_hopping(3)
+    Nt, beta = 256, 32.0
+    dk = beta / Nt
+    c = np.random.default_rng(2).normal(0, 0.6, Nt)
+    phi = uniform_phi(c, 18)
+    for t, t0 in [(200, 17), (17, 200), (1, 1)]:
+        Gc = O.uniform_field_displaced_greens(K, dk, c, t, t0)
+        assert np.abs(O.dsplit_displaced_greens(K, dk, phi, t, t0) - Gc).max() <= 1e-11
+
+
+def test_dsplit_displaced_catches_planted_mistakes(monkeypatch):
+    """A wrong sign for t < t0, or the P and Q chains swapped, fails the
+    block inverse."""
+    from oracle import fdet_oracle as F
+    K = honeycomb_hopping(2)
+    Nt, dk = 8, 0.5
+    phi = sample_phi(36, Nt, 8, dk, 3.0)
+    Minv = np.linalg.inv(O.block_fermion_matrix(K, dk, phi))
+
+    def worst():
+        e = 0.0
+        for t in range(1, Nt + 1):
+            for t0 in range(1, Nt + 1):
+                Gb = Minv[(t - 1) * 8:t * 8, (t0 - 1) * 8:t0 * 8]
+                e = max(e, np.abs(F.dsplit_displaced_greens(K, dk, phi, t, t0) - Gb).max())
+        return e
+
+    assert worst() < 1e-12
+    orig = F.displaced_split
+    monkeypatch.setattr(F, "displaced_split", lambda n, t, t0: orig(n, t, t0)[:4] + (1.0,))
     assert worst() > 1e-3
     monkeypatch.setattr(F, "displaced_split",
                         lambda n, t, t0: (lambda r: (r[2], r[3], r[0], r[1], r[4]))(orig(n, t, t0)))
