@@ -160,6 +160,25 @@ int fd_force(const fd_problem *p, const fd_options *o, double *logdet, double *f
 int fd_udv(const fd_problem *p, const fd_options *o, double *X, double *D, double *T,
            void *ws, size_t ws_bytes, int32_t *status, void *stream);
 
+/* Time-displaced Green's functions G(t, t0) = block (t, t0) of the inverse of
+ * the (N N_t)^2 block fermion matrix (Sec. 4, matrix element derivatives,
+ * eq. sausage_all_in_denominator), 1-based slice labels t, t0 in [1, N_t],
+ * G(1, 1) = G = M^{-1}.  For each pair, P = the slices from t up to t0 - 1
+ * (cyclically; all of them when t = t0) and Q = the remaining ones; then
+ * G(t, t0) = (P + Q^{-1})^{-1} for t >= t0 and -(P + Q^{-1})^{-1} for t < t0,
+ * evaluated without forming either product: P and Q^{-H} (the slices
+ * exp(-dk K) diag(e^{i phi_t})) as stabilised UDV chains (QR every s
+ * slices), and P + Q^{-1} = Xp [Dp (Tp Xq) + (Xp^H Tq^H) Dq] Xq^H inverted
+ * through one pivoted QR of its scale-split bracket (Sec. 7 steps 7-9).
+ * t, t0: host arrays of npairs int32.  G: device, npairs N*N complex
+ * (interleaved, row-major), pair k at offset 2*N*N*k doubles.  Workspace from
+ * fd_displaced_workspace_bytes (0 on invalid arguments).  One problem;
+ * options: s and FD_REUSE_E.                                               */
+size_t fd_displaced_workspace_bytes(const fd_problem *p, const fd_options *o, int32_t npairs);
+int fd_greens_displaced(const fd_problem *p, const fd_options *o, int32_t npairs,
+                        const int32_t *t, const int32_t *t0, double *G, void *ws,
+                        size_t ws_bytes, int32_t *status, void *stream);
+
 /* Batched forms: `p` is a host array of nprob descriptors (sizes may differ).
  * logdet: 2*nprob doubles.  G: one device buffer, problem i at offset
  * 2*sum_{j<i} N_j^2 doubles.  force / force_im: problem i at offset

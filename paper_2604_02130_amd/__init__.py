@@ -42,6 +42,7 @@ SYMBOLS = (
     "fd_tune_load", "fd_tune_clear", "fd_response_trace_workspace_bytes", "fd_response_trace",
     "fd_hmc_leapfrog", "fd_diag_response", "fd_hmc_plan_create", "fd_hmc_plan_launch",
     "fd_hmc_plan_destroy", "fd_plan_segments", "fd_greens_noalloc",
+    "fd_displaced_workspace_bytes", "fd_greens_displaced",
 )
 
 PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export",
@@ -133,6 +134,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fd_plan_segments.restype = ctypes.c_int
     lib.fd_greens_noalloc.argtypes = [P, O, vp, vp, vp, vp]
     lib.fd_greens_noalloc.restype = ctypes.c_int
+    lib.fd_displaced_workspace_bytes.argtypes = [P, O, i32]
+    lib.fd_displaced_workspace_bytes.restype = sz
+    lib.fd_greens_displaced.argtypes = [P, O, i32, vp, vp, vp, vp, sz, vp, vp]
+    lib.fd_greens_displaced.restype = ctypes.c_int
     lib.fd_autotune.argtypes = [i32, P, i32, O, vp, O, ctypes.POINTER(ctypes.c_float)]
     lib.fd_autotune.restype = ctypes.c_int
     lib.fd_tune_save.argtypes = [ctypes.c_char_p]
@@ -326,6 +331,29 @@ def greens_noalloc(K, phi, dk, logdet, G, status, s=0, segments=0, flags=0):
     o = _opts(s=s, segments=segments, flags=flags)
     _check(lib.fd_greens_noalloc(ctypes.byref(p), ctypes.byref(o), logdet.data_ptr(),
                                  G.data_ptr(), status.data_ptr(), _stream()))
+
+
+def greens_displaced(K, phi, dk, pairs, s=0, flags=0, check=True, ws: Workspace | None = None):
+    """Time-displaced Green's functions G(t, t0) (block (t, t0) of the inverse
+    block fermion matrix, 1-based slices, G(1, 1) = G) for the (t, t0) in
+    `pairs`; returns an (npairs, N, N) complex128 tensor."""
+    torch = _torch()
+    lib = load_library()
+    p = _prob(K, phi, dk)
+    o = _opts(s=s, flags=flags)
+    n = len(pairs)
+    th = (ctypes.c_int32 * n)(*[int(a) for a, _ in pairs])
+    t0h = (ctypes.c_int32 * n)(*[int(b) for _, b in pairs])
+    G = torch.empty((n, p.N, p.N, 2), dtype=torch.float64, device=K.device)
+    status = torch.empty(1, dtype=torch.int32, device=K.device)
+    need = lib.fd_displaced_workspace_bytes(ctypes.byref(p), ctypes.byref(o), n)
+    if need == 0:
+        raise FdError(FD_ERR_INVALID_ARG, lib.fd_last_error().decode())
+    wsp, wsn = (ws or _default_ws).get(need, K.device)
+    _check(lib.fd_greens_displaced(ctypes.byref(p), ctypes.byref(o), n, th, t0h, G.data_ptr(),
+                                   wsp, wsn, status.data_ptr(), _stream()))
+    _status_check(status, check)
+    return torch.view_as_complex(G)
 
 
 def force(K, phi, dk, s=0, checkpoint=0, flags=0, check=True, ws: Workspace | None = None,

@@ -938,6 +938,113 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
   pl.total = cur.off;
 }
 
+// ---- time-displaced Green's functions G(t, t0) of one problem
+//
+// Per pair (t, t0): P = the slices from row t-1 up to row t0-1 (cyclically;
+// all N_t slices when t = t0) and Q = the others from row t0-1 on, as in
+// eq. sausage_all_in_denominator; G(t, t0) = sign (P + Q^{-1})^{-1}, sign -1
+// for t < t0.  Phases: exp(+-dk K); for every pair a chain of P's slices and
+// a chain of Q^{-H}'s slices exp(-dk K) diag(e^{i phi_t}) (same rows, same
+// order); one IK_DISPLACED item per pair.
+void displaced_rows(int Nt, int t, int t0, int& ps, int& pl, int& qs, int& ql, int& sign) {
+  const int r = t - 1, r0 = t0 - 1;
+  pl = ((r0 - r) % Nt + Nt) % Nt;
+  if (pl == 0) pl = Nt;
+  ps = r;
+  qs = r0;
+  ql = Nt - pl;
+  sign = t < t0 ? -1 : 1;
+}
+
+void build_displaced_plan(const fd_problem* p, const Opts& o, int npairs, const int32_t* th,
+                          const int32_t* t0h, char* base, Plan& pl, double* Gout) {
+  pl.probs.assign(1, Prob{});
+  pl.units.assign(1, npairs);
+  pl.maxN = p->N;
+  const size_t nitems = 2 + 3 * (size_t)npairs;
+  pl.desc_bytes = align_up(sizeof(Prob)) + align_up(sizeof(Item) * nitems);
+  pl.item_cap = nitems;
+  Cursor cur{base ? base : reinterpret_cast<char*>((uintptr_t)1 << 40), align_up(pl.desc_bytes)};
+  Prob& P = pl.probs[0];
+  P.N = p->N;
+  P.Np = pad16(p->N);
+  P.Nt = p->Nt;
+  P.dk = p->dk;
+  P.K = p->K;
+  P.phi = p->phi;
+  const int Np = P.Np;
+  P.E = cur.take((size_t)Np * Np * sizeof(double));
+  P.Einv = cur.take((size_t)Np * Np * sizeof(double));
+  std::vector<Item> expm, chain, disp;
+  for (int k = 0; k < npairs; ++k) {
+    const Udv sp = make_udv(cur.take(udv_bytes(Np)), Np);
+    const Udv sq = make_udv(cur.take(udv_bytes(Np)), Np);
+    double* scp = cur.take(scratch_bytes(Np));
+    double* scq = cur.take(scratch_bytes(Np));
+    if (k == 0) {
+      for (int sg = 0; sg < 2; ++sg) {
+        Item e = blank_item(fdet::IK_EXPM, 0);
+        e.sign = sg == 0 ? 1 : -1;
+        e.scr = sg == 0 ? scp : scq;
+        expm.push_back(e);
+      }
+    }
+    int ps, pln, qs, qln, sign;
+    displaced_rows(p->Nt, th[k], t0h[k], ps, pln, qs, qln, sign);
+    Item a = blank_item(fdet::IK_CHAIN, 0);
+    a.t0 = ps;
+    a.t1 = ps + pln;
+    a.s = o.s;
+    a.flags = fdet::IF_IDENTITY;
+    a.a = sp;
+    a.scr = scp;
+    chain.push_back(a);
+    Item b = blank_item(fdet::IK_CHAIN, 0);
+    b.t0 = qs;
+    b.t1 = qs + qln;
+    b.s = o.s;
+    b.flags = fdet::IF_IDENTITY | fdet::IF_EINV;
+    b.a = sq;
+    b.scr = scq;
+    chain.push_back(b);
+    Item d = blank_item(fdet::IK_DISPLACED, 0);
+    d.a = sp;
+    d.b = sq;
+    d.sign = sign;
+    d.scr = scp;
+    d.out = Gout ? Gout + (size_t)2 * p->N * p->N * k : nullptr;
+    disp.push_back(d);
+  }
+  auto work = [&](const Item& it) { return it.t1 - it.t0; };
+  std::stable_sort(chain.begin(), chain.end(),
+                   [&](const Item& x, const Item& y) { return work(x) > work(y); });
+  pl.phases.clear();
+  if (!(o.flags & FD_REUSE_E)) pl.phases.push_back(expm);
+  pl.phases.push_back(chain);
+  pl.phases.push_back(disp);
+  pl.single = false;
+  pl.tail_off = pl.deps_off = cur.off;
+  cur.take(sizeof(int32_t));
+  pl.done_off = cur.off;
+  cur.take(sizeof(uint32_t) * nitems);
+  pl.sched_off = cur.off;
+  cur.take(sizeof(fdet::Sched));
+  pl.tail_bytes = cur.off - pl.tail_off;
+  pl.total = cur.off;
+}
+
+int validate_pairs(const fd_problem* p, int32_t npairs, const int32_t* t, const int32_t* t0) {
+  if (npairs < 1) return fail(FD_ERR_INVALID_ARG, "npairs must be >= 1");
+  if (!t || !t0) return fail(FD_ERR_INVALID_ARG, "t and t0 must be host arrays");
+  for (int k = 0; k < npairs; ++k)
+    if (t[k] < 1 || t[k] > p->Nt || t0[k] < 1 || t0[k] > p->Nt) {
+      char buf[128];
+      std::snprintf(buf, sizeof buf, "pair %d: (t, t0) = (%d, %d) outside [1, %d]", k, t[k], t0[k], p->Nt);
+      return fail(FD_ERR_INVALID_ARG, buf);
+    }
+  return FD_OK;
+}
+
 // Descriptors (problems, then the items of every phase, or the single
 // launch's item list) in the head of the workspace; `first` receives the
 // index of each phase's first item.  `tail` receives the single launch's
@@ -1315,6 +1422,38 @@ int fd_udv(const fd_problem* p, const fd_options* o, double* X, double* D, doubl
   out.T = T;
   out.status = status;
   return run(p, 1, o, FD_WHAT_UDV, out, ws, ws_bytes, stream);
+}
+
+size_t fd_displaced_workspace_bytes(const fd_problem* p, const fd_options* o, int32_t npairs) {
+  const Opts r = resolve(o);
+  if (validate(p, 1, r) != FD_OK) return 0;
+  if (npairs < 1) {
+    fail(FD_ERR_INVALID_ARG, "npairs must be >= 1");
+    return 0;
+  }
+  std::vector<int32_t> one(npairs, 1);
+  Plan pl;
+  build_displaced_plan(p, r, npairs, one.data(), one.data(), nullptr, pl, nullptr);
+  return pl.total;
+}
+
+int fd_greens_displaced(const fd_problem* p, const fd_options* o, int32_t npairs, const int32_t* t,
+                        const int32_t* t0, double* G, void* ws, size_t ws_bytes, int32_t* status,
+                        void* stream) {
+  if (!G) return fail(FD_ERR_INVALID_ARG, "G must be a device pointer");
+  if (!status) return fail(FD_ERR_INVALID_ARG, "status must be a device pointer");
+  const Opts r = resolve(o);
+  int rc = validate(p, 1, r);
+  if (rc != FD_OK) return rc;
+  rc = validate_pairs(p, npairs, t, t0);
+  if (rc != FD_OK) return rc;
+  const size_t need = fd_displaced_workspace_bytes(p, o, npairs);
+  rc = check_ws(ws, ws_bytes, need);
+  if (rc != FD_OK) return rc;
+  Plan pl;
+  build_displaced_plan(p, r, npairs, t, t0, static_cast<char*>(ws), pl, G);
+  pl.probs[0].status = status;
+  return execute(pl, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
 }
 
 int fd_logdet_batched(const fd_problem* p, int32_t nprob, const fd_options* o, double* logdet,

@@ -91,9 +91,10 @@ __device__ void status_merge(int32_t* st, int32_t code) {
 
 template <int NC>
 __device__ void load_phases(const Prob& P, int t, SmemC<NC>& S) {
+  const int row = t % P.Nt;   // chains of the displaced Green's function wrap around
   for (int x = threadIdx.x; x < P.N; x += WG) {
     double sv, cv;
-    sincos(P.phi[(size_t)t * P.N + x], &sv, &cv);
+    sincos(P.phi[(size_t)row * P.N + x], &sv, &cv);
     S.phr[x] = cv;
     S.phi_[x] = sv;
   }
@@ -143,11 +144,11 @@ __device__ double block_max(double v, double* red) {
 // ---------------------------------------------------------------------------
 
 // One slice of the chain: out = B_t in = E diag(e^{i phi_t}) in, one real x
-// complex product with the phases applied while the operand is staged.
+// complex product with the phases applied while the operand is staged (E is
+// exp(dk K), or exp(-dk K) for the chains of B_t^{-H}).
 template <int NC>
-__device__ void slice_apply(const Prob& P, CMat in, CMat out, SmemC<NC>& S) {
+__device__ void slice_apply(const Prob& P, const double* E, CMat in, CMat out, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
-  const double* E = P.E;
   mm<NC, false, true>(
       Np, [&](int i, int k) { return (i < N && k < N) ? E[(size_t)k * Np + i] : 0.0; },
       [&](int k, int j, double& br, double& bi) {
@@ -221,7 +222,7 @@ __device__ void chain_chunk(const Prob& P, const Item& it, CMat X, CMat& Tc, CMa
   for (int q = 0; q < ns; ++q) {
     load_phases<NC>(P, tfirst + q, S);
     __syncthreads();
-    slice_apply<NC>(P, src, dst, S);
+    slice_apply<NC>(P, (it.flags & IF_EINV) ? P.Einv : P.E, src, dst, S);
     __syncthreads();
     src = dst;
     dst = (dst.re == W.re) ? Y2 : W;
@@ -579,6 +580,133 @@ __device__ __forceinline__ void do_force(const Prob& P, const Item& it, SmemC<NC
 }
 
 // ---------------------------------------------------------------------------
+// IK_DISPLACED: G(t, t0) = sign (P + Q^{-1})^{-1} (eq.
+// sausage_all_in_denominator; Sec. 7 steps 7-9) with P = Xp Dp Tp (slot a)
+// and Q^{-H} = Xq Dq Tq (slot b, the chain of exp(-dk K) diag(e^{i phi_t})),
+// so that Q^{-1} = Tq^H Dq Xq^H and
+//   P + Q^{-1} = Xp [Dp (Tp Xq) + (Xp^H Tq^H) Dq] Xq^H.
+// With Dp = Dp_b Dp_s and Dq = Dq_s Dq_b (big / small parts, each at most 1
+// on one side) the bracket is Dp_b W Dq_b with
+//   W = Dp_s (Tp Xq) Dq_b^{-1} + Dp_b^{-1} (Xp^H Tq^H) Dq_s,
+// whose entries are O(1); one pivoted QR of W then gives
+//   G(t, t0) = sign Xq Dq_b^{-1} Pi R^{-1} Q^H Dp_b^{-1} Xp^H.
+// ---------------------------------------------------------------------------
+template <int NC>
+__device__ __forceinline__ void do_displaced(const Prob& P, const Item& it, SmemC<NC>& S) {
+  const int N = P.N, Np = P.Np;
+  const size_t cd = cmat_doubles(Np);
+  CMat W = cmat_at(it.scr, Np), Yb = cmat_at(it.scr + cd, Np), F = cmat_at(it.scr + 2 * cd, Np);
+  CMat Xp = cmat_at(it.a.X, Np), Tp = cmat_at(it.a.T, Np);
+  CMat Xq = cmat_at(it.b.X, Np), Tq = cmat_at(it.b.T, Np);
+  double* tst = tstore(it.scr, Np);
+  bool bad = false;
+  // v1 = 1 / Dp_b (kept through the QR, as in the close), v2 = Dp_s,
+  // v3 = 1 / Dq_b, norms = Dq_s (both only before the QR)
+  for (int i = threadIdx.x; i < N; i += WG) {
+    const double dp = it.a.D[i], dq = it.b.D[i];
+    if (!isfinite(dp) || !isfinite(dq)) bad = true;
+    S.v1[i] = 1.0 / (dp > 1.0 ? dp : 1.0);
+    S.v2[i] = dp < 1.0 ? dp : 1.0;
+    S.v3[i] = 1.0 / (dq > 1.0 ? dq : 1.0);
+    S.norms[i] = dq < 1.0 ? dq : 1.0;
+  }
+  __syncthreads();
+  // W = Dp_s (Tp Xq) Dq_b^{-1}
+  mm<NC, true, true>(
+      Np,
+      [&](int i, int k, double& ar, double& ai) {
+        if (i < N && k < N) { ar = Tp.r(i, k); ai = Tp.m(i, k); }
+        else { ar = 0.0; ai = 0.0; }
+      },
+      [&](int k, int j, double& br, double& bi) {
+        if (k < N && j < N) { br = Xq.r(k, j); bi = Xq.m(k, j); }
+        else { br = 0.0; bi = 0.0; }
+      },
+      [&](int i, int j, double cr, double ci) {
+        if (i < N && j < N) {
+          const double sc = S.v2[i] * S.v3[j];
+          W.r(i, j) = sc * cr;
+          W.m(i, j) = sc * ci;
+        }
+      }, S);
+  __syncthreads();
+  // W += Dp_b^{-1} (Xp^H Tq^H) Dq_s
+  mm<NC, true, true>(
+      Np,
+      [&](int i, int k, double& ar, double& ai) {
+        if (i < N && k < N) { ar = Xp.r(k, i); ai = -Xp.m(k, i); }
+        else { ar = 0.0; ai = 0.0; }
+      },
+      [&](int k, int j, double& br, double& bi) {
+        if (k < N && j < N) { br = Tq.r(j, k); bi = -Tq.m(j, k); }
+        else { br = 0.0; bi = 0.0; }
+      },
+      [&](int i, int j, double cr, double ci) {
+        if (i < N && j < N) {
+          const double sc = S.v1[i] * S.norms[j];
+          W.r(i, j) += sc * cr;
+          W.m(i, j) += sc * ci;
+        }
+      }, S);
+  __syncthreads();
+  qr_factor<NC>(W, N, nullptr, F, tst, S);
+  double amin = INFINITY, amax = 0.0;
+  for (int i = threadIdx.x; i < N; i += WG) {
+    const double a = hypot(W.r(i, i), W.m(i, i));
+    if (!isfinite(a)) bad = true;
+    amin = fmin(amin, a);
+    amax = fmax(amax, a);
+  }
+  amax = block_max(amax, S.red);
+  amin = -block_max(-amin, S.red);
+  const double nbad = block_sum(bad ? 1.0 : 0.0, S.red);
+  if (threadIdx.x == 0) {
+    int32_t code = 0;
+    if (nbad > 0.0) code = -4;
+    else if (!(amin > 0.0)) code = -3;
+    else if (amin < 1e3 * N * 2.220446049250313e-16 * fmax(1.0, amax)) code = 1;
+    status_merge(P.status, code);
+  }
+  // Yb = Dp_b^{-1} Xp^H
+  for_each_ij(N, [&](int i, int j) {
+    const double sc = S.v1[i];
+    Yb.r(i, j) = Xp.r(j, i) * sc;
+    Yb.m(i, j) = -Xp.m(j, i) * sc;
+  });
+  for (int r = threadIdx.x; r < N; r += WG) S.pinv[S.piv[r]] = r;
+  __syncthreads();
+  qr_solve<NC>(W, N, Yb, F, tst, S);
+  // G = sign Xq Dq_b^{-1} Pi Z: row a of Pi Z is row pinv[a] of Z
+  double* Gu = it.out;
+  const double sg = (double)it.sign;
+  mm<NC, true, true>(
+      Np,
+      [&](int i, int k, double& ar, double& ai) {
+        if (i < N && k < N) { ar = Xq.r(i, k); ai = Xq.m(i, k); }
+        else { ar = 0.0; ai = 0.0; }
+      },
+      [&](int k, int j, double& br, double& bi) {
+        if (k < N && j < N) {
+          // Dq_b^{-1} from the slot (the QR reused S.v3 for its pivot keys)
+          const int r = S.pinv[k];
+          const double dq = it.b.D[k];
+          const double sc = 1.0 / (dq > 1.0 ? dq : 1.0);
+          br = Yb.r(r, j) * sc;
+          bi = Yb.m(r, j) * sc;
+        } else {
+          br = 0.0; bi = 0.0;
+        }
+      },
+      [&](int i, int j, double cr, double ci) {
+        if (i < N && j < N) {
+          Gu[2 * ((size_t)i * N + j)] = sg * cr;
+          Gu[2 * ((size_t)i * N + j) + 1] = sg * ci;
+        }
+      }, S);
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // IK_EXPM: exp(sign dk K) = (Taylor_16(A / 2^q))^(2^q), A = sign dk K,
 // q chosen so that |A / 2^q|_1 <= 1/2 (truncation below 1e-19).
 // ---------------------------------------------------------------------------
@@ -724,6 +852,7 @@ FDET_KERNEL(k_close, do_close<C>(P, it.a, cmat_at(it.scr, P.Np),
                                    tstore(it.scr, P.Np), S))
 FDET_KERNEL(k_force, do_force<C>(P, it, S))
 FDET_KERNEL(k_export, do_export<C>(P, it, S))
+FDET_KERNEL(k_displaced, do_displaced<C>(P, it, S))
 
 // One item of any kind (the single-launch kernel below).
 template <int C>
@@ -739,6 +868,7 @@ __device__ __forceinline__ void run_item(const Prob& P, const Item& it, SmemC<C>
       break;
     case IK_FORCE: do_force<C>(P, it, S); break;
     case IK_EXPORT: do_export<C>(P, it, S); break;
+    case IK_DISPLACED: do_displaced<C>(P, it, S); break;
     default: break;
   }
 }
@@ -831,6 +961,7 @@ static hipError_t launch_kind(int kind, const fdet::Prob* probs, const fdet::Ite
     case IK_CLOSE: hipLaunchKernelGGL(k_close<NC>, g, b, 0, st, probs, items); break;
     case IK_FORCE: hipLaunchKernelGGL(k_force<NC>, g, b, 0, st, probs, items); break;
     case IK_EXPORT: hipLaunchKernelGGL(k_export<NC>, g, b, 0, st, probs, items); break;
+    case IK_DISPLACED: hipLaunchKernelGGL(k_displaced<NC>, g, b, 0, st, probs, items); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

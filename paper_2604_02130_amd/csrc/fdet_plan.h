@@ -33,6 +33,8 @@ enum ItemKind : int32_t {
                     // (right) of its cyclic product, then carried forward
                     // and backward
   IK_EXPORT = 5,    // copy a UDV out in user layout
+  IK_DISPLACED = 6, // G(t, t0) = sign (P + Q^{-1})^{-1} from the UDV of P (a)
+                    // and the UDV of Q^{-H} (b), into `out`
 };
 
 enum ItemFlags : int32_t {
@@ -40,6 +42,8 @@ enum ItemFlags : int32_t {
   IF_WANT_G = 8,       // close: also form G
   IF_OUT_LOGDET = 16,  // force: write log det M (checkpoint 0 only)
   IF_OUT_G = 32,       // force: write G = G~ of row 0 (checkpoint 0 only)
+  IF_EINV = 64,        // chain: slices exp(-dk K) diag(e^{i phi_t}) (the
+                       // conjugate transposes of B_t^{-1}) instead of B_t
 };
 
 // A UDV triple X diag(D) T in workspace layout.
@@ -51,7 +55,7 @@ struct Udv {
 
 struct Item {
   int32_t kind, prob, flags, sign;
-  int32_t t0, t1;       // slice rows [t0, t1)
+  int32_t t0, t1;       // slice rows [t0, t1), taken mod N_t (chains may wrap)
   int32_t s, pad0;      // stabilisation interval
   int32_t nb, pad1;     // force: rows t0-1, ..., t0-nb (mod N_t) carried backward
   int32_t dep0, ndep;   // single launch: the items this one waits for are
@@ -60,6 +64,7 @@ struct Item {
   Udv b;                // left operand (combine), right factor (force)
   Udv o;                // combine: result (X == nullptr: into a)
   double* scr;          // scratch: 4 cmats + 2*Np doubles
+  double* out;          // displaced: N*N interleaved complex, row-major
 };
 
 // State of a single-launch execution of a whole plan (one persistent kernel

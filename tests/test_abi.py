@@ -289,3 +289,21 @@ def test_single_launch_flag_is_switched_off(lib):
     rc = lib.fd_logdet(ctypes.byref(p), ctypes.byref(o), 0x3000, 0x10000, 1 << 30, 0x4000, None)
     assert rc == fd.FD_ERR_UNSUPPORTED
     assert "switched off" in lib.fd_last_error().decode()
+
+
+def test_displaced_argument_checks(lib):
+    p = prob(N=18, Nt=16)
+    assert lib.fd_displaced_workspace_bytes(ctypes.byref(p), None, 0) == 0
+    n1 = lib.fd_displaced_workspace_bytes(ctypes.byref(p), None, 1)
+    n3 = lib.fd_displaced_workspace_bytes(ctypes.byref(p), None, 3)
+    assert 0 < n1 < n3
+    t = (ctypes.c_int32 * 2)(1, 17)
+    t0 = (ctypes.c_int32 * 2)(1, 1)
+    rc = lib.fd_greens_displaced(ctypes.byref(p), None, 2, t, t0, 0x5000, 0x10000, 1 << 30,
+                                 0x4000, None)
+    assert rc == fd.FD_ERR_INVALID_ARG and "outside" in lib.fd_last_error().decode()
+    t = (ctypes.c_int32 * 2)(1, 16)
+    assert lib.fd_greens_displaced(ctypes.byref(p), None, 2, t, t0, None, 0x10000, 1 << 30,
+                                   0x4000, None) == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_greens_displaced(ctypes.byref(p), None, 2, t, t0, 0x5000, 0x10000, 256,
+                                   0x4000, None) == fd.FD_ERR_WORKSPACE

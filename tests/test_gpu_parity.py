@@ -735,3 +735,83 @@ def test_hmc_plan_and_graph_replays_match_leapfrog(fd):
         if not acc[i]:
             assert torch.equal(probs[i][1], phi0[i])
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# f1: time-displaced Green's function G(t, t0)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("beta,s", [(1.5, 1), (6.0, 4)])
+def test_displaced_every_pair_vs_block_inverse(fd, beta, s):
+    """All (t, t0) of L = 2, N_t = 12 against the blocks of the inverse block
+    fermion matrix (both signs of t - t0, t = t0, wrap-around chains)."""
+    K = honeycomb_hopping(2)
+    Nt = 12
+    dk = beta / Nt
+    phi = sample_phi(41, Nt, 8, dk, 3.0)
+    pairs = [(t, t0) for t in range(1, Nt + 1) for t0 in range(1, Nt + 1)]
+    G = fd.greens_displaced(to_dev(K), to_dev(phi), dk, pairs, s=s).cpu().numpy()
+    Minv = np.linalg.inv(O.block_fermion_matrix(K, dk, phi))
+    for k, (t, t0) in enumerate(pairs):
+        Gb = Minv[(t - 1) * 8:t * 8, (t0 - 1) * 8:t0 * 8]
+        check_G(G[k], Gb)
+
+
+@pytest.mark.parametrize("t,t0", [(1, 1), (200, 17), (17, 200), (256, 1), (1, 256), (129, 128)])
+def test_displaced_uniform_closed_form(fd, t, t0):
+    """Space-uniform field, L = 3, beta = 32, N_t = 256, s = 8: against the
+    eigenbasis closed form."""
+    L, Nt, beta = 3, 256, 32.0
+    K = honeycomb_hopping(L)
+    dk = beta / Nt
+    c = np.random.default_rng(2).normal(0, 0.6, Nt)
+    phi = uniform_phi(c, 18)
+    G = fd.greens_displaced(to_dev(K), to_dev(phi), dk, [(t, t0)], s=8).cpu().numpy()[0]
+    check_G(G, O.uniform_field_displaced_greens(K, dk, c, t, t0))
+
+
+def test_displaced_low_temperature_vs_oracle(fd):
+    """L = 6 (N = 72), N_t = 256, beta = 32 (the lowT_L6 field), s = 8: pairs
+    at both signs and far apart against the split-close oracle (the unsplit
+    close of Sec. 7 step 8 is itself off by ~1e-5 here); G(1, 1) = G."""
+    w = WORKLOADS["lowT_L6"]
+    K, phi = w.K(), w.phi()
+    pairs = [(1, 1), (130, 3), (3, 130), (256, 1), (1, 256), (77, 76)]
+    G = fd.greens_displaced(to_dev(K), to_dev(phi), w.dk, pairs, s=w.s).cpu().numpy()
+    for k, (t, t0) in enumerate(pairs):
+        check_G(G[k], O.dsplit_displaced_greens(K, w.dk, phi, t, t0))
+    _, G0 = gpu_greens(fd, K, phi, w.dk, s=w.s)
+    check_G(G[0], G0)
+
+
+@pytest.mark.parametrize("t,t0", [(70, 3), (3, 70), (128, 1), (40, 39)])
+def test_displaced_low_temperature_vs_block_inverse(fd, t, t0):
+    """L = 2, N_t = 128, beta = 32, random field: straight against the block
+    inverse of the full fermion matrix."""
+    K = honeycomb_hopping(2)
+    Nt, beta = 128, 32.0
+    dk = beta / Nt
+    phi = sample_phi(8, Nt, 8, dk, 3.0)
+    Minv = low_temperature_block_inverse()
+    G = fd.greens_displaced(to_dev(K), to_dev(phi), dk, [(t, t0)], s=8).cpu().numpy()[0]
+    check_G(G, Minv[(t - 1) * 8:t * 8, (t0 - 1) * 8:t0 * 8])
+
+
+@functools.lru_cache(maxsize=None)
+def low_temperature_block_inverse():
+    K = honeycomb_hopping(2)
+    Nt, beta = 128, 32.0
+    dk = beta / Nt
+    return np.linalg.inv(O.block_fermion_matrix(K, dk, sample_phi(8, Nt, 8, dk, 3.0)))
+
+
+def test_displaced_large_class(fd):
+    """N = 162 (the blocked class), N_t = 24: pairs against the oracle."""
+    K = honeycomb_hopping(9)
+    Nt, beta = 24, 3.0
+    dk = beta / Nt
+    phi = sample_phi(309, Nt, K.shape[0], dk, 3.0)
+    pairs = [(1, 1), (20, 5), (5, 20), (24, 1)]
+    G = fd.greens_displaced(to_dev(K), to_dev(phi), dk, pairs, s=8).cpu().numpy()
+    for k, (t, t0) in enumerate(pairs):
+        check_G(G[k], O.displaced_greens(K, dk, phi, t, t0))
