@@ -24,6 +24,7 @@ from .fdet_oracle import (  # noqa: F401
     logdet_close,
     response_trace,
     diag_response,
+    slice_response,
     displaced_split,
     bruteforce_displaced_greens,
     displaced_greens,

@@ -368,6 +368,27 @@ def response_trace(G, A=None):
     return complex(np.trace((np.eye(N) - G) @ A))
 
 
+def slice_response(K, dk, phi, A, rows=None):
+    """Per-slice response tr((1 - G~_t) A) to a general operator A (Sec. 4,
+    shortcut for simple operators, eq. response_simple before the average
+    over t): the matrix inside its trace at slice t is 1 - G~ of the slice
+    next to t, with G~_t = (1 + B_{t-1}...B_1 B_{N_t}...B_t)^{-1}, so that
+    over all slices the traces are those of the 1 - G~_t, t = 1..N_t.
+    Each G~_t is its own stabilised inversion, as in stabilised_force_rows.
+    A is an (N, N) array shared by every slice; returns the complex traces
+    for the 1-based slices in `rows` (all slices when None); their mean is
+    the slice-averaged response."""
+    Nt, N = phi.shape
+    A = np.asarray(A, dtype=np.complex128)
+    rows = range(1, Nt + 1) if rows is None else rows
+    prefix, suffix = _prefix_suffix(K, dk, phi)
+    out = []
+    for t in rows:
+        _, Gt = udv_close(udv_product(prefix[t - 1], suffix[t]))
+        out.append(np.trace((np.eye(N) - Gt) @ A))
+    return np.array(out, dtype=np.complex128)
+
+
 # ---------------------------------------------------------------------------
 # molecular dynamics (HMC)
 # ---------------------------------------------------------------------------

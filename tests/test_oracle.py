@@ -364,6 +364,65 @@ def test_diag_response_averages_the_shifted_greens_functions():
     assert abs(O.diag_response(F) - O.response_trace(G)) <= 1e-12
 
 
+def _dense_operator(N, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(N, N)) + 1j * rng.normal(size=(N, N))
+
+
+def test_slice_response_matches_block_inverse_diagonal_blocks():
+    """tr((1 - G~_t) A) for a dense complex A, every slice, against the
+    diagonal blocks of the block-matrix inverse (which are the G~_t)."""
+    K, dk, phi = case(2, 10, 2.5, seed=33)
+    Nt, N = phi.shape
+    A = _dense_operator(N, 5)
+    Minv = np.linalg.inv(O.block_fermion_matrix(K, dk, phi))
+    want = [np.trace((np.eye(N) - Minv[t * N:(t + 1) * N, t * N:(t + 1) * N]) @ A)
+            for t in range(Nt)]
+    got = O.slice_response(K, dk, phi, A)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    sub = O.slice_response(K, dk, phi, A, rows=[3, 10])
+    assert np.abs(sub - got[[2, 9]]).max() == 0.0
+
+
+def test_slice_response_diagonal_operator_is_the_brute_force_force():
+    """For A = diag(a) the traces are sum_x a_x (-i F_{t,x}) with F the
+    brute-force force (Jacobi on the block matrix, off-diagonal blocks)."""
+    K, dk, phi = case(2, 12, 3.0, seed=34)
+    Nt, N = phi.shape
+    a = np.random.default_rng(6).normal(size=N)
+    F = O.bruteforce_force(K, dk, phi)
+    want = (-1j * F) @ a
+    got = O.slice_response(K, dk, phi, np.diag(a))
+    assert np.abs(got - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+def test_slice_response_uniform_field_closed_form():
+    """A space-uniform field makes every slice matrix a phase times E, so all
+    cyclic products agree and every G~_t is the closed-form G: each trace is
+    tr((1 - G) A), here at beta = 32."""
+    L, Nt, beta = 3, 128, 32.0
+    K = honeycomb_hopping(L)
+    c = np.random.default_rng(7).normal(0, 0.6, Nt)
+    phi = uniform_phi(c, 18)
+    A = _dense_operator(18, 8)
+    Gc = O.uniform_field_greens(L, beta, c.sum())
+    want = np.trace((np.eye(18) - Gc) @ A)
+    got = O.slice_response(K, beta / Nt, phi, A, rows=[1, 50, 128])
+    assert np.abs(got - want).max() <= 1e-10 * max(1.0, abs(want))
+
+
+def test_slice_response_follows_a_rolled_field():
+    """Rolling the field by r slices rolls the per-slice traces by r; a
+    transposed operand (tr((1 - G~) A^T)) fails the block inverse."""
+    K, dk, phi = case(2, 9, 2.0, seed=35)
+    Nt, N = phi.shape
+    A = _dense_operator(N, 9)
+    base = O.slice_response(K, dk, phi, A)
+    rolled = O.slice_response(K, dk, np.roll(phi, -4, axis=0), A)
+    assert np.abs(rolled - np.roll(base, -4)).max() <= 1e-12 * np.abs(base).max()
+    assert np.abs(O.slice_response(K, dk, phi, A.T) - base).max() > 1e-3
+
+
 # --- molecular dynamics (Sec. 3.1) -----------------------------------------
 
 def _md_case():
