@@ -335,6 +335,31 @@ int fd_response_trace(int32_t N, const double *G, const double *A, double *out, 
 int fd_diag_response(int32_t Nt, int32_t N, const double *force, const double *force_im,
                      const double *a, double *out, void *stream);
 
+/* The force sweep with, in addition, the per-slice response to a general
+ * operator A (Sec. 4, shortcut for simple operators: the trace inside
+ * eq. response_simple, before its average over the slices):
+ *     trace[t-1] = tr((1 - G~_t) A) = tr A - sum_xy (G~_t)_xy A_yx,
+ * taken on each G~_t as the sweep forms it (checkpoints and carried rows),
+ * so it costs N^2 per slice beside the 8 N^3 of each carry.  The mean of the
+ * N_t traces is the slice-averaged response; A = diag(a) reproduces
+ * fd_diag_response slice by slice.
+ *   A      device, N*N complex (interleaved, row-major), shared by all slices
+ *   trace  device, N_t complex (interleaved): row t-1 = slice t
+ * The other arguments, the workspace and the options are those of fd_force
+ * (FD_KEEP_CHECKPOINTS included).  Batched: A of problem i at offset
+ * 2*sum_{j<i} N_j^2 doubles, trace at 2*sum_{j<i} Nt_j doubles.
+ * FD_ERR_INVALID_ARG for a NULL A, trace, force or status.
+ * FD_ERR_UNSUPPORTED for any problem with N > 128: the trace is switched off
+ * in the blocked class (one run there returned wrong traces and the next
+ * faulted; the cause is not known).                                        */
+int fd_force_response(const fd_problem *p, const fd_options *o, const double *A,
+                      double *trace, double *logdet, double *force, double *force_im,
+                      void *ws, size_t ws_bytes, int32_t *status, void *stream);
+int fd_force_response_batched(const fd_problem *p, int32_t nprob, const fd_options *o,
+                              const double *A, double *trace, double *logdet, double *force,
+                              double *force_im, void *ws, size_t ws_bytes, int32_t *status,
+                              void *stream);
+
 /* Text for a return/status code; the last error message of this thread.      */
 const char *fd_strerror(int code);
 const char *fd_last_error(void);

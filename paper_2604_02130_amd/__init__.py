@@ -42,7 +42,8 @@ SYMBOLS = (
     "fd_tune_load", "fd_tune_clear", "fd_response_trace_workspace_bytes", "fd_response_trace",
     "fd_hmc_leapfrog", "fd_diag_response", "fd_hmc_plan_create", "fd_hmc_plan_launch",
     "fd_hmc_plan_destroy", "fd_plan_segments", "fd_greens_noalloc",
-    "fd_displaced_workspace_bytes", "fd_greens_displaced",
+    "fd_displaced_workspace_bytes", "fd_greens_displaced", "fd_force_response",
+    "fd_force_response_batched",
 )
 
 PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export",
@@ -110,8 +111,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fd_logdet_batched.argtypes = [P, i32, O, vp, vp, sz, vp, vp]
     lib.fd_greens_batched.argtypes = [P, i32, O, vp, vp, vp, sz, vp, vp]
     lib.fd_force_batched.argtypes = [P, i32, O, vp, vp, vp, vp, sz, vp, vp]
+    lib.fd_force_response.argtypes = [P, O, vp, vp, vp, vp, vp, vp, sz, vp, vp]
+    lib.fd_force_response_batched.argtypes = [P, i32, O, vp, vp, vp, vp, vp, vp, sz, vp, vp]
     for name in ("fd_slice_exponential", "fd_logdet", "fd_greens", "fd_force", "fd_udv",
-                 "fd_logdet_batched", "fd_greens_batched", "fd_force_batched"):
+                 "fd_logdet_batched", "fd_greens_batched", "fd_force_batched",
+                 "fd_force_response", "fd_force_response_batched"):
         getattr(lib, name).restype = ctypes.c_int
     lib.fd_strerror.argtypes = [ctypes.c_int]
     lib.fd_strerror.restype = ctypes.c_char_p
@@ -374,6 +378,31 @@ def force(K, phi, dk, s=0, checkpoint=0, flags=0, check=True, ws: Workspace | No
     _status_check(status, check)
     F = torch.complex(Fr, Fi)
     return (F, torch.view_as_complex(ld)) if with_logdet else F
+
+
+def force_response(K, phi, dk, A, s=0, checkpoint=0, flags=0, check=True,
+                   ws: Workspace | None = None):
+    """(F, traces): the complex force as force() returns it and the per-slice
+    responses traces[t-1] = tr((1 - G~_t) A) to the (N, N) complex operator A
+    (fd_force_response); traces.mean() is the slice-averaged response."""
+    torch = _torch()
+    lib = load_library()
+    p = _prob(K, phi, dk)
+    o = _opts(s=s, checkpoint=checkpoint, flags=flags)
+    Ac = torch.view_as_real(A.to(device=K.device, dtype=torch.complex128).contiguous()).contiguous()
+    if tuple(Ac.shape) != (p.N, p.N, 2):
+        raise ValueError(f"A must be ({p.N}, {p.N}), got {tuple(A.shape)}")
+    Fr = torch.empty((p.Nt, p.N), dtype=torch.float64, device=K.device)
+    Fi = torch.empty((p.Nt, p.N), dtype=torch.float64, device=K.device)
+    tr = torch.empty((p.Nt, 2), dtype=torch.float64, device=K.device)
+    status = torch.empty(1, dtype=torch.int32, device=K.device)
+    need = workspace_bytes([p], FD_WHAT_FORCE, s=s, checkpoint=checkpoint, flags=flags)
+    wsp, wsn = (ws or _default_ws).get(need, K.device)
+    _check(lib.fd_force_response(ctypes.byref(p), ctypes.byref(o), Ac.data_ptr(), tr.data_ptr(),
+                                 None, Fr.data_ptr(), Fi.data_ptr(), wsp, wsn, status.data_ptr(),
+                                 _stream()))
+    _status_check(status, check)
+    return torch.complex(Fr, Fi), torch.view_as_complex(tr)
 
 
 def udv(K, phi, dk, s=0, segments=0, check=True, ws: Workspace | None = None):

@@ -1174,6 +1174,8 @@ struct Outs {
   double* X = nullptr;
   double* D = nullptr;
   double* T = nullptr;
+  const double* op = nullptr;
+  double* op_trace = nullptr;
   int32_t* status = nullptr;
 };
 
@@ -1189,7 +1191,7 @@ int prepare(const fd_problem* p, int nprob, const fd_options* opt, int what, con
   rc = check_ws(ws, ws_bytes, sizing.total);
   if (rc != FD_OK) return rc;
   build_plan(p, nprob, o, what, static_cast<char*>(ws), pl);
-  size_t goff = 0, foff = 0;
+  size_t goff = 0, foff = 0, toff = 0;
   for (int i = 0; i < nprob; ++i) {
     Prob& P = pl.probs[i];
     P.status = out.status ? out.status + i : nullptr;
@@ -1201,6 +1203,9 @@ int prepare(const fd_problem* p, int nprob, const fd_options* opt, int what, con
     P.outX = out.X;
     P.outD = out.D;
     P.outT = out.T;
+    P.op = out.op ? out.op + goff : nullptr;
+    P.op_trace = out.op_trace ? out.op_trace + 2 * toff : nullptr;
+    toff += (size_t)p[i].Nt;
     goff += (size_t)2 * p[i].N * p[i].N;
     foff += (size_t)p[i].Nt * p[i].N;
   }
@@ -1488,6 +1493,35 @@ int fd_force_batched(const fd_problem* p, int32_t nprob, const fd_options* o, do
   out.force_im = force_im;
   out.status = status;
   return run(p, nprob, o, FD_WHAT_FORCE, out, ws, ws_bytes, stream);
+}
+
+int fd_force_response_batched(const fd_problem* p, int32_t nprob, const fd_options* o,
+                              const double* A, double* trace, double* logdet, double* force,
+                              double* force_im, void* ws, size_t ws_bytes, int32_t* status,
+                              void* stream) {
+  if (!A || !trace) return fail(FD_ERR_INVALID_ARG, "A and trace must be device pointers");
+  for (int i = 0; i < nprob && p; ++i)
+    if (p[i].N > 128)
+      return fail(FD_ERR_UNSUPPORTED,
+                  "the operator trace is switched off for N > 128: one run of it at N = 162 "
+                  "returned wrong traces and the next faulted, with the cause not found");
+  if (!force) return fail(FD_ERR_INVALID_ARG, "force must be a device pointer");
+  if (!status) return fail(FD_ERR_INVALID_ARG, "status must be a device pointer");
+  Outs out;
+  out.logdet = logdet;
+  out.force = force;
+  out.force_im = force_im;
+  out.op = A;
+  out.op_trace = trace;
+  out.status = status;
+  return run(p, nprob, o, FD_WHAT_FORCE, out, ws, ws_bytes, stream);
+}
+
+int fd_force_response(const fd_problem* p, const fd_options* o, const double* A, double* trace,
+                      double* logdet, double* force, double* force_im, void* ws, size_t ws_bytes,
+                      int32_t* status, void* stream) {
+  return fd_force_response_batched(p, 1, o, A, trace, logdet, force, force_im, ws, ws_bytes,
+                                   status, stream);
 }
 
 int fd_plan_create(int32_t what, const fd_problem* p, int32_t nprob, const fd_options* o,

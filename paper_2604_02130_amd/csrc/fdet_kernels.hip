@@ -497,6 +497,27 @@ __device__ __forceinline__ void do_force(const Prob& P, const Item& it, SmemC<NC
       P.force[(size_t)t * N + x] = G.m(x, x);
       if (P.force_im) P.force_im[(size_t)t * N + x] = 1.0 - G.r(x, x);
     }
+    // (register and LDS classes only: the host rejects the operator trace
+    // for N > 128)
+    if constexpr (NC <= 128) if (P.op_trace) {
+      // tr((1 - G) A) = sum over (x, y) of (delta_xy - G_xy) A_yx; x runs
+      // fastest so that both G (column-major) and A (row-major) are read
+      // contiguously
+      double sr = 0.0, si = 0.0;
+      for (int idx = threadIdx.x; idx < N * N; idx += WG) {
+        const int y = idx / N, x = idx - y * N;
+        const double gr = (x == y ? 1.0 : 0.0) - G.r(x, y), gi = -G.m(x, y);
+        const double ar = P.op[2 * (size_t)idx], ai = P.op[2 * (size_t)idx + 1];
+        sr += gr * ar - gi * ai;
+        si += gr * ai + gi * ar;
+      }
+      sr = block_sum(sr, S.red);
+      si = block_sum(si, S.red);
+      if (threadIdx.x == 0) {
+        P.op_trace[2 * (size_t)t] = sr;
+        P.op_trace[2 * (size_t)t + 1] = si;
+      }
+    }
   };
   // forward: G~ of row t+1 = B_t G~ B_t^{-1}, B_t = E diag(e^{i phi_t})
   CMat G = W, Y = Qb;

@@ -22,6 +22,8 @@ struct Prob {
   double* outX;         // user UDV export (may be null)
   double* outD;
   double* outT;
+  const double* op;     // user, N*N interleaved complex row-major operator A (may be null)
+  double* op_trace;     // user, Nt interleaved complex: tr((1 - G~ of row t) A) (may be null)
 };
 
 enum ItemKind : int32_t {

@@ -307,3 +307,21 @@ def test_displaced_argument_checks(lib):
                                    0x4000, None) == fd.FD_ERR_INVALID_ARG
     assert lib.fd_greens_displaced(ctypes.byref(p), None, 2, t, t0, 0x5000, 0x10000, 256,
                                    0x4000, None) == fd.FD_ERR_WORKSPACE
+
+
+def test_force_response_argument_checks(lib):
+    p = prob(N=18, Nt=16)
+    for A, tr in ((None, 0x5000), (0x5000, None)):
+        rc = lib.fd_force_response(ctypes.byref(p), None, A, tr, None, 0x6000, None, 0x10000,
+                                   1 << 30, 0x4000, None)
+        assert rc == fd.FD_ERR_INVALID_ARG and "A and trace" in lib.fd_last_error().decode()
+    rc = lib.fd_force_response(ctypes.byref(p), None, 0x5000, 0x5000, None, None, None, 0x10000,
+                               1 << 30, 0x4000, None)
+    assert rc == fd.FD_ERR_INVALID_ARG
+
+
+def test_force_response_rejects_blocked_class(lib):
+    p = prob(N=162, Nt=16)
+    rc = lib.fd_force_response(ctypes.byref(p), None, 0x5000, 0x5000, None, 0x6000, None, 0x10000,
+                               1 << 30, 0x4000, None)
+    assert rc == fd.FD_ERR_UNSUPPORTED and "N > 128" in lib.fd_last_error().decode()

@@ -612,6 +612,69 @@ def test_diag_response_from_force(fd, L, Nt, beta, c):
     assert abs(n - O.response_trace(Go)) <= TOL_F
 
 
+def dense_operator(N, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(N, N)) + 1j * rng.normal(size=(N, N))
+
+
+@pytest.mark.parametrize("L,Nt,beta,s,c,flags", [(2, 10, 2.5, 1, 4, 0), (3, 64, 8.0, 4, 16, 0),
+                                                 (3, 64, 8.0, 4, 16, 2), (5, 40, 5.0, 8, 16, 0)])
+def test_force_response_every_slice(fd, L, Nt, beta, s, c, flags):
+    """Per-slice tr((1 - G~_t) A) for a dense complex A, every slice (the
+    checkpoint rows and the rows carried forward and backward), against the
+    oracle; the force of the same call is bit-identical to fd_force's.
+    flags 2 = grouped prefix / suffix scans."""
+    K = honeycomb_hopping(L)
+    N = K.shape[0]
+    dk = beta / Nt
+    phi = sample_phi(2500 + L, Nt, N, dk, 3.0)
+    A = dense_operator(N, 2600 + L)
+    F, tr = fd.force_response(to_dev(K), to_dev(phi), dk, to_dev(A), s=s, checkpoint=c,
+                              flags=flags)
+    want = O.slice_response(K, dk, phi, A)
+    assert np.abs(tr.cpu().numpy() - want).max() <= TOL_G * np.abs(A).sum()
+    F0 = fd.force(to_dev(K), to_dev(phi), dk, s=s, checkpoint=c, flags=flags)
+    assert np.array_equal(F.cpu().numpy(), F0.cpu().numpy())
+
+
+def test_force_response_diagonal_operator_and_low_temperature(fd):
+    """L = 6, N_t = 256, beta = 32 (the lowT_L6 field), s = 8, c = 16: a
+    dense A against the oracle on sampled slices (checkpoint rows and rows
+    carried up to 8 slices); A = diag(a) reproduces the force slice by slice
+    and its mean is fd_diag_response."""
+    import torch
+    w = WORKLOADS["lowT_L6"]
+    K, phi = w.K(), w.phi()
+    N = K.shape[0]
+    A = dense_operator(N, 2700)
+    F, tr = fd.force_response(to_dev(K), to_dev(phi), w.dk, to_dev(A), s=w.s, checkpoint=16)
+    rows = [1, 9, 16, 17, 24, 137, 200, 256]
+    want = O.slice_response(K, w.dk, phi, A, rows=rows)
+    got = tr.cpu().numpy()[[r - 1 for r in rows]]
+    assert np.abs(got - want).max() <= TOL_G * np.abs(A).sum()
+    a = np.random.default_rng(2701).normal(size=N)
+    F2, tr2 = fd.force_response(to_dev(K), to_dev(phi), w.dk, to_dev(np.diag(a).astype(complex)),
+                                s=w.s, checkpoint=16)
+    byrow = (-1j * F2.cpu().numpy()) @ a
+    assert np.abs(tr2.cpu().numpy() - byrow).max() <= 1e-13 * np.abs(a).sum()
+    avg = complex(fd.diag_response(F2, torch.from_numpy(a)).item())
+    assert abs(complex(tr2.mean().item()) - avg) <= 1e-13 * np.abs(a).sum()
+
+
+@pytest.mark.skip(reason="operator trace switched off for N > 128: at N = 162 one run returned "
+                         "wrong traces and the next faulted the GPU; cause not found")
+def test_force_response_large_class(fd):
+    """N = 162 (the blocked class), N_t = 24, s = 8, c = 8: every slice."""
+    K = honeycomb_hopping(9)
+    N, Nt, beta = K.shape[0], 24, 3.0
+    dk = beta / Nt
+    phi = sample_phi(2800, Nt, N, dk, 3.0)
+    A = dense_operator(N, 2801)
+    _, tr = fd.force_response(to_dev(K), to_dev(phi), dk, to_dev(A), s=8, checkpoint=8)
+    assert np.abs(tr.cpu().numpy() - O.slice_response(K, dk, phi, A)).max() \
+        <= TOL_G * np.abs(A).sum()
+
+
 # ---------------------------------------------------------------------------
 # f: molecular dynamics of HMC (Sec. 3.1)
 # ---------------------------------------------------------------------------
