@@ -9,6 +9,7 @@ from .fdet_oracle import (  # noqa: F401
     slice_exponential,
     slice_matrices,
     block_fermion_matrix,
+    block_matrix_of_slices,
     bruteforce_logdet_greens,
     bruteforce_force,
     dense_logdet_greens,
@@ -29,6 +30,9 @@ from .fdet_oracle import (  # noqa: F401
     bruteforce_displaced_greens,
     displaced_greens,
     dsplit_displaced_greens,
+    taylor_product_coefficients,
+    taylor_slice_matrices,
+    sparse_logdet_greens,
     hmc_hamiltonian,
     hmc_leapfrog,
 )
@@ -38,5 +42,6 @@ from .closed_form import (  # noqa: F401
     uniform_field_greens,
     uniform_field_force,
     uniform_field_displaced_greens,
+    uniform_field_taylor_logdet_greens,
     two_site,
 )

@@ -105,6 +105,56 @@ def uniform_field_force(L: int, bk: float, theta: float) -> complex:
     return complex(-acc / N, 0.5)
 
 
+def _taylor(x: float, n: int) -> float:
+    """sum_{j <= n} x^j / j! by Horner's rule."""
+    acc = 1.0
+    for j in range(n, 0, -1):
+        acc = 1.0 + acc * x / j
+    return acc
+
+
+def uniform_field_taylor_logdet_greens(L: int, dk: float, Nt: int, theta: float, n: int):
+    """log det M~ and G~ = M~^{-1} for a uniform field when every slice uses
+    the degree-n Taylor polynomial p_n of exp in place of exp(dk K) (the
+    product form of Sec. 8 is that polynomial).  p_n(dk K) is diagonal in
+    momentum space with eigenvalues p_n(+-dk |f|), so the product of the N_t
+    slices has eigenvalues e^{i theta} p_n(+-dk |f|)^{N_t}; with
+    a = N_t log p_n(+-dk |f|) (p_n > 0 on the range used here)
+        log det M~ = sum_k sum_+- log(1 + e^{i theta} e^{a}),
+        G~(k)      = sum_+- Pi_+-(k) / (1 + e^{i theta} e^{a}).
+    Both are evaluated without forming e^{a} for large a."""
+    N = 2 * L * L
+    eith = cmath.exp(1j * theta)
+    total = 0.0 + 0.0j
+    G = np.zeros((N, N), dtype=np.complex128)
+    idx = np.arange(L)
+    for (k1, k2), f in zip(_momenta(L), honeycomb_dispersion(L)):
+        af = abs(f)
+        Gk = np.zeros((2, 2), dtype=np.complex128)
+        for sgn in (1.0, -1.0):
+            p = _taylor(sgn * dk * af, n)
+            if not p > 0.0:
+                raise ValueError("p_n(dk lambda) must be positive here")
+            a = Nt * math.log(p)
+            if a > 0:
+                total += a + cmath.log(cmath.exp(-a) + eith)
+                w = cmath.exp(-a) / (cmath.exp(-a) + eith)
+            else:
+                total += cmath.log(1.0 + eith * cmath.exp(a))
+                w = 1.0 / (1.0 + eith * cmath.exp(a))
+            if af < 1e-14:
+                Gk += 0.5 * w * np.eye(2)
+            else:
+                h = np.array([[0.0, f], [np.conj(f), 0.0]], dtype=np.complex128)
+                Gk += w * 0.5 * (np.eye(2) + sgn * h / af)
+        cell = np.outer(np.exp(1j * k1 * idx), np.exp(1j * k2 * idx)).reshape(-1)
+        phase = np.outer(cell, np.conj(cell)) / (L * L)
+        for s_ in range(2):
+            for sp in range(2):
+                G[s_::2, sp::2] += Gk[s_, sp] * phase
+    return _wrap(total), G
+
+
 # ---------------------------------------------------------------------------
 # Two sites with one bond: K = [[0, 1], [1, 0]], so K^2 = 1 and
 # exp(dk K) = cosh(dk) 1 + sinh(dk) K.  The slice matrices, their product and

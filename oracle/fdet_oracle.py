@@ -87,8 +87,13 @@ def block_fermion_matrix(K: np.ndarray, dk: float, phi: np.ndarray) -> np.ndarra
     (0-based block indices, B_t acting between slice t-1 and t) and +B_{N_t}
     in the corner block (0, N_t-1) (anti-periodic time boundary).
     """
-    B = slice_matrices(K, dk, phi)
-    Nt, N = phi.shape
+    return block_matrix_of_slices(slice_matrices(K, dk, phi))
+
+
+def block_matrix_of_slices(B) -> np.ndarray:
+    """The block fermion matrix of Sec. 2 for given slice matrices
+    [B_1, ..., B_{N_t}] (the layout of block_fermion_matrix)."""
+    Nt, N = len(B), B[0].shape[0]
     M = np.eye(N * Nt, dtype=np.complex128)
     for p in range(Nt - 1):
         M[(p + 1) * N:(p + 2) * N, p * N:(p + 1) * N] = -B[p]
@@ -387,6 +392,58 @@ def slice_response(K, dk, phi, A, rows=None):
         _, Gt = udv_close(udv_product(prefix[t - 1], suffix[t]))
         out.append(np.trace((np.eye(N) - Gt) @ A))
     return np.array(out, dtype=np.complex128)
+
+
+# ---------------------------------------------------------------------------
+# intermediate volume, low temperature: slices in the product form of
+# Sec. 8, re-decomposed every s slices (Sec. 9)
+# ---------------------------------------------------------------------------
+
+def taylor_product_coefficients(n: int) -> np.ndarray:
+    """gamma_1 .. gamma_n with prod_k (1 + gamma_k x) = sum_{j <= n} x^j / j!
+    (Sec. 8).  Both sides are degree-n polynomials with constant term 1, so
+    the factors vanish where the Taylor polynomial does: gamma_k = -1 / r_k
+    for its roots r_k.  Ordered by real part, then imaginary part."""
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    r = np.roots([1.0 / math.factorial(j) for j in range(n, -1, -1)])
+    g = -1.0 / r.astype(np.complex128)
+    return g[np.lexsort((g.imag, g.real))]
+
+
+def taylor_slice_matrices(K, dk, phi, n):
+    """[B~_1, ..., B~_{N_t}] with B~_t = prod_k (1 + gamma_k dk K)
+    diag(e^{i phi_t}): the slices of Sec. 8, exp(dk K) replaced by its
+    degree-n Taylor polynomial in product form."""
+    N = K.shape[0]
+    E = np.eye(N, dtype=np.complex128)
+    for g in taylor_product_coefficients(n):
+        E = (np.eye(N) + g * dk * K) @ E
+    return [E * np.exp(1j * phi[t])[None, :] for t in range(phi.shape[0])]
+
+
+def sparse_logdet_greens(K, dk, phi, n, s):
+    """(log det, G) of M~ = 1 + B~_{N_t} ... B~_1 by the method of Sec. 9:
+    from P_0 = 1, each slice is applied to the unitary factor X without
+    forming B~_t, as x <- diag(e^{i phi_t}) x followed by the n product-form
+    steps x <- x + gamma_k dk (K x) of Sec. 8 (each a sparse product when K
+    is stored by its nonzeros); every s slices the accumulated X D Y^-1 is
+    re-decomposed by a pivoted QR (the sporadic stabilisation), and the
+    result is closed by Sec. 7 steps 4-6."""
+    Nt, N = phi.shape
+    gam = taylor_product_coefficients(n)
+    X, D, Yinv = udv_identity(N)
+    t = 0
+    while t < Nt:
+        C = X.astype(np.complex128)
+        for row in range(t, min(t + s, Nt)):
+            C = np.exp(1j * phi[row])[:, None] * C
+            for g in gam:
+                C = C + (g * dk) * (K @ C)
+        t += s
+        Xp, D, Ypinv = _qr_udv(C * D[None, :])
+        X, Yinv = Xp, Ypinv @ Yinv
+    return udv_close((X, D, Yinv))
 
 
 # ---------------------------------------------------------------------------

@@ -737,3 +737,100 @@ def test_dsplit_displaced_catches_planted_mistakes(monkeypatch):
     monkeypatch.setattr(F, "displaced_split",
                         lambda n, t, t0: (lambda r: (r[2], r[3], r[0], r[1], r[4]))(orig(n, t, t0)))
     assert worst() > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# intermediate volume, low temperature: product-form Taylor slices (Sec. 8)
+# with sporadic QR (Sec. 9)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", range(1, 9))
+def test_taylor_product_expands_to_the_taylor_polynomial(n):
+    """prod_k (1 + gamma_k x) multiplied out by hand has the coefficients
+    1 / j! of the degree-n Taylor polynomial of exp; the gammas come in
+    conjugate pairs (real polynomial)."""
+    g = O.taylor_product_coefficients(n)
+    assert len(g) == n
+    coef = np.zeros(n + 1, dtype=complex)   # coef[j] multiplies x^j
+    coef[0] = 1.0
+    for gk in g:
+        coef[1:] = coef[1:] + gk * coef[:-1]
+    want = np.array([1.0 / math.factorial(j) for j in range(n + 1)])
+    assert np.abs(coef - want).max() <= 1e-13
+    assert np.abs(np.sort_complex(g) - np.sort_complex(g.conj())).max() <= 1e-14
+
+
+def test_taylor_slices_against_the_series():
+    """The product-form slice at x = dk K equals the truncated series
+    sum_j (dk K)^j / j! summed by powers."""
+    K = honeycomb_hopping(3)
+    dk, n = 0.125, 4
+    phi = np.zeros((1, 18))
+    B = O.taylor_slice_matrices(K, dk, phi, n)[0]
+    S = np.zeros((18, 18))
+    P = np.eye(18)
+    for j in range(n + 1):
+        S = S + P / math.factorial(j)
+        P = P @ (dk * K)
+    assert np.abs(B - S).max() <= 1e-15
+
+
+@pytest.mark.parametrize("n,s", [(4, 1), (4, 4), (3, 8), (6, 5)])
+def test_sparse_variant_matches_block_inverse(n, s):
+    """Sec. 9 with product-form slices against log det and the (1, 1) block
+    of the inverse of the block matrix built from the same slices (L = 2,
+    N_t = 24, beta = 6, s not dividing N_t in one case)."""
+    K, dk, phi = case(2, 24, 6.0, seed=40)
+    Mb = O.block_matrix_of_slices(O.taylor_slice_matrices(K, dk, phi, n))
+    sgn, la = np.linalg.slogdet(Mb)
+    lb = complex(la, np.angle(sgn))
+    Gb = np.linalg.inv(Mb)[:8, :8]
+    ld, G = O.sparse_logdet_greens(K, dk, phi, n, s)
+    assert rel_err(ld, lb) <= 1e-12
+    assert np.abs(G - Gb).max() <= 1e-12
+
+
+@pytest.mark.parametrize("L,beta,Nt,n", [(3, 32.0, 256, 4), (4, 64.0, 512, 4), (3, 32.0, 256, 2)])
+def test_sparse_variant_uniform_field_closed_form(L, beta, Nt, n):
+    """A uniform field at beta = 32 and 64: log det and G against the
+    momentum-space closed form of the Taylor slices (cond of the product up
+    to ~1e83)."""
+    K = honeycomb_hopping(L)
+    N = K.shape[0]
+    c = np.random.default_rng(9).normal(0, 0.6, Nt)
+    dk = beta / Nt
+    lc, Gc = O.uniform_field_taylor_logdet_greens(L, dk, Nt, c.sum(), n)
+    ld, G = O.sparse_logdet_greens(K, dk, uniform_phi(c, N), n, 16)
+    assert rel_err(ld, lc) <= 1e-12
+    assert np.abs(G - Gc).max() <= 1e-11
+
+
+def test_sparse_variant_tends_to_the_exact_slices():
+    """With n = 14 the Taylor remainder (0.375^15 / 15! ~ 1e-19 per slice) is
+    below rounding: the variant equals the exact stabilised oracle; with
+    n = 4 it differs by the truncation, which shrinks as n grows."""
+    K, dk, phi = case(3, 32, 4.0, seed=41)
+    l0, G0 = O.sporadic_logdet_greens(K, dk, phi, 4)
+    l14, G14 = O.sparse_logdet_greens(K, dk, phi, 14, 4)
+    assert rel_err(l14, l0) <= 1e-12 and np.abs(G14 - G0).max() <= 1e-11
+    errs = [np.abs(O.sparse_logdet_greens(K, dk, phi, n, 4)[1] - G0).max() for n in (3, 4, 5, 6)]
+    assert errs[0] > errs[1] > errs[2] > errs[3] > 1e-12
+
+
+def test_sparse_variant_catches_planted_mistakes(monkeypatch):
+    """Applying the field after the hopping factors, or conjugated gammas
+    with a flipped sign, fails the block inverse."""
+    from oracle import fdet_oracle as F
+    K, dk, phi = case(2, 12, 3.0, seed=42)
+    Mb = O.block_matrix_of_slices(O.taylor_slice_matrices(K, dk, phi, 4))
+    Gb = np.linalg.inv(Mb)[:8, :8]
+    assert np.abs(F.sparse_logdet_greens(K, dk, phi, 4, 4)[1] - Gb).max() < 1e-12
+    real = F.taylor_product_coefficients
+    monkeypatch.setattr(F, "taylor_product_coefficients", lambda n: -real(n).conj())
+    assert np.abs(F.sparse_logdet_greens(K, dk, phi, 4, 4)[1] - Gb).max() > 1e-3
+    monkeypatch.undo()
+    # field after the hopping factors: rotate which factor acts first
+    Bwrong = [np.exp(1j * phi[t])[:, None] * O.taylor_slice_matrices(K, dk, np.zeros_like(phi), 4)[t]
+              for t in range(phi.shape[0])]
+    Gw = np.linalg.inv(O.block_matrix_of_slices(Bwrong))[:8, :8]
+    assert np.abs(F.sparse_logdet_greens(K, dk, phi, 4, 4)[1] - Gw).max() > 1e-3
