@@ -22,7 +22,8 @@ Printed as one JSON line, with
 and further legs: lowT_L6 (det+G of one N = 72 field, N_t = 256), force
 (N = 128 checkpointed adjoint vs the plain per-slice inversion), batched
 (256 mixed configurations in one launch sequence vs one call per
-configuration), observables and an HMC trajectory.
+configuration), observables, an HMC trajectory, and the intermediate-volume
+variant (matrix-free product-form slices) against the dense slices.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -538,6 +539,58 @@ def leg_trajectory(fd, torch, dev):
 
 # ---------------------------------------------------------------------------
 
+def leg_sparse(args, fd, torch, dev):
+    """Intermediate-volume low-temperature variant (Sec. 9 with the product-form
+    slices of Sec. 8, n = 4): det + G of field 0 of the headline batch
+    (N = 512, N_t = 512, beta = 64, s = 16) with matrix-free slices, against
+    det + G of the same field with the dense exponential, both with the
+    library's default time segments."""
+    from workload import hmc_batch
+    w = hmc_batch()[0]
+    N, Nt, s, n = w.N, w.Nt, w.s, 4
+    Kd = torch.from_numpy(w.K()).to(dev)
+    pd = torch.from_numpy(w.phi()).to(dev)
+    col, val = fd.ell(Kd)
+    q = int(col.shape[1])
+    ws = fd.Workspace()
+    out = {"workload": "field 0 of hmc_L16 (N=512, Nt=512, beta=64, U=3), s=16; log det M and G; "
+                       "sparse: degree-4 product-form Taylor slices applied matrix-free (q=3)"}
+    for label, call in (("sparse", lambda: fd.sparse_greens(col, val, pd, w.dk, n=n, s=s, ws=ws,
+                                                            check=False)),
+                        ("dense", lambda: fd.greens(Kd, pd, w.dk, s=s, ws=ws, check=False))):
+        call()
+        torch.cuda.synchronize()
+        reps = 5
+        a = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - a) / reps
+        out[label] = {"ms": dt * 1e3, "evals_per_s": 1.0 / dt, "phases_ms": phase_split(call)}
+        log(f"sparse leg {label}: {dt * 1e3:.2f} ms")
+    # the matrix-free slices: per slice and matrix element one field phase
+    # (6 FLOP) and n stencil steps of q real x complex terms plus the complex
+    # scale (4 q + 8 FLOP); LDS traffic (q + 2) x 16 B per step + 32 B per phase
+    chain_ms = sum(ms for name, _, ms in out["sparse"]["phases_ms"] if name == "chain")
+    flop = Nt * N * N * (n * (4 * q + 8) + 6)
+    lds = Nt * N * N * (n * (q + 2) * 16 + 32)
+    out["sparse"]["stencil_model_flop"] = flop
+    out["sparse"]["stencil_model_lds_bytes"] = lds
+    out["sparse"]["chain_ms"] = chain_ms
+    out["sparse_vs_dense"] = out["dense"]["ms"] / out["sparse"]["ms"]
+    if not args.no_cpu:
+        import scipy.sparse as sp
+        import oracle
+        Ks = sp.csr_matrix(w.K())
+        a = time.perf_counter()
+        oracle.sparse_logdet_greens(Ks, w.dk, w.phi(), n, s)
+        dtc = time.perf_counter() - a
+        out["cpu_oracle"] = {"evals_per_s": 1.0 / dtc, "cores": host_threads(),
+                             "sample": f"1 det+G eval of the same field (sparse K, QR every {s} "
+                                       f"slices), {dtc:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -583,6 +636,7 @@ def main():
         result["batched"] = leg_batched(fd, torch, dev)
         result["observables"] = leg_observables(fd, torch, dev)
         result["hmc_trajectory"] = leg_trajectory(fd, torch, dev)
+        result["sparse"] = leg_sparse(args, fd, torch, dev)
     print(json.dumps(result), flush=True)
 
 

@@ -360,6 +360,39 @@ int fd_force_response_batched(const fd_problem *p, int32_t nprob, const fd_optio
                               double *force_im, void *ws, size_t ws_bytes, int32_t *status,
                               void *stream);
 
+/* Intermediate volume, low temperature (Sec. 9, with the slices of Sec. 8):
+ * log det and G of M~ = 1 + B~_{N_t} ... B~_1 where each slice
+ * B~_t = [prod_{k=1}^{n} (1 + gamma_k dk K)] diag(e^{i phi_t}) replaces
+ * exp(dk K) by its degree-n Taylor polynomial in product form (the gamma_k
+ * are -1 / the roots of that polynomial, computed by the library) and is
+ * never formed: every slice is applied to the stabilised product's unitary
+ * factor as a field phase and n stencil steps x <- x + gamma_k dk K x over
+ * the nonzeros of K, and the product is re-decomposed by a pivoted QR every
+ * s slices (the sporadic stabilisation).  The truncation changes the result
+ * at O((dk |K|)^{n+1}) per slice: this is a different slice matrix from the
+ * exact one of fd_greens, not an approximation of its output.
+ * K by its nonzeros (ELL form): row i has q entries, neighbours col[i*q + j]
+ * in [0, N) with weights val[i*q + j]; pad short rows with weight 0.        */
+typedef struct {
+  int32_t q;            /* entries per row, 1 <= q <= 64                      */
+  const int32_t *col;   /* device, N*q                                         */
+  const double *val;    /* device, N*q                                         */
+} fd_ell;
+/* fd_problem.K is not read (may be NULL).  taylor_n in [1, 8] (the paper
+ * takes 4).  Options: s <= 16 and segments as for fd_greens; no flags.
+ * G == NULL: log det only.  Batched: hop and p are host arrays of nprob
+ * entries; outputs laid out as for fd_greens_batched.  Workspace from
+ * fd_sparse_workspace_bytes (what = FD_WHAT_LOGDET or FD_WHAT_GREENS; 0 on
+ * invalid arguments).                                                       */
+size_t fd_sparse_workspace_bytes(const fd_problem *p, int32_t nprob, const fd_options *o,
+                                 int32_t what);
+int fd_sparse_greens(const fd_problem *p, const fd_ell *hop, int32_t taylor_n,
+                     const fd_options *o, double *logdet, double *G, void *ws, size_t ws_bytes,
+                     int32_t *status, void *stream);
+int fd_sparse_greens_batched(const fd_problem *p, int32_t nprob, const fd_ell *hop,
+                             int32_t taylor_n, const fd_options *o, double *logdet, double *G,
+                             void *ws, size_t ws_bytes, int32_t *status, void *stream);
+
 /* Text for a return/status code; the last error message of this thread.      */
 const char *fd_strerror(int code);
 const char *fd_last_error(void);

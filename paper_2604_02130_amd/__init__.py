@@ -43,7 +43,8 @@ SYMBOLS = (
     "fd_hmc_leapfrog", "fd_diag_response", "fd_hmc_plan_create", "fd_hmc_plan_launch",
     "fd_hmc_plan_destroy", "fd_plan_segments", "fd_greens_noalloc",
     "fd_displaced_workspace_bytes", "fd_greens_displaced", "fd_force_response",
-    "fd_force_response_batched",
+    "fd_force_response_batched", "fd_sparse_workspace_bytes", "fd_sparse_greens",
+    "fd_sparse_greens_batched",
 )
 
 PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "export",
@@ -53,6 +54,10 @@ PHASE_NAMES = {0: "expm", 1: "chain", 2: "combine", 3: "close", 4: "force", 5: "
 class FdProblem(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int32), ("Nt", ctypes.c_int32), ("dk", ctypes.c_double),
                 ("K", ctypes.c_void_p), ("phi", ctypes.c_void_p)]
+
+
+class FdEll(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
 
 
 class FdOptions(ctypes.Structure):
@@ -112,6 +117,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fd_greens_batched.argtypes = [P, i32, O, vp, vp, vp, sz, vp, vp]
     lib.fd_force_batched.argtypes = [P, i32, O, vp, vp, vp, vp, sz, vp, vp]
     lib.fd_force_response.argtypes = [P, O, vp, vp, vp, vp, vp, vp, sz, vp, vp]
+    EL = ctypes.POINTER(FdEll)
+    lib.fd_sparse_workspace_bytes.argtypes = [P, i32, O, i32]
+    lib.fd_sparse_workspace_bytes.restype = sz
+    lib.fd_sparse_greens.argtypes = [P, EL, i32, O, vp, vp, vp, sz, vp, vp]
+    lib.fd_sparse_greens.restype = ctypes.c_int
+    lib.fd_sparse_greens_batched.argtypes = [P, i32, EL, i32, O, vp, vp, vp, sz, vp, vp]
+    lib.fd_sparse_greens_batched.restype = ctypes.c_int
     lib.fd_force_response_batched.argtypes = [P, i32, O, vp, vp, vp, vp, vp, vp, sz, vp, vp]
     for name in ("fd_slice_exponential", "fd_logdet", "fd_greens", "fd_force", "fd_udv",
                  "fd_logdet_batched", "fd_greens_batched", "fd_force_batched",
@@ -323,6 +335,61 @@ def greens(K, phi, dk, s=0, segments=0, flags=0, check=True, ws: Workspace | Non
                          status.data_ptr(), _stream()))
     _status_check(status, check)
     return torch.view_as_complex(ld), torch.view_as_complex(G)
+
+
+def ell(K, device=None):
+    """(col, val): the nonzeros of a hopping matrix in the ELL layout of
+    fd_ell (q = the most nonzeros of any row; short rows padded with their
+    own index and weight 0), as int32 / float64 tensors of shape (N, q) on
+    `device` (default: K's).  Layout conversion only."""
+    torch = _torch()
+    Kh = K.detach().to("cpu", torch.float64)
+    N = Kh.shape[0]
+    nz = [torch.nonzero(Kh[i]).flatten().tolist() for i in range(N)]
+    q = max(1, max(len(r) for r in nz))
+    col = torch.empty((N, q), dtype=torch.int32)
+    val = torch.zeros((N, q), dtype=torch.float64)
+    for i, r in enumerate(nz):
+        col[i] = i
+        for j, c in enumerate(r):
+            col[i, j] = c
+            val[i, j] = Kh[i, c]
+    dev = device if device is not None else K.device
+    return col.to(dev), val.to(dev)
+
+
+def sparse_greens(col, val, phi, dk, n=4, s=0, segments=0, want_g=True, check=True,
+                  ws: Workspace | None = None):
+    """fd_sparse_greens: log det and (if want_g) G of the sausage whose slices
+    are [prod_k (1 + gamma_k dk K)] diag(e^{i phi_t}) (degree-n product-form
+    Taylor polynomial, applied matrix-free from the ELL arrays col / val of
+    shape (N, q)), QR every s slices.  Returns (logdet, G or None)."""
+    torch = _torch()
+    lib = load_library()
+    for name, t, dt in (("col", col, torch.int32), ("val", val, torch.float64),
+                        ("phi", phi, torch.float64)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise FdError(FD_ERR_INVALID_ARG, f"{name} must be a contiguous CUDA {dt} tensor")
+    if col.dim() != 2 or tuple(col.shape) != tuple(val.shape) or phi.dim() != 2 \
+            or phi.shape[1] != col.shape[0]:
+        raise FdError(FD_ERR_INVALID_ARG, "col, val must be (N, q) and phi (Nt, N)")
+    N, q = int(col.shape[0]), int(col.shape[1])
+    p = FdProblem(N, int(phi.shape[0]), float(dk), None, phi.data_ptr())
+    h = FdEll(q, col.data_ptr(), val.data_ptr())
+    o = _opts(s=s, segments=segments)
+    what = FD_WHAT_GREENS if want_g else FD_WHAT_LOGDET
+    ld = torch.empty(2, dtype=torch.float64, device=phi.device)
+    G = torch.empty((N, N, 2), dtype=torch.float64, device=phi.device) if want_g else None
+    status = torch.empty(1, dtype=torch.int32, device=phi.device)
+    need = lib.fd_sparse_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), what)
+    if need == 0:
+        raise FdError(FD_ERR_INVALID_ARG, "fd_sparse_workspace_bytes: " + lib.fd_last_error().decode())
+    wsp, wsn = (ws or _default_ws).get(need, phi.device)
+    _check(lib.fd_sparse_greens(ctypes.byref(p), ctypes.byref(h), int(n), ctypes.byref(o),
+                                ld.data_ptr(), G.data_ptr() if want_g else None, wsp, wsn,
+                                status.data_ptr(), _stream()))
+    _status_check(status, check)
+    return torch.view_as_complex(ld), (torch.view_as_complex(G) if want_g else None)
 
 
 def greens_noalloc(K, phi, dk, logdet, G, status, s=0, segments=0, flags=0):

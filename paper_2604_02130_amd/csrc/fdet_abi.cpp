@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -257,6 +258,10 @@ struct Plan {
   double est_us = 0.0;          // simulated run time of the single launch
   std::vector<int32_t> deps;
   size_t tail_off = 0, tail_bytes = 0, deps_off = 0, done_off = 0, sched_off = 0;
+  // matrix-free slices (intermediate-volume variant): one descriptor per
+  // problem at sops_off inside the descriptor region
+  std::vector<fdet::SparseOp> sops;
+  size_t sops_off = 0;
 };
 
 struct Cursor {
@@ -284,6 +289,64 @@ Item blank_item(int kind, int prob) {
   it.prob = prob;
   it.sign = 1;
   return it;
+}
+
+// gamma_1 .. gamma_n with prod_k (1 + gamma_k x) = sum_{j <= n} x^j / j!
+// (Sec. 8): gamma_k = -1 / r_k for the roots r_k of the Taylor polynomial.
+// The roots of its monic form x^n + sum_j (n! / j!) x^j come from the
+// Weierstrass (Durand-Kerner) iteration, each polished by Newton steps on the
+// polynomial, in long double; ordered by real part, then imaginary part.
+std::vector<std::complex<double>> taylor_product_coefficients(int n) {
+  typedef std::complex<long double> C;
+  std::vector<long double> a(n + 1);   // monic: a[j] multiplies x^j, a[n] = 1
+  long double f = 1.0L;
+  for (int j = n; j >= 0; --j) {
+    a[j] = f;                          // n! / j!
+    f *= (long double)std::max(j, 1);
+  }
+  auto poly = [&](C x, C* dp) {
+    C v = a[n], d = 0.0L;
+    for (int j = n - 1; j >= 0; --j) {
+      d = d * x + v;
+      v = v * x + a[j];
+    }
+    if (dp) *dp = d;
+    return v;
+  };
+  std::vector<C> r(n);
+  const C seed(0.4L, 0.9L);
+  C z = 1.0L;
+  for (int k = 0; k < n; ++k) {
+    z *= seed;
+    r[k] = (long double)n * z;
+  }
+  for (int it = 0; it < 500; ++it) {
+    long double moved = 0.0L;
+    for (int k = 0; k < n; ++k) {
+      C den = 1.0L;
+      for (int j = 0; j < n; ++j)
+        if (j != k) den *= r[k] - r[j];
+      const C step = poly(r[k], nullptr) / den;
+      r[k] -= step;
+      moved = std::max(moved, std::abs(step));
+    }
+    if (moved < 1e-18L) break;
+  }
+  for (int k = 0; k < n; ++k)
+    for (int it = 0; it < 3; ++it) {
+      C d;
+      const C v = poly(r[k], &d);
+      if (std::abs(d) > 0.0L) r[k] -= v / d;
+    }
+  std::vector<std::complex<double>> g(n);
+  for (int k = 0; k < n; ++k) {
+    const C gk = -1.0L / r[k];
+    g[k] = std::complex<double>((double)gk.real(), (double)gk.imag());
+  }
+  std::sort(g.begin(), g.end(), [](const std::complex<double>& x, const std::complex<double>& y) {
+    return x.real() < y.real() || (x.real() == y.real() && x.imag() < y.imag());
+  });
+  return g;
 }
 
 int validate(const fd_problem* p, int nprob, const Opts& o) {
@@ -646,7 +709,8 @@ void single_launch_order(Plan& pl, int workers) {
 }
 
 // Build the layout and the work items.  `what` = FD_WHAT_*.
-void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* base, Plan& pl) {
+void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* base, Plan& pl,
+                const fd_ell* ell = nullptr, int taylor_n = 0) {
   pl.probs.assign(nprob, Prob{});
   pl.maxN = 0;
   size_t nitems = 0;
@@ -690,11 +754,32 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
     }
   }
   pl.desc_bytes = align_up(sizeof(Prob) * nprob) + align_up(sizeof(Item) * nitems);
+  pl.sops.clear();
+  if (ell) {
+    pl.sops_off = pl.desc_bytes;
+    pl.desc_bytes += align_up(sizeof(fdet::SparseOp) * nprob);
+  }
   pl.item_cap = nitems;
   // a sizing pass (base == nullptr) lays out against a stand-in address: the
   // single launch's dependencies are keyed by region addresses, so they must
   // be distinct there too (the pointers of a sizing plan are never used)
   Cursor cur{base ? base : reinterpret_cast<char*>((uintptr_t)1 << 40), align_up(pl.desc_bytes)};
+  if (ell) {
+    const std::vector<std::complex<double>> gam = taylor_product_coefficients(taylor_n);
+    for (int i = 0; i < nprob; ++i) {
+      fdet::SparseOp so;
+      std::memset(&so, 0, sizeof so);
+      so.n = taylor_n;
+      so.q = ell[i].q;
+      so.col = ell[i].col;
+      so.val = ell[i].val;
+      for (int k = 0; k < taylor_n; ++k) {
+        so.gr[k] = gam[k].real() * p[i].dk;
+        so.gi[k] = gam[k].imag() * p[i].dk;
+      }
+      pl.sops.push_back(so);
+    }
+  }
 
   std::vector<Item> expm, chain, close, forcei;
   std::vector<std::vector<Item>> comb(maxlev);
@@ -707,6 +792,8 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
     P.dk = q.dk;
     P.K = q.K;
     P.phi = q.phi;
+    if (ell)
+      P.sp = reinterpret_cast<const fdet::SparseOp*>(cur.base + pl.sops_off) + i;
     const int Np = P.Np;
     P.E = cur.take((size_t)Np * Np * sizeof(double));
     P.Einv = force ? cur.take((size_t)Np * Np * sizeof(double)) : nullptr;
@@ -718,7 +805,7 @@ void build_plan(const fd_problem* p, int nprob, const Opts& o, int what, char* b
         slot[k] = make_udv(cur.take(udv_bytes(Np)), Np);
         scr[k] = cur.take(scratch_bytes(Np));
       }
-      if (!(o.flags & FD_REUSE_E)) {
+      if (!(o.flags & FD_REUSE_E) && !ell) {
         Item e = blank_item(fdet::IK_EXPM, i);
         e.sign = 1;
         e.scr = scr[0];
@@ -1066,6 +1153,8 @@ std::vector<char> pack_descriptors(const Plan& pl, std::vector<size_t>& first,
       n += ph.size();
     }
   }
+  if (!pl.sops.empty())
+    std::memcpy(host.data() + pl.sops_off, pl.sops.data(), pl.sops.size() * sizeof(fdet::SparseOp));
   if (tail) {
     tail->assign(pl.tail_bytes, 0);
     if (!pl.deps.empty())
@@ -1493,6 +1582,66 @@ int fd_force_batched(const fd_problem* p, int32_t nprob, const fd_options* o, do
   out.force_im = force_im;
   out.status = status;
   return run(p, nprob, o, FD_WHAT_FORCE, out, ws, ws_bytes, stream);
+}
+
+size_t fd_sparse_workspace_bytes(const fd_problem* p, int32_t nprob, const fd_options* o,
+                                 int32_t what) {
+  if (!p || nprob < 1) return 0;
+  if (what != FD_WHAT_LOGDET && what != FD_WHAT_GREENS) return 0;
+  const Opts r = resolve(o, p, nprob, what);
+  Plan pl;
+  fd_ell none{1, nullptr, nullptr};
+  std::vector<fd_ell> ell(nprob, none);
+  build_plan(p, nprob, r, what, nullptr, pl, ell.data(), 1);
+  return pl.total;
+}
+
+int fd_sparse_greens_batched(const fd_problem* p, int32_t nprob, const fd_ell* hop,
+                             int32_t taylor_n, const fd_options* o, double* logdet, double* G,
+                             void* ws, size_t ws_bytes, int32_t* status, void* stream) {
+  if (!p || nprob < 1) return fail(FD_ERR_INVALID_ARG, "no problems given");
+  if (!hop) return fail(FD_ERR_INVALID_ARG, "hop must be a host array of nprob fd_ell");
+  if (!logdet) return fail(FD_ERR_INVALID_ARG, "logdet must be a device pointer");
+  if (!status) return fail(FD_ERR_INVALID_ARG, "status must be a device pointer");
+  if (taylor_n < 1 || taylor_n > fdet::kMaxTaylor)
+    return fail(FD_ERR_INVALID_ARG, "taylor_n must be in [1, 8]");
+  if (o && (o->flags & (FD_KEEP_CHECKPOINTS | FD_REUSE_E | FD_SINGLE_LAUNCH)))
+    return fail(FD_ERR_INVALID_ARG, "the matrix-free slices take no flags");
+  const int what = G ? FD_WHAT_GREENS : FD_WHAT_LOGDET;
+  const Opts r = resolve(o, p, nprob, what);
+  if (r.s > 16) return fail(FD_ERR_INVALID_ARG, "the matrix-free slices need s <= 16");
+  std::vector<fd_problem> pk(p, p + nprob);
+  for (int i = 0; i < nprob; ++i) {
+    char buf[128];
+    if (hop[i].q < 1 || hop[i].q > 64 || !hop[i].col || !hop[i].val) {
+      std::snprintf(buf, sizeof buf, "problem %d: q must be in [1, 64] with col and val set", i);
+      return fail(FD_ERR_INVALID_ARG, buf);
+    }
+    if (!pk[i].K) pk[i].K = hop[i].val;   // K itself is not read
+  }
+  int rc = validate(pk.data(), nprob, r);
+  if (rc != FD_OK) return rc;
+  Plan sizing;
+  build_plan(pk.data(), nprob, r, what, nullptr, sizing, hop, taylor_n);
+  rc = check_ws(ws, ws_bytes, sizing.total);
+  if (rc != FD_OK) return rc;
+  Plan pl;
+  build_plan(pk.data(), nprob, r, what, static_cast<char*>(ws), pl, hop, taylor_n);
+  size_t goff = 0;
+  for (int i = 0; i < nprob; ++i) {
+    Prob& P = pl.probs[i];
+    P.status = status + i;
+    P.logdet = logdet + 2 * i;
+    P.G = G ? G + goff : nullptr;
+    goff += (size_t)2 * p[i].N * p[i].N;
+  }
+  return execute(pl, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+}
+
+int fd_sparse_greens(const fd_problem* p, const fd_ell* hop, int32_t taylor_n,
+                     const fd_options* o, double* logdet, double* G, void* ws, size_t ws_bytes,
+                     int32_t* status, void* stream) {
+  return fd_sparse_greens_batched(p, 1, hop, taylor_n, o, logdet, G, ws, ws_bytes, status, stream);
 }
 
 int fd_force_response_batched(const fd_problem* p, int32_t nprob, const fd_options* o,

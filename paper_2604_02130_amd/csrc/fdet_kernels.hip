@@ -213,19 +213,103 @@ template <int NC>
 __device__ __forceinline__ void do_close(const Prob& P, Udv U, CMat W, CMat Yb, CMat Gint, bool want_g,
                          bool user_out, bool ld_out, double* tst, SmemC<NC>& S);
 
+// The ns slices of a chunk without forming B~_t (Sec. 8 product form, used
+// by the sporadic stabilisation of Sec. 9): W = prod over the chunk of
+// [prod_k (1 + gamma_k dk K)] diag(e^{i phi_t}) applied to X.  Columns are
+// independent, so X goes through LDS in panels of w columns (w a power of
+// two, four N x w planes: two buffers, re and im): each panel gets all ns
+// slices there, i.e. ns (n + 1) passes of N w elements, each step
+// x_i <- x_i + gamma_k dk sum_j K_{i,col_ij} x_{col_ij} a stencil over the
+// row's q nonzeros, then it is written to W.  The field phases of the chunk
+// are computed once into Ph (re: cos, im: sin, slice-major; ns N <= Np^2).
+template <int NC>
+__device__ void sparse_slices(const Prob& P, CMat X, CMat W, CMat Ph, int tfirst, int ns,
+                              SmemC<NC>& S) {
+  const int N = P.N, q = P.sp->q, n = P.sp->n;
+  const int32_t* __restrict__ col = P.sp->col;
+  const double* __restrict__ val = P.sp->val;
+  for (int e = threadIdx.x; e < ns * N; e += WG) {
+    const int k = e / N, i = e - k * N;
+    const int row = (tfirst + k) % P.Nt;
+    double sv, cv;
+    sincos(P.phi[(size_t)row * N + i], &sv, &cv);
+    Ph.re[e] = cv;
+    Ph.im[e] = sv;
+  }
+  constexpr int LD = NC <= 128 ? BigLds<NC>::N : LG_BIG;
+  int lw = 0;
+  while ((2 << lw) * 4 * N <= LD && (2 << lw) <= N) ++lw;
+  const int w = 1 << lw, ne = N * w;
+  double* ar = S.big;
+  double* ai = ar + ne;
+  double* br = ai + ne;
+  double* bi = br + ne;
+  __syncthreads();
+  for (int c0 = 0; c0 < N; c0 += w) {
+    const int wc = min(w, N - c0);
+    for (int e = threadIdx.x; e < ne; e += WG) {
+      const int i = e >> lw, c = e & (w - 1);
+      ar[e] = c < wc ? X.r(i, c0 + c) : 0.0;
+      ai[e] = c < wc ? X.m(i, c0 + c) : 0.0;
+    }
+    __syncthreads();
+    double *xr = ar, *xi = ai, *yr = br, *yi = bi;
+    for (int k = 0; k < ns; ++k) {
+      for (int e = threadIdx.x; e < ne; e += WG) {
+        const int i = e >> lw;
+        const double cv = Ph.re[k * N + i], sv = Ph.im[k * N + i];
+        const double r = xr[e], m = xi[e];
+        xr[e] = cv * r - sv * m;
+        xi[e] = sv * r + cv * m;
+      }
+      __syncthreads();
+      for (int f = 0; f < n; ++f) {
+        const double gr = P.sp->gr[f], gi = P.sp->gi[f];
+        for (int e = threadIdx.x; e < ne; e += WG) {
+          const int i = e >> lw, c = e & (w - 1);
+          double sr = 0.0, si = 0.0;
+          for (int j = 0; j < q; ++j) {
+            const double v = val[(size_t)i * q + j];
+            const int cj = min(max(col[(size_t)i * q + j], 0), N - 1);
+            sr = fma(v, xr[(cj << lw) + c], sr);
+            si = fma(v, xi[(cj << lw) + c], si);
+          }
+          yr[e] = xr[e] + (gr * sr - gi * si);
+          yi[e] = xi[e] + (gr * si + gi * sr);
+        }
+        __syncthreads();
+        double* t = xr; xr = yr; yr = t;
+        t = xi; xi = yi; yi = t;
+      }
+    }
+    for (int e = threadIdx.x; e < ne; e += WG) {
+      const int i = e >> lw, c = e & (w - 1);
+      if (c < wc) {
+        W.r(i, c0 + c) = xr[e];
+        W.m(i, c0 + c) = xi[e];
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int NC>
 __device__ void chain_chunk(const Prob& P, const Item& it, CMat X, CMat& Tc, CMat& Tt, double* D,
                             CMat W, CMat Y2, int tfirst, int ns, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
-  CMat src = X;
-  CMat dst = (ns & 1) ? W : Y2;
-  for (int q = 0; q < ns; ++q) {
-    load_phases<NC>(P, tfirst + q, S);
-    __syncthreads();
-    slice_apply<NC>(P, (it.flags & IF_EINV) ? P.Einv : P.E, src, dst, S);
-    __syncthreads();
-    src = dst;
-    dst = (dst.re == W.re) ? Y2 : W;
+  if (P.sp) {
+    sparse_slices<NC>(P, X, W, Y2, tfirst, ns, S);
+  } else {
+    CMat src = X;
+    CMat dst = (ns & 1) ? W : Y2;
+    for (int q = 0; q < ns; ++q) {
+      load_phases<NC>(P, tfirst + q, S);
+      __syncthreads();
+      slice_apply<NC>(P, (it.flags & IF_EINV) ? P.Einv : P.E, src, dst, S);
+      __syncthreads();
+      src = dst;
+      dst = (dst.re == W.re) ? Y2 : W;
+    }
   }
   double* tst = tstore(it.scr, Np);
   qr_factor<NC>(W, N, D, Y2, tst, S);

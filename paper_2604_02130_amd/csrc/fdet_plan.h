@@ -5,6 +5,18 @@
 
 namespace fdet {
 
+// Matrix-free slices of the intermediate-volume variant: the hopping matrix
+// by its nonzeros (q per row, row-major; padding entries have weight 0) and
+// the product-form coefficients gamma_k of the degree-n Taylor polynomial,
+// premultiplied by dk.
+constexpr int kMaxTaylor = 8;
+struct SparseOp {
+  int32_t n, q;
+  const int32_t* col;   // user, N*q column indices in [0, N)
+  const double* val;    // user, N*q weights K_{i, col}
+  double gr[kMaxTaylor], gi[kMaxTaylor];   // gamma_k dk, re and im
+};
+
 // One problem (one field configuration).
 struct Prob {
   int N, Np, Nt, pad0;
@@ -24,6 +36,7 @@ struct Prob {
   double* outT;
   const double* op;     // user, N*N interleaved complex row-major operator A (may be null)
   double* op_trace;     // user, Nt interleaved complex: tr((1 - G~ of row t) A) (may be null)
+  const SparseOp* sp;   // descriptor region: matrix-free slices instead of E (may be null)
 };
 
 enum ItemKind : int32_t {

@@ -230,6 +230,59 @@ int main() {
            fw.phases.size(), bw.phases.front().size(), b ? "BAD" : "ok");
     bad += b;
   }
+  // the product-form Taylor coefficients: prod_k (1 + gamma_k x) multiplied
+  // out must give the coefficients 1 / j! of the degree-n Taylor polynomial
+  for (int n = 1; n <= fdet::kMaxTaylor; ++n) {
+    const std::vector<std::complex<double>> g = taylor_product_coefficients(n);
+    std::vector<std::complex<double>> c(n + 1, 0.0);
+    c[0] = 1.0;
+    for (int k = 0; k < n; ++k)
+      for (int j = k + 1; j >= 1; --j) c[j] += g[k] * c[j - 1];
+    double err = 0.0, fact = 1.0;
+    for (int j = 0; j <= n; ++j) {
+      if (j > 0) fact *= j;
+      err = std::max(err, std::abs(c[j] - 1.0 / fact));
+    }
+    const int b = (int)g.size() != n || !(err < 1e-13);
+    printf("taylor n=%d: max coefficient error %.2e %s\n", n, err, b ? "BAD" : "ok");
+    bad += b;
+  }
+  // matrix-free slices: no exponential phase, one SparseOp per problem inside
+  // the descriptor region carrying gamma_k dk, chunks short enough for the
+  // phase staging (ns N <= Np^2)
+  for (int nt : {1, 7, 64, 300}) for (int s : {1, 5, 16}) {
+    std::vector<fd_problem> v = {prob(72, nt, 0.1), prob(8, nt + 3, 0.2), prob(512, nt, 0.125)};
+    fd_options oo{s, 0, 0, 0};
+    int32_t cols[1] = {0};
+    double vals[1] = {0.0};
+    std::vector<fd_ell> h(3, fd_ell{3, cols, vals});
+    Opts r = resolve(&oo, v.data(), 3, FD_WHAT_GREENS);
+    Plan pl, sz;
+    build_plan(v.data(), 3, r, FD_WHAT_GREENS, (char*)0x10000000, pl, h.data(), 4);
+    build_plan(v.data(), 3, r, FD_WHAT_GREENS, nullptr, sz, h.data(), 4);
+    std::vector<size_t> first;
+    std::vector<char> host = pack_descriptors(pl, first);
+    int b = 0;
+    if (pl.total != sz.total || pl.sops.size() != 3) b++;
+    const std::vector<std::complex<double>> g = taylor_product_coefficients(4);
+    for (int i = 0; i < 3; ++i) {
+      const char* at = (const char*)pl.probs[i].sp;
+      if (at != (const char*)0x10000000 + pl.sops_off + i * sizeof(fdet::SparseOp)) b++;
+      if (pl.sops_off + 3 * sizeof(fdet::SparseOp) > pl.desc_bytes) b++;
+      fdet::SparseOp so;
+      std::memcpy(&so, host.data() + pl.sops_off + i * sizeof(fdet::SparseOp), sizeof so);
+      if (so.n != 4 || so.q != 3 || so.col != cols || so.val != vals) b++;
+      for (int k = 0; k < 4; ++k)
+        if (so.gr[k] != g[k].real() * v[i].dk || so.gi[k] != g[k].imag() * v[i].dk) b++;
+    }
+    for (auto& ph : pl.phases) for (auto& it : ph) {
+      if (it.kind == fdet::IK_EXPM) b++;
+      const int Np = pl.probs[it.prob].Np;
+      if (it.kind == fdet::IK_CHAIN && (long)std::min(it.s, it.t1 - it.t0) * pl.probs[it.prob].N > (long)Np * Np) b++;
+    }
+    printf("sparse Nt=%d s=%d: %zu phases %s\n", nt, s, pl.phases.size(), b ? "BAD" : "ok");
+    bad += b;
+  }
   // random batches of every kind
   {
     std::mt19937 g(12345);

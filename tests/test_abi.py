@@ -325,3 +325,25 @@ def test_force_response_rejects_blocked_class(lib):
     rc = lib.fd_force_response(ctypes.byref(p), None, 0x5000, 0x5000, None, 0x6000, None, 0x10000,
                                1 << 30, 0x4000, None)
     assert rc == fd.FD_ERR_UNSUPPORTED and "N > 128" in lib.fd_last_error().decode()
+
+
+def test_sparse_argument_checks(lib):
+    p = prob(N=18, Nt=16, K=0)
+    h = fd.FdEll(3, 0x1000, 0x2000)
+    o = fd.FdOptions(8, 0, 0, 0)
+    assert lib.fd_sparse_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), fd.FD_WHAT_GREENS) > 0
+    assert lib.fd_sparse_workspace_bytes(ctypes.byref(p), 1, ctypes.byref(o), fd.FD_WHAT_FORCE) == 0
+    args = (0x5000, 0x6000, 0x10000, 1 << 30, 0x4000, None)
+    assert lib.fd_sparse_greens(ctypes.byref(p), ctypes.byref(h), 9, ctypes.byref(o), *args) \
+        == fd.FD_ERR_INVALID_ARG
+    bad = fd.FdEll(0, 0x1000, 0x2000)
+    assert lib.fd_sparse_greens(ctypes.byref(p), ctypes.byref(bad), 4, ctypes.byref(o), *args) \
+        == fd.FD_ERR_INVALID_ARG
+    o2 = fd.FdOptions(32, 0, 0, 0)
+    assert lib.fd_sparse_greens(ctypes.byref(p), ctypes.byref(h), 4, ctypes.byref(o2), *args) \
+        == fd.FD_ERR_INVALID_ARG and "s <= 16" in lib.fd_last_error().decode()
+    o3 = fd.FdOptions(8, 0, 0, fd.FD_KEEP_CHECKPOINTS)
+    assert lib.fd_sparse_greens(ctypes.byref(p), ctypes.byref(h), 4, ctypes.byref(o3), *args) \
+        == fd.FD_ERR_INVALID_ARG
+    assert lib.fd_sparse_greens(ctypes.byref(p), ctypes.byref(h), 4, ctypes.byref(o),
+                                0x5000, 0x6000, 0x10000, 256, 0x4000, None) == fd.FD_ERR_WORKSPACE
