@@ -356,7 +356,7 @@ __device__ __forceinline__ void do_chain(const Prob& P, const Item& it, SmemC<NC
 // result = A1 A2 with A1 = (X1, D1, T1) and A2 = (X2, D2, T2): the bracket
 // D1 (T1 X2) D2 keeps a unitary factor in the middle product.
 // ---------------------------------------------------------------------------
-template <int NC>
+template <int NC, bool RIGHT_Q = false>
 __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMat Xo, CMat To,
                              double* Do, double* tst, SmemC<NC>& S) {
   const int N = P.N, Np = P.Np;
@@ -384,6 +384,23 @@ __device__ void combine_core(const Prob& P, Udv A1, Udv A2, CMat W, CMat Qb, CMa
   qr_factor<NC>(W, N, A2.D, To, tst, S);
   udv_scales<NC>(W, N, S);
   __syncthreads();
+  if constexpr (NC > 128 && RIGHT_Q) {
+    if (lg_block_fits(Np)) {
+      // X = X1 Q by applying the reflector blocks to a copy of X1 from the
+      // right (Q is never formed; Qb is the free matrix)
+      copy_cmat(Xo, X1, N);
+      __syncthreads();
+      lg_right_apply_q<NC>(W, N, Xo, N, Qb, S);
+      __syncthreads();
+      udv_new_t<NC>(W, N, Np,
+                    [&](int r, int j, double& br, double& bi) { br = T2.r(r, j); bi = T2.m(r, j); },
+                    To, S);
+      __syncthreads();
+      for (int i = threadIdx.x; i < N; i += WG) Do[i] = S.v2[i];
+      __syncthreads();
+      return;
+    }
+  }
   qr_form_q<NC>(W, N, Qb, To, tst, S);
   // X = X1 Q
   mm<NC, true, true>(
@@ -426,7 +443,7 @@ __device__ __forceinline__ void do_combine(const Prob& P, const Item& it, SmemC<
   CMat Xo = is_b ? Xs : cmat_at(R.X, Np);
   CMat To = is_a ? Ts : cmat_at(R.T, Np);
   double* Do = R.D;
-  combine_core<NC>(P, it.b, it.a, W, Qb, Xo, To, Do, tstore(it.scr, Np), S);
+  combine_core<NC, true>(P, it.b, it.a, W, Qb, Xo, To, Do, tstore(it.scr, Np), S);
   if (is_b) copy_cmat(cmat_at(R.X, Np), Xs, N);
   if (is_a) copy_cmat(cmat_at(R.T, Np), Ts, N);
   if (threadIdx.x == 0 && S.flag) status_merge(P.status, -4);
@@ -938,8 +955,8 @@ __device__ __forceinline__ void by_class(int n, F&& f) {
   __global__ __launch_bounds__(WG) void NAME(const Prob* __restrict__ probs,           \
                                              const Item* __restrict__ items) {         \
     __shared__ SmemC<NC> S_;                                                          \
-    const Item it = items[blockIdx.x];                                                 \
-    const Prob P = probs[it.prob];                                                     \
+    const Item& it = items[blockIdx.x];                                                \
+    const Prob& P = probs[it.prob];                                                    \
     by_class<NC>(P.N, [&](auto cls) {                                                  \
       constexpr int C = decltype(cls)::value;                                          \
       static_assert(sizeof(SmemC<C>) <= sizeof(SmemC<NC>), "class layout");           \

@@ -576,12 +576,11 @@ constexpr int LG_NB = 64;
 // factors, over 64 columns).  Scratch: the raw storage of the free matrix F
 // (2 Np^2 doubles, at least 128 Np + 16384 for Np >= 144): V^H Y and then
 // T' V^H Y at ld 64, T' and G (64 x 64 each, re then im).
+// T' of the block (pw x pw at ld 64, re then im, at F.re + 2 * 64 * Np) from
+// the Gram matrix of its M rows of V, as described above.
 template <int NC>
-__device__ void lg_apply_block(const LgPanel& pn, CMat Y, int ycol0, int M, int Nc, CMat F,
-                               bool herm, SmemC<NC>& S) {
+__device__ __forceinline__ void lg_block_t(const LgPanel& pn, int M, CMat F, bool herm, SmemC<NC>& S) {
   const int j0 = pn.j0, pw = pn.pw, Np = F.ld;
-  double* f0r = F.re;
-  double* f0i = F.re + (size_t)LG_NB * Np;
   double* tgr = F.re + (size_t)2 * LG_NB * Np;
   double* tgi = tgr + LG_NB * LG_NB;
   double* ggr = tgi + LG_NB * LG_NB;
@@ -641,6 +640,23 @@ __device__ void lg_apply_block(const LgPanel& pn, CMat Y, int ycol0, int M, int 
     else { tgr[e] = tr[i * LG_NB + k]; tgi[e] = -ti[i * LG_NB + k]; }
   }
   __syncthreads();
+}
+
+template <int NC>
+__device__ void lg_apply_block(const LgPanel& pn, CMat Y, int ycol0, int M, int Nc, CMat F,
+                               bool herm, SmemC<NC>& S) {
+  const int j0 = pn.j0, pw = pn.pw, Np = F.ld;
+  double* f0r = F.re;
+  double* f0i = F.re + (size_t)LG_NB * Np;
+  const double* tgr = F.re + (size_t)2 * LG_NB * Np;
+  const double* tgi = tgr + LG_NB * LG_NB;
+  auto vh = [&](int i, int k, double& ar, double& ai) {   // V^H (i, k) = conj V(j0 + k, i)
+    double vr, vi;
+    pn.v(j0 + k, i, vr, vi);
+    ar = vr;
+    ai = -vi;
+  };
+  lg_block_t<NC>(pn, M, F, herm, S);
   // F = V^H Y
   lg_gemm<64, 128, true, true>(
       pw, Nc, M, vh,
@@ -682,6 +698,66 @@ __device__ void lg_apply_block(const LgPanel& pn, CMat Y, int ycol0, int M, int 
       [&](int i, int j, double cr, double ci) {
         Y.r(j0 + i, ycol0 + j) = cr;
         Y.m(j0 + i, ycol0 + j) = ci;
+      }, S.big);
+}
+
+// Y(0:M, j0:N) <- Y(0:M, j0:N) (I - V T V^H) for the block of reflectors
+// j0 .. j0+pw-1: Z = Y V (M x pw at ld Np in the free matrix), Z <- Z T in
+// place (one macro tile holds all pw columns of its rows), Y -= Z V^H.  The
+// scratch is that of lg_apply_block.
+template <int NC>
+__device__ void lg_apply_block_right(const LgPanel& pn, CMat Y, int M, int N, CMat F,
+                                     SmemC<NC>& S) {
+  const int j0 = pn.j0, pw = pn.pw, Np = F.ld;
+  double* zr = F.re;
+  double* zi = F.re + (size_t)LG_NB * Np;
+  const double* tgr = F.re + (size_t)2 * LG_NB * Np;
+  const double* tgi = tgr + LG_NB * LG_NB;
+  lg_block_t<NC>(pn, N - j0, F, false, S);
+  // Z = Y(:, j0:N) V
+  lg_gemm<128, 64, true, true>(
+      M, pw, N - j0,
+      [&](int i, int k, double& ar, double& ai) { ar = Y.r(i, j0 + k); ai = Y.m(i, j0 + k); },
+      [&](int k, int j, double& br, double& bi) { pn.v(j0 + k, j, br, bi); },
+      [&](int i, int j, double cr, double ci) {
+        zr[(size_t)j * Np + i] = cr;
+        zi[(size_t)j * Np + i] = ci;
+      }, S.big);
+  // Z <- Z T
+  lg_gemm<128, 64, true, true>(
+      M, pw, pw,
+      [&](int i, int k, double& ar, double& ai) {
+        ar = zr[(size_t)k * Np + i];
+        ai = zi[(size_t)k * Np + i];
+      },
+      [&](int k, int j, double& br, double& bi) {
+        br = tgr[j * LG_NB + k];
+        bi = tgi[j * LG_NB + k];
+      },
+      [&](int i, int j, double cr, double ci) {
+        zr[(size_t)j * Np + i] = cr;
+        zi[(size_t)j * Np + i] = ci;
+      }, S.big);
+  // Y(:, j0:N) -= Z V^H
+  lg_gemm_sub<128, 128, true, true>(
+      M, N - j0, pw,
+      [&](int i, int k, double& ar, double& ai) {
+        ar = zr[(size_t)k * Np + i];
+        ai = zi[(size_t)k * Np + i];
+      },
+      [&](int k, int j, double& br, double& bi) {
+        double vr, vi;
+        pn.v(j0 + j, k, vr, vi);
+        br = vr;
+        bi = -vi;
+      },
+      [&](int i, int j, double& cr, double& ci) {
+        cr = Y.r(i, j0 + j);
+        ci = Y.m(i, j0 + j);
+      },
+      [&](int i, int j, double cr, double ci) {
+        Y.r(i, j0 + j) = cr;
+        Y.m(i, j0 + j) = ci;
       }, S.big);
 }
 
@@ -738,6 +814,19 @@ __device__ void lg_apply_qh(CMat W, int N, CMat Y, CMat F, const double* tst, Sm
       const LgPanel pn{W, S.u0r, S.u0i, j0, pw, nullptr};
       lg_apply_panel<NC>(pn, tst + (size_t)p * LG_TDBL, Y, 0, N - j0, N, F, true, nullptr, S);
     }
+  }
+}
+
+// Y <- Y Q (M rows, all N columns; Q = H_0 ... H_{N-1} of the factor in W),
+// forward over the blocks of lg_form_q: 8 M N^2 flops instead of forming Q
+// (16/3 N^3) and multiplying by it (8 M N^2).  Requires lg_block_fits(F.ld).
+template <int NC>
+__device__ void lg_right_apply_q(CMat W, int N, CMat Y, int M, CMat F, SmemC<NC>& S) {
+  const int nb = (N + LG_NB - 1) / LG_NB;
+  for (int b = 0; b < nb; ++b) {
+    const int j0 = b * LG_NB, pw = min(LG_NB, N - j0);
+    const LgPanel pn{W, S.u0r, S.u0i, j0, pw, nullptr};
+    lg_apply_block_right<NC>(pn, Y, M, N, F, S);
   }
 }
 
