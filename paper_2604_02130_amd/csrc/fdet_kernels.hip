@@ -50,16 +50,10 @@ __device__ __forceinline__ void qr_form_q(CMat W, int N, CMat Q, CMat F, const d
   __syncthreads();
 }
 
-// C = A B with A, B real or complex (AC, BC).  In the large class a real
-// operand is exp(+-dk K), shared by every item of the problem (and cached),
-// while the complex one is the item's own: the macro tiles are stretched
-// along the real operand (256 x 64 for E B, 64 x 256 for A E) so that the
-// private operand is streamed half as often as with square 128 x 128 tiles.
+// C = A B with A, B real or complex (AC, BC)
 template <int NC, bool AC, bool BC, class LA, class LB, class ST>
 __device__ __forceinline__ void mm(int Np, LA la, LB lb, ST st, SmemC<NC>& S) {
   if constexpr (NC <= 128) gemm_lds<NC, AC, BC>(Np, la, lb, st, S.big);
-  else if constexpr (!AC && BC) lg_gemm<256, 64, AC, BC>(Np, Np, Np, la, lb, st, S.big);
-  else if constexpr (AC && !BC) lg_gemm<64, 256, AC, BC>(Np, Np, Np, la, lb, st, S.big);
   else lg_gemm<128, 128, AC, BC>(Np, Np, Np, la, lb, st, S.big);
 }
 
