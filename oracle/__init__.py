@@ -44,4 +44,7 @@ from .closed_form import (  # noqa: F401
     uniform_field_displaced_greens,
     uniform_field_taylor_logdet_greens,
     two_site,
+    two_site_displaced,
+    two_site_taylor,
+    two_site_slice_response,
 )

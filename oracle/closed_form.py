@@ -162,6 +162,10 @@ def uniform_field_taylor_logdet_greens(L: int, dk: float, Nt: int, theta: float,
 # linear-algebra library: M = 1 + B_{N_t} ... B_1 (Sec. 2), G = M^{-1}, and
 # F_{t,x} = i (1 - G~_t)_{xx} with G~_t = (1 + B_{t-1} ... B_1 B_{N_t} ... B_t)^{-1}
 # (Sec. 4 response formula, phi_{t,x} entering B_t = E diag(e^{i phi_t})).
+# The time-displaced G(t, t0) follows from the rows of the block fermion
+# matrix instead of eq. sausage_all_in_denominator: G(t0, t0) = G~_{t0}, and
+# each block row says G(t + 1, t0) = B_t G(t, t0) for t + 1 != t0, with the
+# sign of the anti-periodic corner when the propagation wraps past slice N_t.
 # ---------------------------------------------------------------------------
 
 def _mul2(a, b):
@@ -232,3 +236,64 @@ def uniform_field_displaced_greens(K: np.ndarray, dk: float, c, t: int, t0: int)
     den = np.where(big, np.exp(-x * Nt) + np.exp(1j * theta), 1.0 + np.exp(1j * theta) * np.exp(x * Nt))
     d = pre * np.exp(1j * a) * num / den
     return (U * d[None, :]) @ U.T
+
+
+def _two_site_slices(cosh_part: float, sinh_part: float, phi):
+    """B_t = (c 1 + s K) diag(e^{i phi_t}) for K = [[0, 1], [1, 0]]."""
+    out = []
+    for row in phi:
+        e0, e1 = cmath.exp(1j * row[0]), cmath.exp(1j * row[1])
+        out.append([[cosh_part * e0, sinh_part * e1], [sinh_part * e0, cosh_part * e1]])
+    return out
+
+
+def _two_site_prod(slices, ts):
+    m = [[1.0 + 0j, 0j], [0j, 1.0 + 0j]]
+    for t in ts:   # later slices on the left
+        m = _mul2(slices[t], m)
+    return m
+
+
+def two_site_displaced(dk: float, phi, t: int, t0: int) -> np.ndarray:
+    """G(t, t0) of the two-site system (1-based slices): G~_{t0} of the
+    cyclic product from slice t0, propagated by the slices between t0 and t:
+    G(t, t0) = B_{t-1} ... B_{t0} G~_{t0} for t > t0, and
+    G(t, t0) = -B_{t-1} ... B_1 B_{N_t} ... B_{t0} G~_{t0} for t < t0."""
+    nt = len(phi)
+    sl = _two_site_slices(math.cosh(dk), math.sinh(dk), phi)
+    r0 = t0 - 1
+    gt, _ = _inv_one_plus2(_two_site_prod(sl, list(range(r0, nt)) + list(range(0, r0))))
+    if t == t0:
+        g = gt
+    elif t > t0:
+        g = _mul2(_two_site_prod(sl, range(r0, t - 1)), gt)
+    else:
+        p = _mul2(_two_site_prod(sl, list(range(r0, nt)) + list(range(0, t - 1))), gt)
+        g = [[-p[0][0], -p[0][1]], [-p[1][0], -p[1][1]]]
+    return np.array(g, dtype=complex)
+
+
+def two_site_taylor(dk: float, phi, n: int) -> tuple:
+    """(log det, G) of the two-site system with the slices of Sec. 8: the
+    degree-n Taylor polynomial of exp(dk K) is c 1 + s K with c the even and
+    s the odd terms of sum_{j <= n} dk^j / j! (K^2 = 1)."""
+    c = sum(dk ** j / math.factorial(j) for j in range(0, n + 1, 2))
+    s_ = sum(dk ** j / math.factorial(j) for j in range(1, n + 1, 2))
+    sl = _two_site_slices(c, s_, phi)
+    g, det = _inv_one_plus2(_two_site_prod(sl, range(len(phi))))
+    return _wrap(cmath.log(det)), np.array(g, dtype=complex)
+
+
+def two_site_slice_response(dk: float, phi, a) -> np.ndarray:
+    """tr((1 - G~_t) A) for every slice t of the two-site system, A 2 x 2."""
+    nt = len(phi)
+    sl = _two_site_slices(math.cosh(dk), math.sinh(dk), phi)
+    out = []
+    for t in range(nt):
+        gt, _ = _inv_one_plus2(_two_site_prod(sl, list(range(t, nt)) + list(range(0, t))))
+        acc = 0j
+        for x in range(2):
+            for y in range(2):
+                acc += ((1.0 if x == y else 0.0) - gt[x][y]) * a[y][x]
+        out.append(acc)
+    return np.array(out, dtype=complex)

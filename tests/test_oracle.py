@@ -515,6 +515,65 @@ def test_golden_two_site_brute_force_and_stabilised():
         assert abs(d) <= 1e-12
 
 
+def _golden_two_site_extra():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "two_site.json")
+    with open(path) as f:
+        doc = json.load(f)
+    cz = lambda z: complex(*z)   # noqa: E731
+    for c in doc["cases"]:
+        disp = {(d["t"], d["t0"]): np.array([[cz(z) for z in row] for row in d["G"]])
+                for d in c["displaced"]}
+        tay = (cz(c["taylor4"]["logdet"]),
+               np.array([[cz(z) for z in row] for row in c["taylor4"]["G"]]))
+        A = np.array([[cz(z) for z in row] for row in c["response"]["A"]])
+        tr = np.array([cz(z) for z in c["response"]["traces"]])
+        yield c["dk"], np.array(c["phi"], dtype=float), disp, tay, A, tr
+
+
+def test_golden_two_site_extras_match_closed_forms_and_block_inverse():
+    """The stored displaced G, Taylor-slice log det / G and per-slice
+    responses are those of the 2 x 2 closed forms, and those closed forms
+    agree with the block inverse of the matching slices (the displaced G is
+    built there from the block rows, not from eq. sausage_all_in_denominator)."""
+    K = np.array([[0.0, 1.0], [1.0, 0.0]])
+    for dk, phi, disp, (lt, Gt), A, tr in _golden_two_site_extra():
+        Nt = len(phi)
+        Minv = np.linalg.inv(O.block_fermion_matrix(K, dk, phi))
+        for (t, t0), Gd in disp.items():
+            assert np.abs(O.two_site_displaced(dk, phi.tolist(), t, t0) - Gd).max() <= 1e-15
+            assert np.abs(Minv[(t - 1) * 2:t * 2, (t0 - 1) * 2:t0 * 2] - Gd).max() \
+                <= 1e-12 * max(1.0, np.abs(Gd).max())
+        assert len(disp) == Nt * Nt
+        l2, G2 = O.two_site_taylor(dk, phi.tolist(), 4)
+        assert abs(wrapped_diff(l2, lt)) <= 1e-15 * abs(lt) and np.abs(G2 - Gt).max() <= 1e-15
+        Mb = O.block_matrix_of_slices(O.taylor_slice_matrices(K, dk, phi, 4))
+        sg, la = np.linalg.slogdet(Mb)
+        assert rel_err(complex(la, np.angle(sg)), lt) <= 1e-12
+        assert np.abs(np.linalg.inv(Mb)[:2, :2] - Gt).max() <= 1e-12
+        assert np.abs(O.two_site_slice_response(dk, phi.tolist(), A) - tr).max() <= 1e-15
+        want = [np.trace((np.eye(2) - Minv[t * 2:(t + 1) * 2, t * 2:(t + 1) * 2]) @ A)
+                for t in range(Nt)]
+        assert np.abs(np.array(want) - tr).max() <= 1e-12 * max(1.0, np.abs(tr).max())
+
+
+def test_golden_two_site_extras_against_the_oracle():
+    """The oracle's displaced G (Sec. 7 steps 7-9 as written and the split
+    close), its intermediate-volume variant (Sec. 9, n = 4, QR every 1, 3 and
+    5 slices) and its per-slice responses against the stored values."""
+    K = np.array([[0.0, 1.0], [1.0, 0.0]])
+    for dk, phi, disp, (lt, Gt), A, tr in _golden_two_site_extra():
+        for (t, t0), Gd in disp.items():
+            bar = 1e-12 * max(1.0, np.abs(Gd).max())
+            assert np.abs(O.displaced_greens(K, dk, phi, t, t0) - Gd).max() <= bar, (t, t0)
+            assert np.abs(O.dsplit_displaced_greens(K, dk, phi, t, t0) - Gd).max() <= bar, (t, t0)
+        for s in (1, 3, 5):
+            l2, G2 = O.sparse_logdet_greens(K, dk, phi, 4, s)
+            assert rel_err(l2, lt) <= 1e-12 and np.abs(G2 - Gt).max() <= 1e-12
+        assert np.abs(O.slice_response(K, dk, phi, A) - tr).max() <= 1e-12 * max(1.0, np.abs(tr).max())
+
+
 def test_response_pins_catch_planted_mistakes():
     """A transposed operand and a dropped identity must fail the pins above."""
     rng = np.random.default_rng(3)
