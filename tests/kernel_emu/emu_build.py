@@ -9,9 +9,9 @@ header hip/hip_runtime.h of this folder:
         private arrays and of shared-memory objects, and indexes past a member
         array of the shared-memory struct.
   race  the kernels instrumented for emu_race.cpp: races between waves of a
-        workgroup (no barrier between two accesses, one a write), between
-        workgroups of one launch, and reads of shared memory the workgroup
-        never wrote.
+        workgroup and between lanes of one wave (no barrier between two
+        accesses, one a write), between workgroups of one launch, and reads of
+        shared memory the workgroup never wrote.
 
 Only the size classes asked for are compiled (32 and 512 by default: the
 register/LDS code and the blocked code); the others are stubs that fail

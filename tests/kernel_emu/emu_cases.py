@@ -9,7 +9,8 @@ results with the oracle and prints one JSON line: the largest deviation
 (relative to max(1, max |oracle value|); log det relative to max(1, |log det|)),
 the status words and the run's counters (launches, workgroups, barriers,
 wave-level operations, barrier-site mismatches and, for the race build, the
-number of distinct races).  A sanitizer finding or an emulation error aborts
+numbers of distinct races between waves or workgroups and between lanes of one
+wave).  A sanitizer finding or an emulation error aborts
 the process before that line is printed.  For the AddressSanitizer build the
 caller preloads its runtime.
 """
@@ -308,9 +309,9 @@ def main():
            "launches": st[0], "groups": st[1], "barriers": st[2], "wave_ops": st[3], "mfma": st[4],
            "barrier_site_mismatch": st[5]}
     if hasattr(lib, "emu_race_stats"):
-        rs = (C.c_uint64 * 2)()
+        rs = (C.c_uint64 * 3)()
         lib.emu_race_stats(rs)
-        out["races"], out["checked_accesses"] = rs[0], rs[1]
+        out["races"], out["checked_accesses"], out["lane_races"] = rs[0], rs[1], rs[2]
     print(json.dumps(out), flush=True)
 
 

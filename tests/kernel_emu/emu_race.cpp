@@ -7,8 +7,11 @@
 //   * two workgroups of one launch touch a granule, at least one writing
 //                                                          -> inter-group race
 //   * a workgroup reads shared memory it has not written    -> undefined read
-// Lanes of one wave run in lockstep on the hardware, so they never race
-// with each other here.  Atomic operations are not recorded.
+//   * two lanes of one wave touch a granule between the same pair of
+//     barriers, one of them writing                         -> lane race
+//     (the lanes run in lockstep, but the compiler orders each lane's
+//     accesses as if no other lane touched them)
+// Atomic operations are not recorded.
 #include "hip/hip_runtime.h"
 
 #include <dlfcn.h>
@@ -37,8 +40,10 @@ struct Cell {
   uint32_t rl, rg;       // launch and group of the last read
   uint64_t re;           // epoch of the reads recorded in rmask
   uint16_t wwave, rmask; // writing wave, reading waves (bit per wave) in epoch re
+  uint16_t wtid, rtid;   // writing lane (thread index), first reading lane in epoch re
   uint8_t rmulti;        // read by more than one group in launch rl
-  uint8_t pad[3];
+  uint8_t rtmulti;       // read by more than one lane in epoch re
+  uint8_t pad[2];
 };
 
 struct Region {
@@ -52,7 +57,7 @@ std::map<uintptr_t, Region> regions;   // by base
 Region lds{0, 0, nullptr, -1};
 Region* last = nullptr;
 int next_id = 0;
-uint64_t n_reports = 0, n_checked = 0;
+uint64_t n_reports = 0, n_checked = 0, n_lane_reports = 0;
 std::map<std::pair<void*, void*>, uint64_t> seen;   // (pc, other pc) -> count
 
 Region* find(uintptr_t a) {
@@ -73,11 +78,13 @@ void describe(void* pc, char* buf, size_t n) {
     snprintf(buf, n, "%p", pc);
 }
 
-void report(const char* kind, const Region* r, uintptr_t a, void* pc, void* opc, uint32_t og, int ow) {
+void report(const char* kind, const Region* r, uintptr_t a, void* pc, void* opc, uint32_t og, int ow,
+            bool lanes = false) {
   auto key = std::make_pair(pc, opc);
   if (seen[key]++ > 0) return;
-  n_reports++;
-  if (n_reports > 60) return;
+  if (lanes) n_lane_reports++;
+  else n_reports++;
+  if (n_reports + n_lane_reports > 60) return;
   char b1[512], b2[512];
   describe(pc, b1, sizeof b1);
   describe(opc, b2, sizeof b2);
@@ -97,7 +104,7 @@ inline void access(uintptr_t a, size_t size, bool write, void* pc) {
   n_checked++;
   const uint32_t L = (uint32_t)emu::g_launch, g = emu::g_group;
   const uint64_t e = emu::g_epoch;
-  const int w = (int)(emu::g_cur->tid.x >> 6);
+  const int t = (int)emu::g_cur->tid.x, w = t >> 6;
   const size_t g0 = (a - r->base) >> 2, g1 = (a + size - 1 - r->base) >> 2;
   if (r == &lds) {
     // shared memory lives for one workgroup: a read must see a write of
@@ -107,13 +114,22 @@ inline void access(uintptr_t a, size_t size, bool write, void* pc) {
       const bool mine = c.wpc && c.wl == L && c.wg == g;
       if (write) {
         if (mine && c.we == e && c.wwave != w) report("shared write after write by another wave, no barrier", r, a, pc, c.wpc, c.wg, c.wwave);
-        if (c.rl == L && c.rg == g && c.re == e && (c.rmask & ~(1u << w))) report("shared write after read by another wave, no barrier", r, a, pc, nullptr, c.rg, -1);
-        c.wl = L; c.wg = g; c.we = e; c.wwave = (uint16_t)w; c.wpc = pc;
+        else if (mine && c.we == e && c.wtid != t) report("shared write after write by another lane of the wave, no barrier", r, a, pc, c.wpc, c.wg, c.wwave, true);
+        if (c.rl == L && c.rg == g && c.re == e) {
+          if (c.rmask & ~(1u << w)) report("shared write after read by another wave, no barrier", r, a, pc, nullptr, c.rg, -1);
+          else if (c.rtid != t || c.rtmulti) report("shared write after read by another lane of the wave, no barrier", r, a, pc, nullptr, c.rg, -1, true);
+        }
+        c.wl = L; c.wg = g; c.we = e; c.wwave = (uint16_t)w; c.wtid = (uint16_t)t; c.wpc = pc;
       } else {
         if (!mine) report("shared read of a value this workgroup never wrote", r, a, pc, c.wpc, c.wg, c.wwave);
         else if (c.we == e && c.wwave != w) report("shared read after write by another wave, no barrier", r, a, pc, c.wpc, c.wg, c.wwave);
-        if (c.rl == L && c.rg == g && c.re == e) c.rmask |= (uint16_t)(1u << w);
-        else { c.rl = L; c.rg = g; c.re = e; c.rmask = (uint16_t)(1u << w); }
+        else if (c.we == e && c.wtid != t) report("shared read after write by another lane of the wave, no barrier", r, a, pc, c.wpc, c.wg, c.wwave, true);
+        if (c.rl == L && c.rg == g && c.re == e) {
+          c.rmask |= (uint16_t)(1u << w);
+          if (c.rtid != t) c.rtmulti = 1;
+        } else {
+          c.rl = L; c.rg = g; c.re = e; c.rmask = (uint16_t)(1u << w); c.rtid = (uint16_t)t; c.rtmulti = 0;
+        }
       }
     }
     return;
@@ -124,24 +140,31 @@ inline void access(uintptr_t a, size_t size, bool write, void* pc) {
       if (c.wl == L && c.wpc) {
         if (c.wg != g) report("write after write by another workgroup", r, a, pc, c.wpc, c.wg, c.wwave);
         else if (c.we == e && c.wwave != w) report("write after write by another wave, no barrier", r, a, pc, c.wpc, c.wg, c.wwave);
+        else if (c.we == e && c.wtid != t) report("write after write by another lane of the wave, no barrier", r, a, pc, c.wpc, c.wg, c.wwave, true);
       }
       if (c.rl == L) {
         if (c.rg != g || c.rmulti) report("write after read by another workgroup", r, a, pc, nullptr, c.rg, -1);
         else if (c.re == e && (c.rmask & ~(1u << w))) report("write after read by another wave, no barrier", r, a, pc, nullptr, c.rg, -1);
+        else if (c.re == e && (c.rtid != t || c.rtmulti)) report("write after read by another lane of the wave, no barrier", r, a, pc, nullptr, c.rg, -1, true);
       }
-      c.wl = L; c.wg = g; c.we = e; c.wwave = (uint16_t)w; c.wpc = pc;
+      c.wl = L; c.wg = g; c.we = e; c.wwave = (uint16_t)w; c.wtid = (uint16_t)t; c.wpc = pc;
     } else {
       if (c.wl == L && c.wpc) {
         if (c.wg != g) report("read of a value written by another workgroup", r, a, pc, c.wpc, c.wg, c.wwave);
         else if (c.we == e && c.wwave != w) report("read after write by another wave, no barrier", r, a, pc, c.wpc, c.wg, c.wwave);
+        else if (c.we == e && c.wtid != t) report("read after write by another lane of the wave, no barrier", r, a, pc, c.wpc, c.wg, c.wwave, true);
       }
       if (c.rl == L && c.rg == g) {
-        if (c.re == e) c.rmask |= (uint16_t)(1u << w);
-        else { c.re = e; c.rmask = (uint16_t)(1u << w); }
+        if (c.re == e) {
+          c.rmask |= (uint16_t)(1u << w);
+          if (c.rtid != t) c.rtmulti = 1;
+        } else {
+          c.re = e; c.rmask = (uint16_t)(1u << w); c.rtid = (uint16_t)t; c.rtmulti = 0;
+        }
       } else {
         if (c.rl == L && c.rg != g) c.rmulti = 1;
         else c.rmulti = 0;
-        c.rl = L; c.rg = g; c.re = e; c.rmask = (uint16_t)(1u << w);
+        c.rl = L; c.rg = g; c.re = e; c.rmask = (uint16_t)(1u << w); c.rtid = (uint16_t)t; c.rtmulti = 0;
       }
     }
   }
@@ -167,7 +190,7 @@ void emu_race_lds_setup() {
   lds.n = __stop_emu_lds - __start_emu_lds;
   lds.sh = (Cell*)calloc((lds.n + 3) / 4 + 1, sizeof(Cell));
 }
-void emu_race_stats(uint64_t* out) { out[0] = n_reports; out[1] = n_checked; }
+void emu_race_stats(uint64_t* out) { out[0] = n_reports; out[1] = n_checked; out[2] = n_lane_reports; }
 
 void __tsan_init() {}
 void __tsan_func_entry(void*) {}

@@ -14,6 +14,9 @@
 //                  its end
 //   divergent_wave the emulator: half a wave at a shuffle, the other half at a
 //                  barrier (reported as a deadlock)
+//   lane_race      race build: a lane reads shared memory that another lane of
+//                  its own wave writes, with no barrier in between (the
+//                  compiler may reorder one lane's accesses around it)
 #include <hip/hip_runtime.h>
 
 #include <stdio.h>
@@ -68,6 +71,10 @@ __global__ void k_selftest(double* out, int n, int mode) {
       if (lane < 32) v = __shfl(S.a[t], 0, 64);
       __syncthreads();
       break;
+    case 8:   // lane_race
+      v = S.a[(t & ~63) | ((t + 1) & 63)];
+      __syncthreads();
+      break;
     default:  // ok
       __syncthreads();
       v = S.a[(t + 64) % 512] + S.b[lane];
@@ -82,9 +89,9 @@ extern "C" void emu_stats(uint64_t*);
 
 int main(int argc, char** argv) {
   static const char* modes[] = {"ok", "wave_race", "group_race", "uninit_shared", "member_oob",
-                                "heap_oob", "private_oob", "divergent_wave"};
+                                "heap_oob", "private_oob", "divergent_wave", "lane_race"};
   int mode = -1;
-  for (int m = 0; m < 8; ++m)
+  for (int m = 0; m < 9; ++m)
     if (argc > 1 && strcmp(argv[1], modes[m]) == 0) mode = m;
   if (mode < 0) {
     fprintf(stderr, "usage: %s <mode>\n", argv[0]);
@@ -94,12 +101,13 @@ int main(int argc, char** argv) {
   double* d = nullptr;
   if (hipMalloc((void**)&d, n * sizeof(double)) != hipSuccess) return 3;
   hipLaunchKernelGGL(k_selftest, dim3(groups), dim3(512), 0, 0, d, n, mode);
-  uint64_t races[2] = {0, 0};
+  uint64_t races[3] = {0, 0, 0};
   if (emu_race_stats) emu_race_stats(races);
   uint64_t st[6];
   emu_stats(st);
-  printf("{\"mode\": \"%s\", \"races\": %llu, \"barrier_site_mismatch\": %llu}\n", modes[mode],
-         (unsigned long long)races[0], (unsigned long long)st[5]);
+  printf("{\"mode\": \"%s\", \"races\": %llu, \"lane_races\": %llu, \"barrier_site_mismatch\": %llu}\n",
+         modes[mode], (unsigned long long)races[0], (unsigned long long)races[2],
+         (unsigned long long)st[5]);
   hipFree(d);
   return 0;
 }
