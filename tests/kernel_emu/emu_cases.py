@@ -275,6 +275,199 @@ def case_sparse(cfg, n=4, s=4):
     return worst, st.get(np.int32, (1,)).tolist()
 
 
+FD_WHAT_LOGDET, FD_WHAT_UDV, FD_WHAT_HMC = 0, 3, 4
+FD_REUSE_E, FD_KEEP_CHECKPOINTS = 0x1, 0x8
+
+
+def bits_equal(a, b):
+    return np.array_equal(np.atleast_1d(np.asarray(a)).view(np.uint8), np.atleast_1d(np.asarray(b)).view(np.uint8))
+
+
+def case_plans():
+    """Prepared force and G plans, each launched twice, against the eager
+    calls bit for bit; a plan with FD_REUSE_E on the eager call's workspace."""
+    cfgs = [honeycomb(3, 16, 2.0, 71), honeycomb(2, 8, 1.0, 72)]
+    n = len(cfgs)
+    P, keep = problems(cfgs)
+    worst = 0.0
+    fsz = sum(K.shape[0] * phi.shape[0] for K, phi, _ in cfgs)
+    gsz = sum(2 * K.shape[0] ** 2 for K, _, _ in cfgs)
+    for what in (FD_WHAT_GREENS, FD_WHAT_FORCE):
+        o = Opts(4, 4, 0, 0)
+        ws_n = lib.fd_workspace_bytes(P, n, C.byref(o), what)
+        outs = []
+        for mode in ("eager", "plan", "reuse"):
+            ws, ld, st, G = Buf(ws_n), Buf(16 * n), Buf(4 * n), Buf(8 * gsz)
+            F, Fi = Buf(8 * fsz), Buf(8 * fsz)
+            args = (C.c_void_p(ld.p), C.c_void_p(G.p))
+            fargs = (C.c_void_p(F.p), C.c_void_p(Fi.p))
+            if mode in ("eager", "reuse"):
+                if what == FD_WHAT_GREENS:
+                    check(lib.fd_greens_batched(P, n, C.byref(o), *args, C.c_void_p(ws.p), C.c_size_t(ws_n),
+                                                C.c_void_p(st.p), None), "greens")
+                else:
+                    check(lib.fd_force_batched(P, n, C.byref(o), C.c_void_p(ld.p), *fargs, C.c_void_p(ws.p),
+                                               C.c_size_t(ws_n), C.c_void_p(st.p), None), "force")
+            if mode in ("plan", "reuse"):
+                o2 = Opts(4, 4, 0, FD_REUSE_E if mode == "reuse" else 0)
+                plan = C.c_void_p()
+                check(lib.fd_plan_create(what, P, n, C.byref(o2), *args, *(fargs if what == FD_WHAT_FORCE else
+                                                                            (None, None)),
+                                         C.c_void_p(ws.p), C.c_size_t(ws_n), C.c_void_p(st.p), None,
+                                         C.byref(plan)), "plan_create")
+                for _ in range(2):
+                    check(lib.fd_plan_launch(plan, None), "plan_launch")
+                lib.fd_plan_destroy(plan)
+            res = [ld.get(np.float64, (n, 2))]
+            res.append(G.get(np.float64, (gsz,)) if what == FD_WHAT_GREENS else F.get(np.float64, (fsz,)))
+            assert st.get(np.int32, (n,)).tolist() == [0] * n
+            outs.append(res)
+        for o_ in outs[1:]:
+            for a, b in zip(outs[0], o_):
+                if not bits_equal(a, b):
+                    worst = max(worst, 1.0)
+    # the eager results against the oracle
+    w2, st = check_force(cfgs, 4, 4)
+    return max(worst, w2), st
+
+
+def case_keep_checkpoints():
+    """G with FD_KEEP_CHECKPOINTS, then the force from its checkpoints, against
+    the full force (and the oracle)."""
+    cfg = honeycomb(3, 16, 2.0, 73)
+    K, phi, dk = cfg
+    P, keep = problems([cfg])
+    o = Opts(4, 4, 0, FD_KEEP_CHECKPOINTS)
+    ws_n = lib.fd_workspace_bytes(P, 1, C.byref(o), FD_WHAT_FORCE)
+    ws, ld, st, G = Buf(ws_n), Buf(16), Buf(4), Buf(16 * 18 * 18)
+    F, Fi = Buf(8 * 16 * 18), Buf(8 * 16 * 18)
+    check(lib.fd_greens(P, C.byref(o), C.c_void_p(ld.p), C.c_void_p(G.p), C.c_void_p(ws.p), C.c_size_t(ws_n),
+                        C.c_void_p(st.p), None), "greens keep")
+    check(lib.fd_force(P, C.byref(o), None, C.c_void_p(F.p), C.c_void_p(Fi.p), C.c_void_p(ws.p),
+                       C.c_size_t(ws_n), C.c_void_p(st.p), None), "force keep")
+    f = (F.get(np.float64, (16, 18)) + 1j * Fi.get(np.float64, (16, 18)))
+    full, _, _ = run_force([cfg], 4, 4)
+    lo, Go = O.stabilised_logdet_greens(K, dk, phi)
+    l = ld.get(np.float64, (2,))
+    worst = max(rel(f, full[0]), rel(f, O.stabilised_force(K, dk, phi)), dlog(complex(l[0], l[1]), lo),
+                rel(cplx(G.get(np.float64, (18, 18, 2))), Go))
+    return worst, st.get(np.int32, (1,)).tolist()
+
+
+def case_udv_exp():
+    """fd_udv: X unitary, X diag(D) T = B_{N_t} ... B_1; fd_slice_exponential
+    against exp(dk K)."""
+    cfg = honeycomb(3, 8, 0.5, 74)
+    K, phi, dk = cfg
+    N = 18
+    P, keep = problems([cfg])
+    o = Opts(4, 0, 0, 0)
+    ws_n = lib.fd_workspace_bytes(P, 1, C.byref(o), FD_WHAT_UDV)
+    ws, st = Buf(ws_n), Buf(4)
+    X, D, T = Buf(16 * N * N), Buf(8 * N), Buf(16 * N * N)
+    check(lib.fd_udv(P, C.byref(o), C.c_void_p(X.p), C.c_void_p(D.p), C.c_void_p(T.p), C.c_void_p(ws.p),
+                     C.c_size_t(ws_n), C.c_void_p(st.p), None), "udv")
+    x, d, t = cplx(X.get(np.float64, (N, N, 2))), D.get(np.float64, (N,)), cplx(T.get(np.float64, (N, N, 2)))
+    prod = np.eye(N, dtype=complex)
+    for B in O.slice_matrices(K, dk, phi):
+        prod = B @ prod
+    worst = max(rel((x * d) @ t, prod), float(np.abs(x.conj().T @ x - np.eye(N)).max()))
+    ws_e = lib.fd_workspace_bytes(P, 1, C.byref(o), FD_WHAT_LOGDET)
+    wse, E = Buf(ws_e), Buf(8 * N * N)
+    check(lib.fd_slice_exponential(P, C.c_void_p(E.p), C.c_void_p(wse.p), C.c_size_t(ws_e), None), "exp")
+    worst = max(worst, rel(E.get(np.float64, (N, N)), O.slice_exponential(K, dk)))
+    return worst, st.get(np.int32, (1,)).tolist()
+
+
+def case_observables():
+    """fd_response_trace (A and the fermion number) and fd_diag_response
+    against the oracle, on the library's own G and force."""
+    cfg = honeycomb(3, 16, 2.0, 75)
+    K, phi, dk = cfg
+    N, Nt = 18, 16
+    lds, Gs, st = run_greens([cfg], 4)
+    Fs, st2, _ = run_force([cfg], 4, 4)
+    rng = np.random.default_rng(76)
+    A = rng.normal(size=(N, N)) + 1j * rng.normal(size=(N, N))
+    a = rng.normal(size=N)
+    g_il = np.stack([Gs[0].real, Gs[0].imag], -1)
+    bG = Buf(g_il.nbytes, g_il)
+    a_il = np.stack([A.real, A.imag], -1)
+    bA = Buf(a_il.nbytes, a_il)
+    lib.fd_response_trace_workspace_bytes.restype = C.c_size_t
+    wn = lib.fd_response_trace_workspace_bytes(N)
+    ws, out = Buf(wn), Buf(16)
+    worst = 0.0
+    for Aop, ref in ((bA, O.response_trace(Gs[0], A)), (None, O.response_trace(Gs[0]))):
+        check(lib.fd_response_trace(N, C.c_void_p(bG.p), C.c_void_p(Aop.p if Aop else None), C.c_void_p(out.p),
+                                    C.c_void_p(ws.p), C.c_size_t(wn), None), "trace")
+        r = out.get(np.float64, (2,))
+        worst = max(worst, abs(complex(r[0], r[1]) - ref) / max(1.0, abs(ref)))
+    f = Fs[0]
+    bF, bFi, ba = Buf(8 * N * Nt, np.ascontiguousarray(f.real)), Buf(8 * N * Nt, np.ascontiguousarray(f.imag)), Buf(8 * N, a)
+    check(lib.fd_diag_response(Nt, N, C.c_void_p(bF.p), C.c_void_p(bFi.p), C.c_void_p(ba.p), C.c_void_p(out.p),
+                               None), "diag")
+    r = out.get(np.float64, (2,))
+    ref = O.diag_response(f, a)
+    worst = max(worst, abs(complex(r[0], r[1]) - ref) / max(1.0, abs(ref)))
+    return worst, st + st2
+
+
+def case_leapfrog():
+    """fd_hmc_leapfrog against the oracle's leapfrog, and the prepared
+    trajectory (fd_hmc_plan_*) against fd_hmc_leapfrog bit for bit."""
+    K, phi0, dk = honeycomb(2, 8, 1.0, 77)
+    N, Nt = 8, 8
+    dU, eps, nsteps = dk * 3.0, 0.05, 2
+    pi0 = np.random.default_rng(78).normal(size=(Nt, N))
+    ph_o, pi_o, dH_o = O.hmc_leapfrog(K, dk, phi0, pi0, dU, eps, nsteps)
+    res = []
+    for mode in ("call", "plan"):
+        bK, bphi, bpi = Buf(K.nbytes, K), Buf(phi0.nbytes, phi0), Buf(pi0.nbytes, pi0)
+        P = (Prob * 1)(Prob(N, Nt, dk, bK.p, bphi.p))
+        o = Opts(4, 4, 0, 0)
+        ws_n = lib.fd_workspace_bytes(P, 1, C.byref(o), FD_WHAT_HMC)
+        ws, dH, st = Buf(ws_n), Buf(8), Buf(4)
+        if mode == "call":
+            check(lib.fd_hmc_leapfrog(P, 1, C.byref(o), C.c_double(dU), C.c_double(eps), nsteps, C.c_void_p(bpi.p),
+                                      C.c_void_p(dH.p), C.c_void_p(ws.p), C.c_size_t(ws_n), C.c_void_p(st.p), None),
+                  "leapfrog")
+        else:
+            plan = C.c_void_p()
+            check(lib.fd_hmc_plan_create(P, 1, C.byref(o), C.c_double(dU), C.c_double(eps), nsteps,
+                                         C.c_void_p(bpi.p), C.c_void_p(dH.p), C.c_void_p(ws.p), C.c_size_t(ws_n),
+                                         C.c_void_p(st.p), None, C.byref(plan)), "hmc plan")
+            check(lib.fd_hmc_plan_launch(plan, None), "hmc plan launch")
+            lib.fd_hmc_plan_destroy(plan)
+        res.append((bphi.get(np.float64, (Nt, N)), bpi.get(np.float64, (Nt, N)), dH.get(np.float64, (1,))[0],
+                    st.get(np.int32, (1,)).tolist()))
+    worst = max(rel(res[0][0], ph_o), rel(res[0][1], pi_o), abs(res[0][2] - dH_o) / max(1.0, abs(dH_o)))
+    if not (bits_equal(res[0][0], res[1][0]) and bits_equal(res[0][1], res[1][1])
+            and bits_equal(np.float64(res[0][2]), np.float64(res[1][2]))):
+        worst = max(worst, 1.0)
+    return worst, res[0][3] + res[1][3]
+
+
+def case_noalloc():
+    """fd_greens_noalloc against fd_greens bit for bit, two calls in a row,
+    the second smaller."""
+    worst, sts = 0.0, []
+    for cfg in (honeycomb(3, 16, 2.0, 79), honeycomb(2, 8, 1.0, 80)):
+        N = cfg[0].shape[0]
+        P, keep = problems([cfg])
+        o = Opts(4, 0, 0, 0)
+        ld, G, st = Buf(16), Buf(16 * N * N), Buf(4)
+        check(lib.fd_greens_noalloc(P, C.byref(o), C.c_void_p(ld.p), C.c_void_p(G.p), C.c_void_p(st.p), None),
+              "noalloc")
+        lds, Gs, st2 = run_greens([cfg], 4)
+        g = cplx(G.get(np.float64, (N, N, 2)))
+        l = ld.get(np.float64, (2,))
+        if not (bits_equal(g, Gs[0]) and bits_equal(l, np.array([lds[0].real, lds[0].imag]))):
+            worst = 1.0
+        sts += st.get(np.int32, (1,)).tolist() + st2
+    return worst, sts
+
+
 CASES = {
     # class 32 (register QR)
     "greens": lambda: check_greens([honeycomb(3, 16, 2.0, 11)], 4),
@@ -291,6 +484,13 @@ CASES = {
     "b512_force_scans": lambda: check_force(batch_512(53), 4, 2, FD_FORCE_SCANS),
     "b512_displaced": lambda: case_displaced(ring(130, 4, 0.5, 54)),
     "b512_sparse": lambda: case_sparse(ring(130, 4, 0.5, 55)),
+    # further entry points (class 32)
+    "plans": case_plans,
+    "keep_checkpoints": case_keep_checkpoints,
+    "udv_exp": case_udv_exp,
+    "observables": case_observables,
+    "leapfrog": case_leapfrog,
+    "noalloc": case_noalloc,
     # every class (host builds with all classes only)
     "mixed_greens": lambda: check_greens(batch_mixed(61), 4),
     "mixed_force": lambda: check_force(batch_mixed(62), 4, 4),

@@ -17,6 +17,10 @@ never reach and wave-level operations (MFMA, DPP, shuffles) taken by part of a
 wave.  The launch classes built are 32 (register QR, LDS products) and 512
 (blocked QR, MFMA products from device memory), the latter through a batch
 with one N = 130 problem, whose smaller members then run the blocked code too.
+The other entry points run at class 32: prepared plans (launched twice, bit
+for bit the eager calls, also with FD_REUSE_E), FD_KEEP_CHECKPOINTS, fd_udv,
+the slice exponential, the observables, the leapfrog and its prepared
+trajectory, and the allocation-free G (bit for bit fd_greens).
 With FDET_EMU_ALL=1 every class is built, and mixed batches (N = 18 to 128
 in one class-128 launch, each item on its own class's code and the class-128
 shared-memory layout) and a class-80 force run as well (a few minutes more).
@@ -43,7 +47,8 @@ pytestmark = pytest.mark.slow
 
 CASES = ["greens", "force_windows", "force_scans", "response", "displaced", "sparse",
          "batch_greens", "batch_force", "b512_greens", "b512_force", "b512_force_scans",
-         "b512_displaced", "b512_sparse"]
+         "b512_displaced", "b512_sparse",
+         "plans", "keep_checkpoints", "udv_exp", "observables", "leapfrog", "noalloc"]
 ALL = os.environ.get("FDET_EMU_ALL") == "1"
 CLASSES = emu_build.ALL_CLASSES if ALL else (32, 512)
 if ALL:
