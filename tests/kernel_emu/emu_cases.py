@@ -468,6 +468,39 @@ def case_noalloc():
     return worst, sts
 
 
+def case_full_lowT():
+    """lowT_L6 at full size (N = 72, N_t = 256, beta = 32, s = 8) with 32
+    segments, det + G."""
+    from workload import WORKLOADS
+    w = WORKLOADS["lowT_L6"]
+    return check_greens_seg([(w.K(), w.phi(), w.dk)], w.s, 32)
+
+
+def case_full_force_L8():
+    """force_L8 at full size (N = 128, N_t = 256, beta = 32, s = 8, c = 16)."""
+    from workload import WORKLOADS
+    w = WORKLOADS["force_L8"]
+    return check_force([(w.K(), w.phi(), w.dk)], w.s, w.c)
+
+
+def case_n512_force():
+    """The HMC step's shape per field (L = 16, N = 512, delta kappa = 0.125,
+    s = c = 16) on the first 32 slices of field 0: two checkpoint intervals."""
+    from workload import hmc_batch
+    w = hmc_batch(1)[0]
+    phi = np.ascontiguousarray(w.phi()[:32])
+    return check_force([(w.K(), phi, w.dk)], w.s, w.c)
+
+
+def check_greens_seg(cfgs, s, segments):
+    lds, Gs, st = run_greens(cfgs, s, segments)
+    worst = 0.0
+    for (K, phi, dk), l, g in zip(cfgs, lds, Gs):
+        lo, Go = O.stabilised_logdet_greens(K, dk, phi)
+        worst = max(worst, dlog(l, lo), rel(g, Go))
+    return worst, st
+
+
 CASES = {
     # class 32 (register QR)
     "greens": lambda: check_greens([honeycomb(3, 16, 2.0, 11)], 4),
@@ -495,6 +528,10 @@ CASES = {
     "mixed_greens": lambda: check_greens(batch_mixed(61), 4),
     "mixed_force": lambda: check_force(batch_mixed(62), 4, 4),
     "class80_force": lambda: check_force([honeycomb(6, 32, 4.0, 63)], 8, 16),
+    # named workloads at full size, and the HMC step's N = 512 shape (long)
+    "full_lowT_L6": case_full_lowT,
+    "full_force_L8": case_full_force_L8,
+    "full_n512_force": case_n512_force,
 }
 
 

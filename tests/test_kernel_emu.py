@@ -24,6 +24,9 @@ trajectory, and the allocation-free G (bit for bit fd_greens).
 With FDET_EMU_ALL=1 every class is built, and mixed batches (N = 18 to 128
 in one class-128 launch, each item on its own class's code and the class-128
 shared-memory layout) and a class-80 force run as well (a few minutes more).
+FDET_EMU_FULL=1 adds the named workloads at full size (lowT_L6 det + G with
+32 segments, force_L8) and the HMC step's N = 512 shape (field 0's first 32
+slices, s = c = 16): tens of minutes.
 Every case is also compared with the oracle (relative deviation at most
 1e-10), and the checkers are pinned by a self-test that plants each kind of
 mistake in a small kernel and expects it reported.
@@ -49,12 +52,16 @@ CASES = ["greens", "force_windows", "force_scans", "response", "displaced", "spa
          "batch_greens", "batch_force", "b512_greens", "b512_force", "b512_force_scans",
          "b512_displaced", "b512_sparse",
          "plans", "keep_checkpoints", "udv_exp", "observables", "leapfrog", "noalloc"]
-ALL = os.environ.get("FDET_EMU_ALL") == "1"
+FULL = os.environ.get("FDET_EMU_FULL") == "1"
+ALL = FULL or os.environ.get("FDET_EMU_ALL") == "1"
 CLASSES = emu_build.ALL_CLASSES if ALL else (32, 512)
 if ALL:
     CASES += ["mixed_greens", "mixed_force", "class80_force"]
+if FULL:
+    CASES += ["full_lowT_L6", "full_force_L8", "full_n512_force"]
 MODES = ["asan", "race"]
 TOL = 1e-10
+TIMEOUT = 7200 if FULL else 900
 
 # planted mistake -> (build, text the report must contain)
 SELFTEST = {
@@ -79,10 +86,10 @@ def _env(preload):
 
 def _run(cmd, preload):
     try:
-        p = subprocess.run(cmd, capture_output=True, text=True, timeout=900, env=_env(preload))
+        p = subprocess.run(cmd, capture_output=True, text=True, timeout=TIMEOUT, env=_env(preload))
         return p.returncode, p.stdout, p.stderr
     except subprocess.TimeoutExpired:
-        return -1, "", "timed out after 900 s"
+        return -1, "", f"timed out after {TIMEOUT} s"
 
 
 @pytest.fixture(scope="module")
@@ -98,7 +105,8 @@ def emu():
     workers = max(2, min(8, os.cpu_count() or 2))
     with cf.ThreadPoolExecutor(workers) as ex:
         # the longest cases first
-        for case in sorted(CASES, key=lambda c: not c.startswith(("b512", "mixed", "class80"))):
+        for case in sorted(CASES, key=lambda c: (not c.startswith("full"),
+                                                 not c.startswith(("b512", "mixed", "class80")))):
             for m in MODES:
                 jobs[("case", m, case)] = ex.submit(
                     _run, [sys.executable, os.path.join(EMU, "emu_cases.py"), libs[m], case], m == "asan")
