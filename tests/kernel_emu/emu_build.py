@@ -40,6 +40,8 @@ MODES = {
     "asan": (_ASAN, _ASAN, ["-fsanitize=address,array-bounds", "-shared-libasan"], []),
     "race": (["-fsanitize=thread", "-DEMU_LDS_SECTION", "-DEMU_RACE"],
              ["-DEMU_LDS_SECTION", "-DEMU_RACE"], ["-ldl"], ["emu_race.cpp"]),
+    # no checker: the fastest build, for counting work (MFMA instructions per launch)
+    "plain": (["-O2"], ["-O2"], [], []),
 }
 
 

@@ -10,9 +10,10 @@ results with the oracle and prints one JSON line: the largest deviation
 the status words and the run's counters (launches, workgroups, barriers,
 wave-level operations, barrier-site mismatches and, for the race build, the
 numbers of distinct races between waves or workgroups and between lanes of one
-wave).  A sanitizer finding or an emulation error aborts
-the process before that line is printed.  For the AddressSanitizer build the
-caller preloads its runtime.
+wave), and per launch its workgroups, MFMA instructions (per wave) and barrier
+arrivals.  A sanitizer finding or an emulation error aborts the process before
+that line is printed.  For the AddressSanitizer build the caller preloads its
+runtime.
 """
 from __future__ import annotations
 
@@ -545,6 +546,9 @@ def main():
     out = {"case": name, "worst": worst, "status": status, "seconds": round(time.time() - t, 2),
            "launches": st[0], "groups": st[1], "barriers": st[2], "wave_ops": st[3], "mfma": st[4],
            "barrier_site_mismatch": st[5]}
+    log = (C.c_uint64 * (3 * 4096))()
+    nl = lib.emu_launch_log(log, 4096)
+    out["launch_log"] = [[log[3 * i], log[3 * i + 1], log[3 * i + 2]] for i in range(min(nl, 4096))]
     if hasattr(lib, "emu_race_stats"):
         rs = (C.c_uint64 * 3)()
         lib.emu_race_stats(rs)

@@ -129,6 +129,8 @@ Group G;
 uint64_t n_launch = 0, n_groups = 0, n_bar = 0, n_wave = 0, n_mfma = 0;
 uint64_t n_bar_mismatch = 0;
 uint64_t clock_ticks = 0;
+// per launch: workgroups, MFMA instructions (per wave), barriers
+std::vector<uint64_t> launch_log;
 
 [[noreturn]] void fail(const char* fmt, const char* file, int line, const char* extra = "") {
   fprintf(stderr, "EMU ERROR: ");
@@ -473,6 +475,7 @@ void launch(dim3 grid, dim3 block, const std::function<void()>& body) {
   }
   n_launch++;
   g_launch = n_launch;
+  const uint64_t mfma0 = n_mfma, bar0 = n_bar;
 #ifdef EMU_RACE
   emu_race_lds_setup();
 #endif
@@ -512,6 +515,9 @@ void launch(dim3 grid, dim3 block, const std::function<void()>& body) {
     }
   }
   G.cur = -1;
+  launch_log.push_back(grid.x);
+  launch_log.push_back(n_mfma - mfma0);
+  launch_log.push_back(n_bar - bar0);
 }
 
 }  // namespace emu
@@ -524,6 +530,15 @@ void emu_stats(uint64_t* out) {
   out[3] = emu::n_wave;
   out[4] = emu::n_mfma;
   out[5] = emu::n_bar_mismatch;
+}
+
+// per-launch records (workgroups, MFMA instructions of whole waves, barrier
+// arrivals of lanes), oldest first; returns the number of launches
+int emu_launch_log(uint64_t* out, int max) {
+  const int n = (int)(emu::launch_log.size() / 3);
+  for (int i = 0; i < n && i < max; ++i)
+    for (int k = 0; k < 3; ++k) out[3 * i + k] = emu::launch_log[3 * i + k];
+  return n;
 }
 
 static int g_fill = -1;   // byte written into fresh allocations (-1: none)
