@@ -11,7 +11,7 @@ the status words and the run's counters (launches, workgroups, barriers,
 wave-level operations, barrier-site mismatches and, for the race build, the
 numbers of distinct races between waves or workgroups and between lanes of one
 wave), and per launch its workgroups, MFMA instructions (per wave) and barrier
-arrivals.  A sanitizer finding or an emulation error aborts the process before
+arrivals (and, for the race build, the device bytes read and written).  A sanitizer finding or an emulation error aborts the process before
 that line is printed.  For the AddressSanitizer build the caller preloads its
 runtime.
 """
@@ -549,6 +549,10 @@ def main():
     log = (C.c_uint64 * (3 * 4096))()
     nl = lib.emu_launch_log(log, 4096)
     out["launch_log"] = [[log[3 * i], log[3 * i + 1], log[3 * i + 2]] for i in range(min(nl, 4096))]
+    if hasattr(lib, "emu_race_launch_bytes"):
+        b = (C.c_uint64 * (2 * 4096))()
+        nb = lib.emu_race_launch_bytes(b, 4096)
+        out["launch_bytes"] = [[b[2 * i], b[2 * i + 1]] for i in range(min(nb, 4096))]
     if hasattr(lib, "emu_race_stats"):
         rs = (C.c_uint64 * 3)()
         lib.emu_race_stats(rs)

@@ -7,6 +7,7 @@
 //   * two workgroups of one launch touch a granule, at least one writing
 //                                                          -> inter-group race
 //   * a workgroup reads shared memory it has not written    -> undefined read
+// It also adds up the device bytes each launch's loads and stores ask for.
 //   * two lanes of one wave touch a granule between the same pair of
 //     barriers, one of them writing                         -> lane race
 //     (the lanes run in lockstep, but the compiler orders each lane's
@@ -58,6 +59,8 @@ Region lds{0, 0, nullptr, -1};
 Region* last = nullptr;
 int next_id = 0;
 uint64_t n_reports = 0, n_checked = 0, n_lane_reports = 0;
+uint64_t dev_read = 0, dev_write = 0;              // device bytes of the current launch
+std::vector<uint64_t> launch_bytes;                 // per launch: read, written
 std::map<std::pair<void*, void*>, uint64_t> seen;   // (pc, other pc) -> count
 
 Region* find(uintptr_t a) {
@@ -102,6 +105,7 @@ inline void access(uintptr_t a, size_t size, bool write, void* pc) {
   if (!r) return;            // private memory, kernel arguments
   if (r == &lds && !r->sh) return;
   n_checked++;
+  if (r != &lds) (write ? dev_write : dev_read) += size;
   const uint32_t L = (uint32_t)emu::g_launch, g = emu::g_group;
   const uint64_t e = emu::g_epoch;
   const int t = (int)emu::g_cur->tid.x, w = t >> 6;
@@ -191,6 +195,22 @@ void emu_race_lds_setup() {
   lds.sh = (Cell*)calloc((lds.n + 3) / 4 + 1, sizeof(Cell));
 }
 void emu_race_stats(uint64_t* out) { out[0] = n_reports; out[1] = n_checked; out[2] = n_lane_reports; }
+// called by the runtime at the end of every launch
+void emu_race_launch_end() {
+  launch_bytes.push_back(dev_read);
+  launch_bytes.push_back(dev_write);
+  dev_read = dev_write = 0;
+}
+// per launch: device bytes the kernel's loads and stores asked for (before
+// any cache), oldest first; returns the number of launches
+int emu_race_launch_bytes(uint64_t* out, int max) {
+  const int n = (int)(launch_bytes.size() / 2);
+  for (int i = 0; i < n && i < max; ++i) {
+    out[2 * i] = launch_bytes[2 * i];
+    out[2 * i + 1] = launch_bytes[2 * i + 1];
+  }
+  return n;
+}
 
 void __tsan_init() {}
 void __tsan_func_entry(void*) {}

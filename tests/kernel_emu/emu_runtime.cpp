@@ -64,6 +64,7 @@ extern "C" char __stop_emu_lds[] __attribute__((weak));
 #endif
 
 #ifdef EMU_RACE
+extern "C" void emu_race_launch_end();
 extern "C" void emu_race_register(void* p, size_t n);
 extern "C" void emu_race_unregister(void* p);
 extern "C" void emu_race_lds_setup();
@@ -518,6 +519,9 @@ void launch(dim3 grid, dim3 block, const std::function<void()>& body) {
   launch_log.push_back(grid.x);
   launch_log.push_back(n_mfma - mfma0);
   launch_log.push_back(n_bar - bar0);
+#ifdef EMU_RACE
+  emu_race_launch_end();
+#endif
 }
 
 }  // namespace emu
