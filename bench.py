@@ -22,8 +22,10 @@ Printed as one JSON line, with
 and further legs: lowT_L6 (det+G of one N = 72 field, N_t = 256), force
 (N = 128 checkpointed adjoint vs the plain per-slice inversion), batched
 (256 mixed configurations in one launch sequence vs one call per
-configuration), observables, an HMC trajectory, and the intermediate-volume
-variant (matrix-free product-form slices) against the dense slices.
+configuration), observables, an HMC trajectory, the intermediate-volume
+variant (matrix-free product-form slices) against the dense slices, the
+time-displaced G(t, t0) (with the CPU oracle's time per pair), and the force
+sweep with the per-slice trace of a dense operator against the force alone.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -591,6 +593,78 @@ def leg_sparse(args, fd, torch, dev):
     return out
 
 
+def leg_displaced(args, fd, torch, dev):
+    """Time-displaced G(t, t0) (two slice chains per pair and a scale-split
+    close, Sec. 7 steps 7-9) on the lowT_L6 field for the pairs its parity test
+    checks, beside the CPU oracle's split close of one pair.  Model FLOP per
+    pair: the slice chains over all N_t slices with their QRs, one stabilised
+    product and a close with G."""
+    from workload import WORKLOADS
+    w = WORKLOADS["lowT_L6"]
+    K = torch.from_numpy(w.K()).to(dev)
+    ph = torch.from_numpy(w.phi()).to(dev)
+    pairs = [(1, 1), (130, 3), (3, 130), (256, 1), (1, 256), (77, 76)]
+    ws = fd.Workspace()
+    fd.greens_displaced(K, ph, w.dk, pairs, s=w.s, ws=ws)   # checks the status
+    torch.cuda.synchronize()
+    reps = 5
+    a = time.perf_counter()
+    for _ in range(reps):
+        fd.greens_displaced(K, ph, w.dk, pairs, s=w.s, check=False, ws=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - a) / reps
+    flop = len(pairs) * (chain_flops(w.N, w.Nt, w.s) + combine_flops(w.N) + close_flops(w.N))
+    out = {"workload": f"lowT_L6 field (N={w.N}, Nt={w.Nt}, beta={w.beta}, s={w.s}), "
+                       f"{len(pairs)} (t, t0) pairs per call",
+           "ms_per_call": dt * 1e3, "pairs_per_s": len(pairs) / dt,
+           "model_tflop_s": flop / dt / 1e12,
+           "phases_ms": phase_split(lambda: fd.greens_displaced(K, ph, w.dk, pairs, s=w.s,
+                                                                check=False, ws=ws))}
+    log(f"displaced G: {dt * 1e3:.2f} ms per call of {len(pairs)} pairs")
+    if not args.no_cpu:
+        import oracle
+        a = time.perf_counter()
+        oracle.dsplit_displaced_greens(w.K(), w.dk, w.phi(), 130, 3)
+        cpu = time.perf_counter() - a
+        out["cpu_oracle_s_per_pair"] = cpu
+        out["vs_cpu_oracle"] = cpu / (dt / len(pairs))
+    return out
+
+
+def leg_force_response(fd, torch, dev):
+    """The force sweep with the per-slice trace tr((1 - G~_t) A) of a dense
+    complex A (eq. response_simple before its slice average) on the lowT_L6
+    field, against the same force without the trace."""
+    import numpy as np
+    from workload import WORKLOADS
+    w = WORKLOADS["lowT_L6"]
+    K = torch.from_numpy(w.K()).to(dev)
+    ph = torch.from_numpy(w.phi()).to(dev)
+    rng = np.random.default_rng(2700)
+    A = torch.from_numpy(rng.normal(size=(w.N, w.N)) + 1j * rng.normal(size=(w.N, w.N))).to(dev)
+    ws = fd.Workspace()
+    fd.force_response(K, ph, w.dk, A, s=w.s, checkpoint=16, ws=ws)   # checks the status
+    torch.cuda.synchronize()
+    out = {"workload": f"lowT_L6 field (N={w.N}, Nt={w.Nt}, beta={w.beta}, s={w.s}, c=16), "
+                       "dense complex A"}
+    reps = 5
+    for label, call in (
+            ("with_trace", lambda: fd.force_response(K, ph, w.dk, A, s=w.s, checkpoint=16,
+                                                     check=False, ws=ws)),
+            ("force_only", lambda: fd.force(K, ph, w.dk, s=w.s, checkpoint=16, check=False,
+                                            ws=ws))):
+        call()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            call()
+        torch.cuda.synchronize()
+        out[label] = {"ms": (time.perf_counter() - a) / reps * 1e3}
+    out["trace_overhead"] = out["with_trace"]["ms"] / out["force_only"]["ms"]
+    log(f"force with trace {out['with_trace']['ms']:.2f} ms, without {out['force_only']['ms']:.2f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -637,6 +711,14 @@ def main():
         result["observables"] = leg_observables(fd, torch, dev)
         result["hmc_trajectory"] = leg_trajectory(fd, torch, dev)
         result["sparse"] = leg_sparse(args, fd, torch, dev)
+        # an error in one of these legs is reported in its key; the line is printed anyway
+        for key, leg in (("displaced", lambda: leg_displaced(args, fd, torch, dev)),
+                         ("force_response", lambda: leg_force_response(fd, torch, dev))):
+            try:
+                result[key] = leg()
+            except Exception as e:  # noqa: BLE001
+                result[key] = {"error": f"{type(e).__name__}: {e}"}
+                log(f"{key} leg failed: {e}")
     print(json.dumps(result), flush=True)
 
 
