@@ -593,6 +593,41 @@ def leg_sparse(args, fd, torch, dev):
     return out
 
 
+def force_cpu_oracle():
+    """The oracle's force (stabilised prefix and suffix products of single
+    slices, one stabilised inversion per row) on the force_L8 field, timed on
+    a bounded sample of its steps and scaled to one evaluation: 2 N_t slice
+    products and N_t row inversions (as the headline's cpu_baseline does at
+    N = 512)."""
+    import numpy as np
+    from oracle import fdet_oracle as F
+    from workload import WORKLOADS
+    w = WORKLOADS["force_L8"]
+    K, phi = w.K(), w.phi()
+    N, Nt = w.N, w.Nt
+    U, e = F._slice_factors(K, w.dk)
+    slices = [F._slice_udv(U, e, np.exp(1j * phi[t])) for t in range(24)]
+    P = F.udv_product(slices[0], F.udv_identity(N))      # warm-up
+    n_prod = 20
+    a = time.perf_counter()
+    for t in range(1, n_prod + 1):
+        P = F.udv_product(slices[t], P)
+    t_prod = (time.perf_counter() - a) / n_prod
+    S = F.udv_product(F.udv_identity(N), slices[23])
+    F.udv_close(F.udv_product(P, S))                    # warm-up
+    n_close = 8
+    a = time.perf_counter()
+    for _ in range(n_close):
+        F.udv_close(F.udv_product(P, S))
+    t_close = (time.perf_counter() - a) / n_close
+    per_eval = 2 * Nt * t_prod + Nt * t_close
+    return {"force_evals_per_s": 1.0 / per_eval, "s_per_eval": per_eval, "cores": host_threads(),
+            "kind": "oracle",
+            "sample": f"extrapolated from {n_prod} stabilised single-slice products "
+                      f"({t_prod:.4f} s each) and {n_close} row inversions ({t_close:.4f} s each) "
+                      f"at N={N}; one evaluation = 2*{Nt} products + {Nt} inversions"}
+
+
 def leg_displaced(args, fd, torch, dev):
     """Time-displaced G(t, t0) (two slice chains per pair and a scale-split
     close, Sec. 7 steps 7-9) on the lowT_L6 field for the pairs its parity test
@@ -707,6 +742,11 @@ def main():
     if not args.no_extra:
         result["lowT_L6"] = leg_lowT(args, fd, torch, dev)
         result["force"] = leg_force(fd, torch, dev)
+        if not args.no_cpu:
+            try:
+                result["force"]["cpu_oracle"] = force_cpu_oracle()
+            except Exception as e:  # noqa: BLE001
+                result["force"]["cpu_oracle"] = {"error": f"{type(e).__name__}: {e}"}
         result["batched"] = leg_batched(fd, torch, dev)
         result["observables"] = leg_observables(fd, torch, dev)
         result["hmc_trajectory"] = leg_trajectory(fd, torch, dev)
