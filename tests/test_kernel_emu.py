@@ -14,16 +14,17 @@ Two builds of the unmodified sources in paper_2604_02130_amd/csrc:
         in the workgroup.
 Both run every lane as a fiber, so they also catch barriers that some lanes
 never reach and wave-level operations (MFMA, DPP, shuffles) taken by part of a
-wave.  The launch classes built are 32 (register QR, LDS products) and 512
-(blocked QR, MFMA products from device memory), the latter through a batch
-with one N = 130 problem, whose smaller members then run the blocked code too.
+wave.  The launch classes built are 32 and 128 (register QR, LDS products)
+and 512 (blocked QR, MFMA products from device memory).  Class 128 runs a
+mixed batch (N = 18 to 128 in one launch: each item on its own class's code
+and the class-128 shared-memory layout); class 512 runs through batches with
+one N = 130 problem, whose smaller members then run the blocked code too.
 The other entry points run at class 32: prepared plans (launched twice, bit
 for bit the eager calls, also with FD_REUSE_E), FD_KEEP_CHECKPOINTS, fd_udv,
 the slice exponential, the observables, the leapfrog and its prepared
 trajectory, and the allocation-free G (bit for bit fd_greens).
-With FDET_EMU_ALL=1 every class is built, and mixed batches (N = 18 to 128
-in one class-128 launch, each item on its own class's code and the class-128
-shared-memory layout) and a class-80 force run as well (a few minutes more).
+With FDET_EMU_ALL=1 every class is built, and the mixed batch's force and a
+class-80 force run as well (a few minutes more).
 FDET_EMU_FULL=1 adds the named workloads at full size (lowT_L6 det + G with
 32 segments, force_L8) and the HMC step's N = 512 shape (field 0's first 32
 slices, s = c = 16): tens of minutes.
@@ -54,9 +55,10 @@ CASES = ["greens", "force_windows", "force_scans", "response", "displaced", "spa
          "plans", "keep_checkpoints", "udv_exp", "observables", "leapfrog", "noalloc"]
 FULL = os.environ.get("FDET_EMU_FULL") == "1"
 ALL = FULL or os.environ.get("FDET_EMU_ALL") == "1"
-CLASSES = emu_build.ALL_CLASSES if ALL else (32, 512)
+CLASSES = emu_build.ALL_CLASSES if ALL else (32, 128, 512)
+CASES += ["mixed_greens"]
 if ALL:
-    CASES += ["mixed_greens", "mixed_force", "class80_force"]
+    CASES += ["mixed_force", "class80_force"]
 if FULL:
     CASES += ["full_lowT_L6", "full_force_L8", "full_n512_force"]
 MODES = ["asan", "race"]
