@@ -34,6 +34,12 @@
 #endif
 #endif
 
+#if !defined(__x86_64__) || !defined(__linux__)
+#error "the fiber switch below is written for x86-64 Linux (System V calling convention)"
+#endif
+
+// Saves the callee-saved registers and the stack pointer of the running
+// fiber in *save_sp and resumes the fiber whose stack pointer is new_sp.
 extern "C" void emu_swap(void** save_sp, void* new_sp);
 asm(R"(
 .text
